@@ -1,0 +1,456 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the part of the model it pins (arXiv:2512.18863, §2.2) and
+what it is pinned to: a hand-computed example, a closed form, an invariant, a
+library routine or a brute force.  None of them re-types the oracle's own
+formula.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.ndimage
+
+import oracle
+from paper_2512_18863_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _custom_case(n_taps=1, field=(2.0, 0.5), lat=2.0, edges=None, shape=(2, 2, 2), tau=0.0, spacing=2.0):
+    m = inputs.Machine(n_leaf=1, leaf_width=2.0, tau=tau)
+    hu = np.zeros(shape, dtype=np.float32)
+    sp = (spacing,) * 3
+    origin = inputs._centred_origin(shape, sp)
+    c = inputs.Case("custom", hu, sp, origin, (0.0, 0.0, 0.0), np.array([0.0]), np.zeros((1, 2, 1)),
+                    np.zeros((1, 4)), np.array([1.0]), n_taps, field, m, lat_step=lat, depth_step=lat)
+    return c
+
+
+# ----------------------------------------------------------------- §2.2.2 fluence
+
+
+def test_raster_golden_three_pixels():
+    """Eq. 4 with jaw masking and transmission: hand-computed 3-pixel values."""
+    g = json.load(open(os.path.join(GOLDEN, "raster_3px.json")))
+    for cs in g["cases"]:
+        c = _custom_case(tau=cs["tau"])
+        m = oracle.Model(c)
+        assert (m.Nu, m.Nv) == (3, 3)
+        F = oracle.raster(m, np.array([[g["leaf"][0]], [g["leaf"][1]]]), np.array(cs["jaws"]))
+        np.testing.assert_allclose(F[1], cs["F"], rtol=0, atol=1e-15)
+        assert np.all(F[0] == 0.0) and np.all(F[2] == 0.0)
+
+
+def test_raster_partition_of_unity():
+    """Summed over a row, the overlap fractions times the pixel width give the opening
+    r - l exactly (the overlap areas tile the opening); covered pixels are exactly 1
+    and uncovered pixels exactly 0."""
+    rng = np.random.default_rng(11)
+    c = inputs.config_c1(n_cp=1)
+    c.machine.tau = 0.0
+    m = oracle.Model(c)
+    D = c.lat_step
+    u = (np.arange(m.Nu) - (m.Nu - 1) / 2) * D
+    v = (np.arange(m.Nv) - (m.Nv - 1) / 2) * D
+    edges = c.machine.leaf_edges
+    for _ in range(5):
+        lo = rng.uniform(-60, 20, size=60)        # openings stay on the grid (|u| <= 64.5)
+        hi = lo + rng.uniform(0, 40, size=60)
+        F = oracle.raster(m, np.stack([lo, hi]), np.array([-200.0, 200.0, -200.0, 200.0]))
+        for j in range(m.Nv):
+            # rows lying entirely inside one leaf
+            l = np.searchsorted(edges, v[j]) - 1
+            if l < 0 or l >= 60 or v[j] - D / 2 < edges[l] or v[j] + D / 2 > edges[l + 1]:
+                continue
+            assert abs(F[j].sum() * D - (hi[l] - lo[l])) < 1e-12
+            inside = (u - D / 2 >= lo[l]) & (u + D / 2 <= hi[l])
+            outside = (u + D / 2 <= lo[l]) | (u - D / 2 >= hi[l])
+            assert np.all(F[j][inside] == 1.0)
+            assert np.all(F[j][outside] == 0.0)
+
+
+def test_raster_rows_split_across_leaves():
+    """A pixel row straddling two leaves with the same opening sees that opening with
+    weight one (the row coverage fractions of adjacent leaves add up)."""
+    c = _custom_case(field=(6.0, 6.0), lat=2.0)
+    c.machine = inputs.Machine(n_leaf=2, leaf_width=3.0, tau=0.0)   # edges -3, 0, 3
+    m = oracle.Model(c)
+    leaves = np.array([[-1.0, -1.0], [3.0, 3.0]])
+    F = oracle.raster(m, leaves, np.array([-10.0, 10.0, -10.0, 10.0]))
+    v = (np.arange(m.Nv) - (m.Nv - 1) / 2) * 2.0
+    j = int(np.where(v == 0.0)[0][0])           # pixel [-1, 1] straddles the leaf boundary at 0
+    u = (np.arange(m.Nu) - (m.Nu - 1) / 2) * 2.0
+    expect = np.array([max(0.0, min(3.0, x + 1) - max(-1.0, x - 1)) / 2.0 for x in u])
+    np.testing.assert_allclose(F[j], expect, atol=1e-15)
+
+
+# ----------------------------------------------------------------- whole forward
+
+
+@pytest.fixture(scope="module")
+def c0():
+    c = inputs.config_c0()
+    m = oracle.Model(c)
+    return c, m, oracle.density(m)
+
+
+def test_zero_aperture_gives_exact_zero(c0):
+    """Closed jaws or zero MU give exactly zero dose; with tau = 0, closed leaves too."""
+    c, m, rho = c0
+    cj = inputs.config_c0("jaws_closed")
+    assert np.all(oracle.forward(m, rho, cj.gantry, cj.leaves, cj.jaws, cj.mu) == 0.0)
+    assert np.all(oracle.forward(m, rho, c.gantry, c.leaves, c.jaws, np.zeros(1)) == 0.0)
+    cl = inputs.config_c0("leaves_closed")
+    ml = oracle.Model(cl)
+    assert np.all(oracle.forward(ml, rho, cl.gantry, cl.leaves, cl.jaws, cl.mu) == 0.0)
+
+
+def test_dose_linear_in_mu():
+    """Eq. 9: doubling MU doubles the dose bit for bit; the plan dose is the sum of its
+    single-control-point doses."""
+    c = inputs.tiny_case(seed=3, n_cp=3, n_taps=3)
+    m = oracle.Model(c)
+    rho = oracle.density(m)
+    d1 = oracle.forward(m, rho, c.gantry, c.leaves, c.jaws, c.mu)
+    d2 = oracle.forward(m, rho, c.gantry, c.leaves, c.jaws, 2.0 * c.mu)
+    assert np.array_equal(d2, 2.0 * d1)
+    parts = sum(oracle.forward(m, rho, c.gantry[b:b + 1], c.leaves[b:b + 1], c.jaws[b:b + 1], c.mu[b:b + 1])
+                for b in range(c.n_cp))
+    np.testing.assert_allclose(parts, d1, rtol=0, atol=1e-13 * np.abs(d1).max())
+
+
+def test_mirror_symmetry_x(c0):
+    """Water cube, isocentre at the centre, gantry 0: the mirrored aperture (l, r) ->
+    (-r, -l) (with mirrored x jaws) mirrors the dose in x."""
+    c, m, rho = c0
+    d = oracle.forward(m, rho, c.gantry, c.leaves, c.jaws, c.mu)
+    cm = inputs.config_c0("mirror")
+    jm = c.jaws[:, [1, 0, 2, 3]] * np.array([-1, -1, 1, 1])
+    dm = oracle.forward(m, rho, cm.gantry, cm.leaves, jm, cm.mu)
+    np.testing.assert_allclose(dm, d[:, :, ::-1], rtol=0, atol=1e-12 * d.max())
+
+
+def test_mirror_symmetry_z(c0):
+    """Reversing the leaf order (and mirroring the y jaws) mirrors the dose in z."""
+    c, m, rho = c0
+    d = oracle.forward(m, rho, c.gantry, c.leaves, c.jaws, c.mu)
+    lr = c.leaves[:, :, ::-1].copy()
+    jm = c.jaws[:, [0, 1, 3, 2]] * np.array([1, 1, -1, -1])
+    dz = oracle.forward(m, rho, c.gantry, lr, jm, c.mu)
+    np.testing.assert_allclose(dz, d[::-1], rtol=0, atol=1e-12 * d.max())
+
+
+def test_gantry_rotation_consistency(c0):
+    """On the water cube, gantry 90 gives the gantry-0 dose rotated by 90 degrees about z:
+    a point (x, y) irradiated at gantry 0 corresponds to (-y, x) at gantry 90."""
+    c, m, rho = c0
+    d0 = oracle.forward(m, rho, np.array([0.0]), c.leaves, c.jaws, c.mu)
+    d90 = oracle.forward(m, rho, np.array([90.0]), c.leaves, c.jaws, c.mu)
+    N = d0.shape[1]
+    # D90[z, j', i'] = D0[z, j, i] with x = y', y = -x'  ->  i = j', j = N-1-i'
+    jj, ii = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    rot = d0[:, N - 1 - ii, jj]
+    np.testing.assert_allclose(d90, rot, rtol=0, atol=1e-12 * d0.max())
+    d180 = oracle.forward(m, rho, np.array([180.0]), c.leaves, c.jaws, c.mu)
+    np.testing.assert_allclose(d180, d0[:, ::-1, ::-1], rtol=0, atol=1e-12 * d0.max())
+
+
+# ----------------------------------------------------------------- §2.2.4 depth
+
+
+def _hat(X, n):
+    """Trilinear interpolation of a zero-padded run of ones of length n at index X."""
+    X = np.asarray(X, dtype=np.float64)
+    return np.clip(np.minimum(X + 1.0, n - X), 0.0, 1.0)
+
+
+@pytest.mark.parametrize("gantry", [0.0, 33.0, 90.0, 217.5])
+def test_wepl_water_closed_form(gantry):
+    """In a uniform water cube the interpolated density at index (X, Y, Z) is the
+    product of three clamped hat functions; W along a ray is then the sum of those
+    products times the sec-scaled step."""
+    c = inputs.config_c0()
+    c.iso = (3.0, -4.0, 2.0)
+    m = oracle.Model(c)
+    rho = oracle.density(m)
+    W = oracle.wepl(m, rho, gantry)
+    N, s = 32, 5.0
+    a = math.radians(gantry)
+    sn, cs = math.sin(a), math.cos(a)
+    sad = c.machine.sad
+    src = np.array([c.iso[0] + sad * sn, c.iso[1] - sad * cs, c.iso[2]])
+    for (j, i) in [(13, 13), (0, 0), (5, 20), (26, 3), (13, 2)]:
+        u = (i - (m.Nu - 1) / 2) * c.lat_step
+        v = (j - (m.Nv - 1) / 2) * c.lat_step
+        target = np.array(c.iso) + u * np.array([cs, sn, 0.0]) + v * np.array([0.0, 0.0, 1.0])
+        direction = (target - src) / sad                     # per unit of distance along the axis
+        ks = np.arange(m.Nk)
+        d = m.d0 + ks * c.depth_step
+        pts = src[None, :] + d[:, None] * direction[None, :]
+        idx = (pts - np.array(c.origin)) / s
+        rho_s = _hat(idx[:, 0], N) * _hat(idx[:, 1], N) * _hat(idx[:, 2], N)
+        step = np.linalg.norm(direction) * c.depth_step
+        np.testing.assert_allclose(W[:, j, i], np.cumsum(rho_s) * step, rtol=1e-12, atol=1e-10)
+
+
+def test_central_axis_mode_and_centre_ray():
+    """Central-axis mode gives every ray the single-ray profile (§2.2.4); per-ray mode
+    gives the central ray that same profile."""
+    c = inputs.tiny_case(seed=5)
+    m = oracle.Model(c)
+    rho = oracle.density(m)
+    z = oracle.ca_depth(m, rho, c.gantry[0])
+    W = oracle.wepl(m, rho, c.gantry[0])
+    np.testing.assert_allclose(W[:, (m.Nv - 1) // 2, (m.Nu - 1) // 2], z, rtol=1e-13, atol=1e-12)
+    mc = oracle.Model(c, wepl_mode=oracle.WEPL_CENTRAL_AXIS)
+    Wc = oracle.wepl(mc, rho, c.gantry[0])
+    assert np.array_equal(Wc, np.broadcast_to(z[:, None, None], Wc.shape))
+
+
+def test_density_matches_numpy_interp():
+    """HU -> density is a clamped piecewise-linear calibration curve (§2.2)."""
+    rng = np.random.default_rng(1)
+    hu = rng.uniform(-1500, 3000, size=1000)
+    hp = np.array([-1000.0, -200.0, 0.0, 1500.0])
+    rp = np.array([0.0, 0.8, 1.0, 1.85])
+    np.testing.assert_allclose(oracle.hu_to_density(hu, hp, rp), np.interp(hu, hp, rp), rtol=0, atol=1e-14)
+
+
+# ----------------------------------------------------------------- §2.2.5 kernel
+
+
+def _square_integral(A, a, B, b, half):
+    """Integral of the unit-normalised kernel over the square [-half, half]^2, from the
+    radial closed form: 1 minus the mass outside the square."""
+    norm = A / a + B / b
+
+    def radial(r):             # p(r) 2 pi r
+        return (A * math.exp(-a * r) + B * math.exp(-b * r)) / norm
+    outside_corner, _ = scipy.integrate.quad(lambda r: radial(r) * (4 / math.pi) * math.acos(half / r),
+                                             half, half * math.sqrt(2), epsabs=1e-14, epsrel=1e-12)
+    rc = half * math.sqrt(2)
+    tail = (A / a * math.exp(-a * rc) + B / b * math.exp(-b * rc)) / norm
+    return 1.0 - outside_corner - tail
+
+
+@pytest.mark.parametrize("z", [0.0, 150.0, 400.0])
+def test_kernel_mass_converges_to_square_integral(z):
+    """As the tap spacing shrinks, the taps' sum converges (first order) to the
+    integral of the unit-mass kernel over the square they cover."""
+    errs = []
+    for lat in (0.4, 0.2, 0.1):
+        c = _custom_case(n_taps=2 * int(round(20.0 / lat)) + 1, lat=lat)
+        m = oracle.Model(c)
+        K = oracle.taps(m, c.machine.sad, z)
+        kp = c.machine.kpoly
+        A, a, B, b = (kp[r][0] + kp[r][1] * z for r in range(4))
+        half = (K.shape[0] / 2.0) * lat
+        errs.append(abs(K.sum() - _square_integral(A, a, B, b, half)))
+    assert errs[0] < 0.02
+    assert errs[1] < 0.6 * errs[0] and errs[2] < 0.6 * errs[1]
+
+
+def test_kernel_spacing_scales_with_plane_distance():
+    """Taps sit at the fan-plane spacing Delta d / SAD: halving Delta and doubling d
+    leaves the taps unchanged."""
+    c1 = _custom_case(n_taps=9, lat=2.0)
+    c2 = _custom_case(n_taps=9, lat=1.0)
+    K1 = oracle.taps(oracle.Model(c1), 1000.0, 50.0)
+    K2 = oracle.taps(oracle.Model(c2), 2000.0, 50.0)
+    np.testing.assert_allclose(K1, K2, rtol=1e-14)
+
+
+def test_kernel_radial_symmetry_and_depth_clamp():
+    c = _custom_case(n_taps=11, lat=3.0)
+    m = oracle.Model(c)
+    K = oracle.taps(m, 1100.0, 120.0)
+    np.testing.assert_array_equal(K, K.T)
+    np.testing.assert_array_equal(K, K[::-1, :])
+    np.testing.assert_array_equal(oracle.taps(m, 1000.0, -5.0), oracle.taps(m, 1000.0, 0.0))
+    np.testing.assert_array_equal(oracle.taps(m, 1000.0, 900.0), oracle.taps(m, 1000.0, 700.0))
+
+
+# ----------------------------------------------------------------- §2.2.6 convolution
+
+
+def test_conv_plane_matches_scipy_correlate():
+    """Per-plane zero-padded convolution equals scipy's correlate (mode constant); an
+    asymmetric kernel pins the orientation."""
+    rng = np.random.default_rng(2)
+    for (nv, nu, n) in [(9, 13, 5), (20, 17, 7), (6, 6, 9)]:
+        K = rng.normal(size=(n, n))
+        P = rng.normal(size=(nv, nu))
+        out = oracle.conv_plane(K, P)
+        ref = scipy.ndimage.correlate(P, K, mode="constant", cval=0.0)
+        np.testing.assert_allclose(out, ref, rtol=0, atol=1e-12)
+
+
+def test_conv_delta_reproduces_kernel():
+    c = _custom_case(n_taps=7, lat=3.0)
+    K = oracle.taps(oracle.Model(c), 1000.0, 30.0)
+    P = np.zeros((15, 15))
+    P[7, 7] = 1.0
+    out = oracle.conv_plane(K, P)
+    np.testing.assert_allclose(out[4:11, 4:11], K[::-1, ::-1], rtol=0, atol=0)
+
+
+# ----------------------------------------------------------------- §2.2.7 rotation / sum
+
+
+@pytest.mark.parametrize("gantry", [0.0, 90.0, 47.0, 301.0])
+def test_gather_inverts_fan_geometry(gantry):
+    """Trilinear interpolation reproduces multilinear functions exactly.  Each patient
+    coordinate of a fan node, s + d_k (b + (u_i e_u + v_j e_v)/SAD), is multilinear in
+    (k, j, i); gathering those coordinates must return the voxel centres themselves,
+    which pins the back-projection as the inverse of the fan-node placement."""
+    c = inputs.tiny_case(seed=9, shape=(7, 8, 9), spacing=8.0, field=60.0)
+    m = oracle.Model(c)
+    a = math.radians(gantry)
+    sn, cs = math.sin(a), math.cos(a)
+    sad = c.machine.sad
+    k = np.arange(m.Nk)[:, None, None]
+    j = np.arange(m.Nv)[None, :, None]
+    i = np.arange(m.Nu)[None, None, :]
+    d = m.d0 + k * c.depth_step
+    u = (i - (m.Nu - 1) / 2) * c.lat_step
+    v = (j - (m.Nv - 1) / 2) * c.lat_step
+    src = (c.iso[0] + sad * sn, c.iso[1] - sad * cs, c.iso[2])
+    node = [src[0] + d * (-sn + u * cs / sad) + 0 * v,
+            src[1] + d * (cs + u * sn / sad) + 0 * v,
+            src[2] + d * (v / sad) + 0 * u]
+    xs, ys, zs = inputs.voxel_centres(c.shape, c.spacing, c.origin)
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    ones = oracle.gather(m, gantry, np.ones(m.fan_shape))
+    inside = ones > 1 - 1e-12          # all eight corners on the grid
+    assert inside.sum() > 0.5 * inside.size
+    for comp, truth in zip(node, (X, Y, Z)):
+        got = oracle.gather(m, gantry, np.ascontiguousarray(comp))
+        np.testing.assert_allclose(got[inside], truth[inside], rtol=0, atol=1e-9)
+
+
+def test_gather_matches_map_coordinates():
+    """The interpolation itself equals scipy's order-1 map_coordinates with zero padding
+    (mode grid-constant), at the fan indices of each voxel."""
+    c = inputs.tiny_case(seed=4, shape=(5, 6, 7), spacing=9.0, field=40.0)
+    m = oracle.Model(c)
+    rng = np.random.default_rng(0)
+    Dfan = rng.uniform(size=m.fan_shape)
+    g = 30.0
+    got = oracle.gather(m, g, Dfan)
+    a = math.radians(g)
+    sn, cs = math.sin(a), math.cos(a)
+    xs, ys, zs = inputs.voxel_centres(c.shape, c.spacing, c.origin)
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    tx, ty, tz = X - c.iso[0], Y - c.iso[1], Z - c.iso[2]
+    sad = c.machine.sad
+    dd = -sn * tx + cs * ty + sad
+    coords = np.stack([(dd - m.d0) / c.depth_step,
+                       sad * tz / dd / c.lat_step + (m.Nv - 1) / 2,
+                       sad * (cs * tx + sn * ty) / dd / c.lat_step + (m.Nu - 1) / 2])
+    ref = scipy.ndimage.map_coordinates(Dfan, coords.reshape(3, -1), order=1, mode="grid-constant",
+                                        cval=0.0).reshape(got.shape)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------- adjoint
+
+
+def test_gather_scatter_dot_product():
+    c = inputs.tiny_case(seed=8, shape=(6, 7, 5))
+    m = oracle.Model(c)
+    rng = np.random.default_rng(3)
+    Dfan = rng.normal(size=m.fan_shape)
+    g = rng.normal(size=m.vol_shape)
+    for gantry in (0.0, 123.0):
+        lhs = np.vdot(oracle.gather(m, gantry, Dfan), g)
+        rhs = np.vdot(Dfan, oracle.scatter(m, gantry, g))
+        assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
+def test_mu_gradient_identity():
+    """D is linear in each MU_b, so MU_b dL/dMU_b = <g, calib MU_b D_b>."""
+    c = inputs.tiny_case(seed=12, n_cp=3)
+    m = oracle.Model(c)
+    rho = oracle.density(m)
+    g = np.random.default_rng(4).normal(size=m.vol_shape)
+    _, _, gmu = oracle.backward(m, rho, c.gantry, c.leaves, c.jaws, c.mu, g)
+    for b in range(c.n_cp):
+        Db = oracle.forward(m, rho, c.gantry[b:b + 1], c.leaves[b:b + 1], c.jaws[b:b + 1], c.mu[b:b + 1])
+        assert abs(c.mu[b] * gmu[b] - np.vdot(g, Db)) < 1e-11 * max(1.0, abs(np.vdot(g, Db)))
+
+
+def _kink_distance(x, D, edges_u):
+    """Distance from an edge position to the nearest pixel boundary."""
+    return np.min(np.abs(x - edges_u))
+
+
+def test_leaf_jaw_gradients_match_central_differences():
+    """The dose is piecewise linear in each leaf and jaw position (Eq. 4 is), so a central
+    difference with a step smaller than the distance to the nearest pixel edge is exact
+    up to rounding."""
+    c = inputs.tiny_case(seed=21, n_cp=2, n_taps=3, shape=(6, 7, 6), field=30.0)
+    m = oracle.Model(c)
+    rho = oracle.density(m)
+    w = np.random.default_rng(5).uniform(size=m.vol_shape)
+    gl, gj, gm = oracle.backward(m, rho, c.gantry, c.leaves, c.jaws, c.mu, w)
+    D = c.lat_step
+    boundaries = (np.arange(m.Nu + 1) - m.Nu / 2) * D
+    h = 1e-3
+
+    def loss(lv, jw, mu):
+        return np.vdot(w, oracle.forward(m, rho, c.gantry, lv, jw, mu))
+    checked = 0
+    for b in range(c.n_cp):
+        for side in (0, 1):
+            for l in range(c.machine.n_leaf):
+                x = c.leaves[b, side, l]
+                if _kink_distance(x, D, boundaries) < 10 * h:
+                    continue
+                lp, lm = c.leaves.copy(), c.leaves.copy()
+                lp[b, side, l] += h
+                lm[b, side, l] -= h
+                fd = (loss(lp, c.jaws, c.mu) - loss(lm, c.jaws, c.mu)) / (2 * h)
+                assert abs(fd - gl[b, side, l]) < 1e-7 * max(1.0, abs(fd)), (b, side, l, fd, gl[b, side, l])
+                checked += 1
+        for q in range(4):
+            x = c.jaws[b, q]
+            if _kink_distance(x, D, boundaries) < 10 * h:
+                continue
+            jp, jm = c.jaws.copy(), c.jaws.copy()
+            jp[b, q] += h
+            jm[b, q] -= h
+            fd = (loss(c.leaves, jp, c.mu) - loss(c.leaves, jm, c.mu)) / (2 * h)
+            assert abs(fd - gj[b, q]) < 1e-7 * max(1.0, abs(fd)), (b, q, fd, gj[b, q])
+            checked += 1
+    assert checked >= 10
+    assert np.any(np.abs(gl) > 0)
+
+
+# ----------------------------------------------------------------- §2.2.1 projection
+
+
+def test_projection_feasible_idempotent_identity():
+    rng = np.random.default_rng(6)
+    lv = rng.uniform(-80, 80, size=(4, 2, 10))
+    jw = rng.uniform(-80, 80, size=(4, 4))
+    mu = rng.uniform(-2, 3, size=4)
+    args = (50.0, 45.0, 40.0, 1.0, 0.22)
+    p1 = oracle.project(lv, jw, mu, *args)
+    p2 = oracle.project(*p1, *args)
+    for a, b in zip(p1, p2):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-12)
+    l1, j1, m1 = p1
+    assert np.all(l1[:, 1] - l1[:, 0] >= 1.0 - 1e-12)
+    assert np.all(np.abs(0.5 * (l1[:, 0] + l1[:, 1])) <= 50.0 + 1e-12)
+    assert np.all(np.abs(0.5 * (j1[:, 0] + j1[:, 1])) <= 45.0 + 1e-12)
+    assert np.all(np.abs(0.5 * (j1[:, 2] + j1[:, 3])) <= 40.0 + 1e-12)
+    assert np.all(m1 >= 0.22)
+    feas_l = np.stack([np.full((4, 10), -3.0), np.full((4, 10), 7.0)], axis=1)
+    feas_j = np.tile(np.array([-20.0, 20.0, -10.0, 10.0]), (4, 1))
+    out = oracle.project(feas_l, feas_j, np.full(4, 2.0), *args)
+    np.testing.assert_array_equal(out[0], feas_l)
+    np.testing.assert_array_equal(out[1], feas_j)
