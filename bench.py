@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the dose path: forward + backward control points per second.
+
+Workload (the 128^3 benchmark plan): a randomised synthetic pelvis CT of 128^3
+voxels at 3 mm, a two-arc VMAT plan of 180 control points, 60 leaf pairs of
+5 mm, jaws +-40 mm, 61 x 61 lateral kernel; one step = the dose forward plus the
+backward of L = sum w D to leaves, jaws and MU (all 180 control points).
+Inputs are resident in HBM before the timed region.  The plain FP32 path gives
+`value`; the BF16 convolution variant is timed the same way and its dose is
+compared with the FP32 dose (max error, 1 %/1 mm gamma).  Per-kernel times come
+from HIP events recorded by the library around every launch in the timed
+region.  The FP64 CPU oracle is timed on a bounded sample of the same plan.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2512_18863_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2512_18863_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = rec.get(workload, {}).get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def run_gpu(case, conv, steps, warmup, w):
+    import torch
+    from paper_2512_18863_amd import engine as E
+    eng = E.DoseEngine(case, conv=conv)
+    dev = eng.device
+    lv = torch.tensor(case.leaves, dtype=torch.float32, device=dev)
+    jw = torch.tensor(case.jaws, dtype=torch.float32, device=dev)
+    mu = torch.tensor(case.mu, dtype=torch.float32, device=dev)
+    g = torch.tensor(w, dtype=torch.float32, device=dev)
+    dose = torch.empty(eng.vol_shape, dtype=torch.float32, device=dev)
+
+    def step():
+        eng.forward(lv, jw, mu, out=dose)
+        return eng.backward(lv, jw, mu, g)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    E.profile_begin(64 * steps + 64)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    kernels = E.profile_end()
+    ms = t0.elapsed_time(t1) / steps
+    fwd_dose = eng.forward(lv, jw, mu).cpu().numpy()
+    torch.cuda.synchronize()
+    return ms, kernels, fwd_dose, eng
+
+
+def cpu_baseline(case, w, budget_s=12.0, max_cp=24):
+    """The FP64 oracle, as it stands, on a sample of the plan's control points."""
+    import numpy as np
+    import oracle
+    m = oracle.Model(case)
+    rho = oracle.density(m)
+    order = np.random.default_rng(0).permutation(case.n_cp)
+    t0 = time.perf_counter()
+    done = 0
+    for b in order[:max_cp]:
+        sl = slice(b, b + 1)
+        oracle.forward(m, rho, case.gantry[sl], case.leaves[sl], case.jaws[sl], case.mu[sl])
+        oracle.backward(m, rho, case.gantry[sl], case.leaves[sl], case.jaws[sl], case.mu[sl], w)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": round(done / dt, 4), "unit": "control points/s (fwd+bwd)", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d of the %d control points of the same plan, forward + backward, one at a time, "
+                      "%.1f s" % (done, case.n_cp, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the dose path is built and timed on a single MI355X; "
+              "multi-GPU control-point sharding is a design note only (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2512_18863_amd import gamma, inputs
+
+    case = inputs.config_c4_plan(2000, bench=True)
+    w = np.random.default_rng(4001).uniform(0.0, 1.0, size=case.shape)
+    n_cp = case.n_cp
+    print("[bench] fp32 fwd+bwd, %d CPs, 128^3, n=61: warmup %d, steps %d" % (n_cp, args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    ms, kernels, d32, eng = run_gpu(case, "fp32", args.steps, args.warmup, w)
+    nodes = n_cp * eng.Nk * eng.Nu * eng.Nv
+    n = eng.spec.n_taps
+    conv_name = "conv_mfma_f32"
+    launches, total_ms = kernels.get(conv_name, (0, 0.0))
+    avg_s = total_ms / max(launches, 1) / 1e3
+    flops = 2.0 * n * n * nodes
+    achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
+    traffic = measured_traffic(conv_name, "c4bench_fp32")
+    out = {
+        "metric": "fwd+bwd control points/s at 128^3",
+        "value": round(n_cp / (ms / 1e3), 3),
+        "unit": "control points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "128^3 pelvis at 3 mm, two arcs of 180 control points, 60 leaf pairs, "
+                               "jaws +-40 mm, 61x61 kernel, per-ray depth, FP32 convolution",
+                   "grid": [128, 128, 128], "n_cp": n_cp, "n_taps": n,
+                   "beam_frame_grid": [eng.Nu, eng.Nv, eng.Nk]},
+        "roofline": {"kernel": conv_name, "bound": "mfma", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+                     "traffic": traffic,
+                     "flops_per_launch": flops, "avg_launch_ms": round(avg_s * 1e3, 4),
+                     "launches": launches},
+        "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(kernels.items())},
+        "paper_context": {"value": 35.3, "unit": "control points/s (fwd+bwd)", "hardware": "NVIDIA A40",
+                          "workload": "105x224x224 grid, 180 control points, kernel 55 (Table 6: 5.102 s)"},
+    }
+    del eng
+    torch.cuda.empty_cache()
+    if not args.no_bf16:
+        print("[bench] bf16 variant", file=sys.stderr, flush=True)
+        ms16, k16, d16, eng16 = run_gpu(case, "bf16", args.steps, args.warmup, w)
+        l16, t16 = k16.get("conv_mfma_bf16", (0, 0.0))
+        a16 = flops / (t16 / max(l16, 1) / 1e3) / 1e12 if t16 > 0 else 0.0
+        err = float(np.abs(d16.astype(np.float64) - d32).max() / np.abs(d32).max())
+        print("[bench] gamma 1%/1mm bf16 vs fp32", file=sys.stderr, flush=True)
+        gp = gamma.pass_rate(d32, d16, case.spacing, 1.0, 1.0)
+        out["variants"] = {"bf16": {
+            "value": round(n_cp / (ms16 / 1e3), 3), "ms_per_step": round(ms16, 4),
+            "max_abs_err_vs_fp32_over_max": err, "gamma_1pct_1mm_vs_fp32": round(gp, 6),
+            "roofline": {"kernel": "conv_mfma_bf16", "bound": "mfma", "achieved": round(a16, 3),
+                         "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(a16 / PEAK_BF16_MFMA_TFLOPS, 4)},
+            "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(k16.items())}}}
+        del eng16
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(case, w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

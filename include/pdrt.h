@@ -1,0 +1,206 @@
+/*
+ * pdrt.h — C ABI of the MI355X (gfx950) differentiable pencil-beam VMAT dose
+ * engine, after arXiv:2512.18863 §2.2 ("A physics-informed, plug-and-play dose
+ * engine for gradient-based radiotherapy treatment planning").
+ *
+ * The engine maps per-control-point delivery parameters (MLC leaf positions,
+ * jaw positions, monitor units) to a 3-D dose grid for a fixed CT and beam
+ * geometry (§2.1-2.2), and returns the gradient of a scalar loss with respect
+ * to those parameters only (§2.1: density, depth and kernels sit outside the
+ * gradient graph).
+ *
+ * Conventions shared by every entry point
+ *  - Units: lengths in mm, angles in degrees.  Patient frame LPS, head-first
+ *    supine: gantry angle phi puts the source at iso + SAD (sin phi, -cos phi, 0);
+ *    the leaves travel along e_u = (cos phi, sin phi, 0) and are stacked along z.
+ *  - Arrays are row-major, last index fastest.  Volumes on the CT grid are
+ *    [nz][ny][nx]; leaves [n_cp][2][L] (bank A = left edges, bank B = right
+ *    edges); jaws [n_cp][4] = (x1, x2, y1, y2), x along e_u, y along z;
+ *    mu [n_cp].
+ *  - Pointers marked "device" must point to memory of the current HIP device;
+ *    "host" pointers are read during the call only.  The caller allocates and
+ *    owns every buffer, including the workspace; the library keeps no state
+ *    between calls and never allocates or synchronises.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls only
+ *    enqueue work on it and return; results are valid once the stream reaches
+ *    that point.
+ *  - Return value: PDRT_OK (0) or a negative PDRT_E_* code.  All arguments are
+ *    validated on the host before anything is enqueued, so an invalid call
+ *    enqueues nothing.  PDRT_E_HIP means a launch failed; the stream's state is
+ *    then unspecified.
+ *  - Outputs are overwritten, never accumulated.  NaN and Inf propagate.
+ *  - Calls that share a workspace on different streams race.
+ */
+#ifndef PDRT_H
+#define PDRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PDRT_OK 0
+#define PDRT_E_INVALID (-1)     /* NULL pointer, non-positive size, even kernel size, ... */
+#define PDRT_E_WORKSPACE (-2)   /* workspace NULL or smaller than pdrt_workspace_bytes() */
+#define PDRT_E_HIP (-3)         /* a HIP launch or API call failed */
+#define PDRT_E_UNSUPPORTED (-4) /* valid request the library does not implement */
+
+#define PDRT_WEPL_PER_RAY 0      /* water-equivalent depth along every divergent ray */
+#define PDRT_WEPL_CENTRAL_AXIS 1 /* every ray takes the central-axis depth profile (§2.2.4) */
+
+#define PDRT_CONV_FP32 0 /* lateral convolution in FP32 */
+#define PDRT_CONV_BF16 1 /* lateral convolution with BF16 operands, FP32 accumulation */
+
+#define PDRT_MAX_LEAF_PAIRS 160
+#define PDRT_MAX_TAPS 127
+
+/* CT grid.  Voxel (i, j, k) has its centre at (ox + i sx, oy + j sy, oz + k sz). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double sx, sy, sz;
+  double ox, oy, oz;
+} pdrt_grid;
+
+/* Beam geometry shared by all control points (§2.2, beam parameter vector; the
+ * collimator angle is fixed at 0). */
+typedef struct {
+  double sad_mm;               /* source-to-isocentre distance */
+  double iso_mm[3];            /* isocentre in the patient frame */
+  int32_t n_leaf_pairs;        /* L, 1..PDRT_MAX_LEAF_PAIRS */
+  const double* leaf_edges_mm; /* host [L+1], ascending leaf boundaries along z at the isocentre plane */
+  int32_t n_cp;                /* number of control points, >= 1 */
+  const void* gantry_deg;      /* device [n_cp]: float for the FP32 entry points, double for _f64 */
+  double field_limit_mm[2];    /* largest |jaw| along e_u and z; fixes the beam-frame grid extent */
+} pdrt_beam;
+
+/* Dose model: kernel size, depth mode, convolution precision and machine tables. */
+typedef struct {
+  int32_t n_taps;          /* odd lateral kernel size n, 1..PDRT_MAX_TAPS */
+  int32_t wepl_mode;       /* PDRT_WEPL_* */
+  int32_t conv_mode;       /* PDRT_CONV_*; the _f64 entry points accept PDRT_CONV_FP32 only */
+  double lateral_step_mm;  /* ray spacing Delta at the isocentre plane (the fluence pixel size) */
+  double depth_step_mm;    /* plane spacing Delta_d along the central axis */
+  double transmission;     /* MLC transmission tau (§2.2.2) */
+  double calib;            /* dose per MU */
+  int32_t n_dd;            /* depth-dose table length, >= 2 */
+  double dd_step_mm;       /* depth-dose table spacing in water-equivalent depth */
+  const void* dd;          /* device [n_dd]: DD(m dd_step), float (FP32 entry points) or double (_f64) */
+  double kpoly[4][4];      /* kernel parameters A, a, B, b as cubics in depth z: c0 + c1 z + c2 z^2 + c3 z^3 */
+  double kz_max_mm;        /* depths are clamped to [0, kz_max] before the polynomials */
+  int32_t max_cp_batch;    /* control points per internal batch; 0 = the whole plan */
+} pdrt_kernel_spec;
+
+/* Beam-frame grid of a problem (§2.2.3): Nu x Nv rays, Nk planes, first plane at
+ * distance d0 from the source.  dims = {Nu, Nv, Nk}.  Internal fan-grid arrays are
+ * laid out [cp][Nk][Nu][Nv] (v fastest). */
+int pdrt_fan_dims(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spec* spec,
+                  int32_t dims[3], double* d0_mm);
+
+/* Bytes of device workspace that pdrt_dose_forward / pdrt_dose_backward need
+ * (with_backward != 0 sizes for both).  elem_bytes is 4 for the FP32 entry points,
+ * 8 for _f64.  Returns 0 for an invalid problem. */
+size_t pdrt_workspace_bytes(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spec* spec,
+                            int32_t with_backward, int32_t elem_bytes);
+
+/* Byte offsets of the intermediates inside the workspace after a forward call
+ * (debugging and tests): frame, rho_t ([ny][nx][nz]), F ([B][Nu][Nv]), z ([B][Nk]),
+ * P and Dfan ([B][Nk][Nu][Nv]), A ([B][Nu][Nv]), comp; B = control points per batch;
+ * the arrays hold the last batch. */
+typedef struct {
+  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, total;
+  int32_t batch;
+} pdrt_ws_layout;
+int pdrt_workspace_layout(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spec* spec,
+                          int32_t with_backward, int32_t elem_bytes, pdrt_ws_layout* out);
+
+/* HU -> relative electron density (§2.2, CT representation): piecewise linear
+ * through (hu_pts[i], rho_pts[i]), clamped outside.  hu, rho: device [nz][ny][nx]
+ * float (may alias).  hu_pts, rho_pts: host [n_pts], hu_pts ascending, 2..16 points. */
+int pdrt_hu_to_density(const pdrt_grid* grid, const float* hu, float* rho, int32_t n_pts,
+                       const double* hu_pts, const double* rho_pts, void* stream);
+
+/* Forward dose (§2.2.2-2.2.7): for every control point the fluence map of the
+ * aperture (Eq. 4, jaw masks, transmission), the water-equivalent depth by ray
+ * marching through rho (Eq. 7), the primary with inverse square (Eq. 6) and depth
+ * dose, the per-plane lateral convolution with the depth-dependent kernel (Eq. 8),
+ * then trilinear back-projection to the CT grid and dose = calib sum_b MU_b D_b
+ * (Eq. 9, compensated summation).
+ *   rho    device [nz][ny][nx] relative density
+ *   leaves device [n_cp][2][L], jaws device [n_cp][4], mu device [n_cp]
+ *   dose   device [nz][ny][nx], overwritten
+ *   ws     device workspace of ws_bytes >= pdrt_workspace_bytes(..., 0, 4) */
+int pdrt_dose_forward(const pdrt_grid* grid, const float* rho, const pdrt_beam* beam, const float* leaves,
+                      const float* jaws, const float* mu, const pdrt_kernel_spec* spec, float* dose, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Reverse mode of pdrt_dose_forward: given grad_dose = dL/d dose (device
+ * [nz][ny][nx]) writes dL/d leaves [n_cp][2][L], dL/d jaws [n_cp][4] and dL/d mu
+ * [n_cp] (device, overwritten).  Beam-frame volumes are recomputed per control
+ * point, nothing is kept from the forward call.  The fluence map is piecewise
+ * linear; at its kinks the one-sided derivative with strict inequalities is used
+ * (a leaf exactly on a pixel boundary contributes zero there).  Uses float atomics
+ * in the back-projection adjoint, so results may differ in the last bits between
+ * runs.  ws_bytes >= pdrt_workspace_bytes(..., 1, 4). */
+int pdrt_dose_backward(const pdrt_grid* grid, const float* rho, const pdrt_beam* beam, const float* leaves,
+                       const float* jaws, const float* mu, const pdrt_kernel_spec* spec, const float* grad_dose,
+                       float* grad_leaves, float* grad_jaws, float* grad_mu, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* The forward in double precision throughout (for finite-difference checks):
+ * every array argument is double, beam->gantry_deg and spec->dd point to
+ * doubles, spec->conv_mode must be PDRT_CONV_FP32.
+ * ws_bytes >= pdrt_workspace_bytes(..., 0, 8). */
+int pdrt_dose_forward_f64(const pdrt_grid* grid, const double* rho, const pdrt_beam* beam,
+                          const double* leaves, const double* jaws, const double* mu,
+                          const pdrt_kernel_spec* spec, double* dose, void* ws, size_t ws_bytes, void* stream);
+
+/* Hardware-constrained projection (§2.2.1, Eqs. 1-3): every opposing pair
+ * (leaf pair, x jaws, y jaws) goes to centre-width form, the width is raised to
+ * w_min and the centre clamped to [-limit, limit]; MU is raised to mu_min.
+ * In/out arrays as in pdrt_dose_forward (device, float); outputs may alias inputs. */
+typedef struct {
+  double leaf_limit_mm, jaw_limit_x_mm, jaw_limit_y_mm, w_min_mm, mu_min;
+} pdrt_limits;
+int pdrt_project_params(int32_t n_cp, int32_t n_leaf_pairs, const float* leaves_in, const float* jaws_in,
+                        const float* mu_in, const pdrt_limits* limits, float* leaves_out, float* jaws_out,
+                        float* mu_out, void* stream);
+
+/* Backward of the projection.  straight_through != 0 passes the gradient
+ * unchanged (the default: a clamped closed aperture could otherwise never
+ * reopen); straight_through == 0 applies the projection's own Jacobian.
+ * Inputs are the unprojected parameters and the gradients w.r.t. the projected
+ * ones; outputs (may alias the gradients) are the gradients w.r.t. the inputs. */
+int pdrt_project_params_backward(int32_t n_cp, int32_t n_leaf_pairs, const float* leaves_in,
+                                 const float* jaws_in, const float* mu_in, const pdrt_limits* limits,
+                                 int32_t straight_through, const float* g_leaves, const float* g_jaws,
+                                 const float* g_mu, float* gi_leaves, float* gi_jaws, float* gi_mu, void* stream);
+
+/* Per-launch timing, a profiling aid.  Between pdrt_profile_begin and
+ * pdrt_profile_end every kernel that pdrt_dose_forward / _backward / _forward_f64
+ * enqueue is bracketed by a pair of HIP events on the caller's stream (at most
+ * max_launches launches are recorded; later ones run untimed).  pdrt_profile_end
+ * waits for the recorded events, writes one entry per kernel name (summed
+ * milliseconds and launch count) to out[0 .. *n_entries) and stops recording;
+ * it returns PDRT_E_WORKSPACE if launches went unrecorded.  The recorder is
+ * process-wide and not thread-safe; begin creates its HIP events once and keeps
+ * them for the life of the process. */
+typedef struct {
+  char name[32];
+  int32_t launches;
+  double total_ms;
+} pdrt_kernel_time;
+int pdrt_profile_begin(int32_t max_launches);
+int pdrt_profile_end(pdrt_kernel_time* out, int32_t max_entries, int32_t* n_entries);
+
+/* Human-readable text of a status code (static storage). */
+const char* pdrt_status_string(int status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int pdrt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDRT_H */

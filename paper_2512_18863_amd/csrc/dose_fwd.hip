@@ -1,0 +1,454 @@
+// dose_fwd.hip — forward kernels of the dose path (arXiv:2512.18863 §2.2.2-2.2.7).
+//
+// Per control-point batch the forward runs
+//   k_raster      fluence map F [b][Nu][Nv]                  (§2.2.2, Eq. 4)
+//   k_ca_depth    central-axis depth z [b][Nk]               (§2.2.4, Eq. 7)
+//   k_march       primary P = F (SAD/d)^2 DD(W) [b][Nk][Nu][Nv] (§2.2.3-2.2.4, Eqs. 6-7)
+//   conv          beam-frame dose Dfan = K_k (*) P_k         (§2.2.5-2.2.6, Eq. 8)
+//   k_gather      dose += MU_b trilinear(Dfan_b)             (§2.2.7, Eq. 9)
+// k_frame and k_transpose_rho prepare per-call constants.
+#include "taps.hpp"
+
+namespace pdrt {
+
+// ------------------------------------------------------------------ setup
+
+template <typename T>
+__global__ void k_frame(const T* __restrict__ gantry, int n_cp, T* __restrict__ frame) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_cp) return;
+  double sn, cs;
+  sincospi((double)gantry[b] / 180.0, &sn, &cs);
+  frame[2 * b] = (T)sn;
+  frame[2 * b + 1] = (T)cs;
+}
+
+template <typename T>
+hipError_t launch_frame(const Geo<T>& g, const T* gantry, int n_cp, T* frame, hipStream_t s) {
+  (void)g;
+  hipLaunchKernelGGL(k_frame<T>, dim3((n_cp + 255) / 256), dim3(256), 0, s, gantry, n_cp, frame);
+  return hipGetLastError();
+}
+
+struct HuTable {
+  int n;
+  float hu[16], rho[16];
+};
+
+// HU -> relative density: piecewise-linear calibration curve, clamped (§2.2).
+__global__ void k_hu_to_density(long n, const float* __restrict__ hu, float* __restrict__ rho, HuTable t) {
+  long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  float h = hu[q];
+  float r;
+  if (h <= t.hu[0]) {
+    r = t.rho[0];
+  } else if (h >= t.hu[t.n - 1]) {
+    r = t.rho[t.n - 1];
+  } else {
+    int s = 0;
+    while (h > t.hu[s + 1]) ++s;
+    float f = (h - t.hu[s]) / (t.hu[s + 1] - t.hu[s]);
+    r = t.rho[s] + f * (t.rho[s + 1] - t.rho[s]);
+  }
+  rho[q] = r;
+}
+
+hipError_t launch_hu_to_density(long n, const float* hu, float* rho, int n_pts, const float* hp, const float* rp,
+                                hipStream_t s) {
+  HuTable t;
+  t.n = n_pts;
+  for (int i = 0; i < n_pts; ++i) {
+    t.hu[i] = hp[i];
+    t.rho[i] = rp[i];
+  }
+  hipLaunchKernelGGL(k_hu_to_density, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, hu, rho, t);
+  return hipGetLastError();
+}
+
+// rho [nz][ny][nx] -> rho_t [ny][nx][nz] (per y slice, a tiled 2-D transpose).
+template <typename T>
+__global__ void __launch_bounds__(256) k_transpose_rho(int nx, int ny, int nz, const T* __restrict__ rho,
+                                                        T* __restrict__ rho_t) {
+  __shared__ T tile[32][33];
+  int x0 = blockIdx.x * 32, z0 = blockIdx.y * 32, y = blockIdx.z;
+  int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    int z = z0 + r, x = x0 + tx;
+    tile[r][tx] = (z < nz && x < nx) ? rho[((size_t)z * ny + y) * nx + x] : T(0);
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    int x = x0 + r, z = z0 + tx;
+    if (x < nx && z < nz) rho_t[((size_t)y * nx + x) * nz + z] = tile[tx][r];
+  }
+}
+
+template <typename T>
+hipError_t launch_transpose_rho(const Geo<T>& g, const T* rho, T* rho_t, hipStream_t s) {
+  dim3 grid((g.nx + 31) / 32, (g.nz + 31) / 32, g.ny);
+  hipLaunchKernelGGL(k_transpose_rho<T>, grid, dim3(256), 0, s, g.nx, g.ny, g.nz, rho, rho_t);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fluence
+
+// Fluence map of one pixel (§2.2.2):
+//   F = f(u; x1, x2) f(v; y1, y2) [tau S + (1 - tau) O],
+//   S = sum_l w_l (row coverage by the leaf bank), O = sum_l w_l f(u; l_l, r_l).
+template <typename T>
+__global__ void __launch_bounds__(256) k_raster(Geo<T> g, const T* __restrict__ leaves, const T* __restrict__ jaws,
+                                                T* __restrict__ F) {
+  int b = blockIdx.y;
+  int plane = g.Nu * g.Nv;
+  int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= plane) return;
+  int i = r / g.Nv, j = r - i * g.Nv;
+  T D = g.lat, iD = g.inv_lat;
+  T u = (T(i) - g.cu) * D, v = (T(j) - g.cv) * D;
+  const T* jw = jaws + 4 * b;
+  const T* lv = leaves + (size_t)2 * g.L * b;
+  T fx = overlap(u, jw[0], jw[1], D, iD);
+  T fy = overlap(v, jw[2], jw[3], D, iD);
+  T S = T(0), O = T(0);
+  if (fx * fy != T(0)) {
+    for (int l = 0; l < g.L; ++l) {
+      T w = overlap(v, g.leaf_edges[l], g.leaf_edges[l + 1], D, iD);
+      if (w > T(0)) {
+        S += w;
+        O += w * overlap(u, lv[l], lv[g.L + l], D, iD);
+      }
+    }
+  }
+  F[(size_t)b * plane + r] = fx * fy * (g.tau * S + (T(1) - g.tau) * O);
+}
+
+template <typename T>
+hipError_t launch_raster(const Geo<T>& g, int nb, const T* leaves, const T* jaws, T* F, hipStream_t s) {
+  dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
+  hipLaunchKernelGGL(k_raster<T>, grid, dim3(256), 0, s, g, leaves, jaws, F);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ depth
+
+// Central-axis depth (§2.2.4, Eq. 7): one wavefront per control point samples
+// 64 consecutive planes at a time and turns them into the running integral with
+// an inclusive wavefront prefix sum plus the carry of the previous chunk.
+template <typename T>
+__global__ void __launch_bounds__(64) k_ca_depth(Geo<T> g, const T* __restrict__ frame, const T* __restrict__ rho_t,
+                                                 T* __restrict__ z) {
+  int b = blockIdx.x;
+  int lane = threadIdx.x;
+  T sn = frame[2 * b], cs = frame[2 * b + 1];
+  T carry = T(0);
+  for (int k0 = 0; k0 < g.Nk; k0 += 64) {
+    int k = k0 + lane;
+    T val = T(0);
+    if (k < g.Nk) {
+      T e = g.e0 + T(k) * g.dstep;
+      T X = g.iso_ix + (-e * sn) * g.inv_sx;
+      T Y = g.iso_iy + (e * cs) * g.inv_sy;
+      val = sample_rho(rho_t, g.nx, g.ny, g.nz, X, Y, g.iso_iz) * g.dstep;
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      T o = __shfl_up(val, off, 64);
+      if (lane >= off) val += o;
+    }
+    if (k < g.Nk) z[(size_t)b * g.Nk + k] = carry + val;
+    carry += __shfl(val, 63, 64);
+  }
+}
+
+template <typename T>
+hipError_t launch_ca_depth(const Geo<T>& g, int nb, const T* frame, const T* rho_t, T* z, hipStream_t s) {
+  hipLaunchKernelGGL(k_ca_depth<T>, dim3(nb), dim3(64), 0, s, g, frame, rho_t, z);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ ray march
+
+// One thread per divergent ray (i, j): ray (u_i, v_j) meets plane k at
+//   q - iso = (d_k - SAD) b + (d_k / SAD)(u e_u + v e_v);
+// the density is sampled trilinearly there and integrated with a compensated
+// running sum (step Dd sqrt(1 + (u^2 + v^2)/SAD^2)), giving W_k; the primary is
+// P_k = F (SAD / d_k)^2 DD(W_k).  Lanes run along v, i.e. along patient z, so the
+// z-fastest density copy is read almost contiguously.  With ADJ the same march
+// instead accumulates A = sum_k H_k (SAD / d_k)^2 DD(W_k) (the adjoint of the
+// primary w.r.t. F).
+template <typename T, bool ADJ>
+__global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ frame, const T* __restrict__ rho_t,
+                                               const T* __restrict__ F, const T* __restrict__ zca,
+                                               const T* __restrict__ dd, T* __restrict__ vol, T* __restrict__ A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tab = reinterpret_cast<T*>(smem_raw);
+  for (int q = threadIdx.x; q < g.n_dd; q += 256) tab[q] = dd[q];
+  __syncthreads();
+  int b = blockIdx.y;
+  int plane = g.Nu * g.Nv;
+  int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= plane) return;
+  int i = r / g.Nv, j = r - i * g.Nv;
+  T* vb = vol + (size_t)b * g.Nk * plane + r;
+  T Fv = T(1);
+  if (!ADJ) {
+    Fv = F[(size_t)b * plane + r];
+    if (Fv == T(0)) {
+      for (int k = 0; k < g.Nk; ++k) vb[(size_t)k * plane] = T(0);
+      return;
+    }
+  }
+  T sn = frame[2 * b], cs = frame[2 * b + 1];
+  T u = (T(i) - g.cu) * g.lat, v = (T(j) - g.cv) * g.lat;
+  T ucs = u * cs, usn = u * sn;
+  T ds = g.dstep * dsqrt(T(1) + (u * u + v * v) * (g.inv_sad * g.inv_sad));
+  const T* zb = zca + (size_t)b * g.Nk;
+  T W = T(0), c = T(0), acc = T(0);
+  for (int k = 0; k < g.Nk; ++k) {
+    T e = g.e0 + T(k) * g.dstep;
+    T gk = T(1) + e * g.inv_sad;
+    T Wk;
+    if (g.wepl_mode == PDRT_WEPL_PER_RAY) {
+      T X = g.iso_ix + (-e * sn + gk * ucs) * g.inv_sx;
+      T Y = g.iso_iy + (e * cs + gk * usn) * g.inv_sy;
+      T Z = g.iso_iz + (gk * v) * g.inv_sz;
+      T rho = sample_rho(rho_t, g.nx, g.ny, g.nz, X, Y, Z);
+      T y = rho * ds - c;  // Kahan-compensated running sum
+      T t = W + y;
+      c = (t - W) - y;
+      W = t;
+      Wk = W;
+    } else {
+      Wk = zb[k];
+    }
+    T geo = dd_lookup(tab, g.n_dd, g.inv_dd_step, Wk) / (gk * gk);
+    if (ADJ)
+      acc += vb[(size_t)k * plane] * geo;
+    else
+      vb[(size_t)k * plane] = Fv * geo;
+  }
+  if (ADJ) A[(size_t)b * plane + r] = acc;
+}
+
+template <typename T>
+hipError_t launch_march(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* F, const T* z, const T* dd,
+                        T* P, hipStream_t s) {
+  dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
+  hipLaunchKernelGGL((k_march<T, false>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t, F, z, dd, P,
+                     (T*)nullptr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_march_adj(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* z, const T* dd,
+                            const T* H, T* A, hipStream_t s) {
+  dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
+  hipLaunchKernelGGL((k_march<T, true>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t, (const T*)nullptr,
+                     z, dd, const_cast<T*>(H), A);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ kernel taps
+
+template <typename T>
+__device__ void build_taps(const Geo<T>& g, int k, T zk, T* K, int tid, int nthreads) {
+  TapParams<T> tp = tap_params(g, k, zk);
+  int n = g.n_taps, h = g.h;
+  for (int idx = tid; idx < n * n; idx += nthreads) K[idx] = tap_value(tp, idx / n - h, idx % n - h);
+}
+
+// ------------------------------------------------------------------ direct conv
+
+// Zero-padded per-plane convolution Dfan_k = K_k (*) P_k (§2.2.6, Eq. 8) on the
+// vector ALUs.  A block owns a 48 (u) x 32 (v) output tile of one plane; the
+// input tile with its halo and the plane's taps are staged in LDS.  Each thread
+// owns 6 outputs along u and slides a 6-deep register window down the tap rows,
+// so each tap costs 6 FMAs per LDS load.  Used for the FP64 path and for small
+// kernels.
+constexpr int DC_COLS = 32, DC_RG = 8, DC_R = 6, DC_ROWS = DC_RG * DC_R;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_conv_direct(Geo<T> g, const T* __restrict__ zca, const T* __restrict__ in,
+                                                     T* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = g.n_taps, h = g.h;
+  const int pitch = DC_COLS + 2 * h;
+  const int rows = DC_ROWS + 2 * h + DC_R;  // DC_R spare rows for the window prefetch
+  T* tile = reinterpret_cast<T*>(smem_raw);
+  T* K = tile + rows * pitch;
+  const int k = blockIdx.y, b = blockIdx.z;
+  const int tiles_v = (g.Nv + DC_COLS - 1) / DC_COLS;
+  const int i0 = (blockIdx.x / tiles_v) * DC_ROWS, j0 = (blockIdx.x % tiles_v) * DC_COLS;
+  const int plane = g.Nu * g.Nv;
+  const T* src = in + ((size_t)b * g.Nk + k) * plane;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < rows * pitch; idx += 256) {
+    int rr = idx / pitch, cc = idx - rr * pitch;
+    int i = i0 - h + rr, j = j0 - h + cc;
+    T val = T(0);
+    if (rr < DC_ROWS + 2 * h && i >= 0 && i < g.Nu && j >= 0 && j < g.Nv) val = src[(size_t)i * g.Nv + j];
+    tile[idx] = val;
+  }
+  build_taps(g, k, zca[(size_t)b * g.Nk + k], K, tid, 256);
+  __syncthreads();
+  const int tx = tid % DC_COLS, ty = tid / DC_COLS;
+  const int rbase = ty * DC_R;
+  T acc[DC_R];
+#pragma unroll
+  for (int r = 0; r < DC_R; ++r) acc[r] = T(0);
+  for (int q = 0; q < n; ++q) {
+    const T* col = tile + rbase * pitch + tx + q;
+    T w[DC_R];
+#pragma unroll
+    for (int r = 0; r < DC_R; ++r) w[r] = col[r * pitch];
+    for (int p0 = 0; p0 < n; p0 += DC_R) {
+#pragma unroll
+      for (int s = 0; s < DC_R; ++s) {
+        int p = p0 + s;
+        if (p < n) {
+          T t = K[p * n + q];
+#pragma unroll
+          for (int r = 0; r < DC_R; ++r) acc[r] += t * w[(r + s) % DC_R];
+          w[s] = col[(p + DC_R) * pitch];
+        }
+      }
+    }
+  }
+  T* dst = out + ((size_t)b * g.Nk + k) * plane;
+  int j = j0 + tx;
+#pragma unroll
+  for (int r = 0; r < DC_R; ++r) {
+    int i = i0 + rbase + r;
+    if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[r];
+  }
+}
+
+template <typename T>
+size_t conv_direct_lds(const Geo<T>& g) {
+  int pitch = DC_COLS + 2 * g.h, rows = DC_ROWS + 2 * g.h + DC_R;
+  return sizeof(T) * ((size_t)rows * pitch + (size_t)g.n_taps * g.n_taps);
+}
+
+template <typename T>
+hipError_t launch_conv_direct(const Geo<T>& g, int nb, const T* z, const T* in, T* out, hipStream_t s) {
+  size_t lds = conv_direct_lds(g);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_conv_direct<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  int tiles = ((g.Nu + DC_ROWS - 1) / DC_ROWS) * ((g.Nv + DC_COLS - 1) / DC_COLS);
+  dim3 grid(tiles, g.Nk, nb);
+  hipLaunchKernelGGL(k_conv_direct<T>, grid, dim3(256), lds, s, g, z, in, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ gather
+
+// Back-projection and MU-weighted sum (§2.2.7, Eq. 9).  One thread per voxel,
+// lanes along z so the 2 x 2 beam-frame columns a wavefront reads are contiguous
+// in v.  The sum over control points uses Neumaier compensation; across batches
+// the running sum lives in `dose` and its compensation in `comp`.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather(Geo<T> g, int nb, int first, int last, const T* __restrict__ frame,
+                                                const T* __restrict__ mu, const T* __restrict__ Dfan,
+                                                T* __restrict__ dose, T* __restrict__ comp) {
+  int z = blockIdx.x * 64 + (threadIdx.x & 63);
+  int x = blockIdx.y * 4 + (threadIdx.x >> 6);
+  int y = blockIdx.z;
+  if (z >= g.nz || x >= g.nx) return;
+  size_t vox = ((size_t)z * g.ny + y) * g.nx + x;
+  T tx = g.rel_ox + T(x) * g.sx, ty = g.rel_oy + T(y) * g.sy, tz = g.rel_oz + T(z) * g.sz;
+  T s = T(0), c = T(0);
+  if (!first) {
+    s = dose[vox];
+    c = comp[vox];
+  }
+  const int plane = g.Nu * g.Nv;
+  for (int b = 0; b < nb; ++b) {
+    T sn = frame[2 * b], cs = frame[2 * b + 1];
+    FanIdx<T> f = voxel_to_fan(g, sn, cs, tx, ty, tz);
+    T fk = dfloor(f.k), fi = dfloor(f.i), fj = dfloor(f.j);
+    int k0 = (int)fk, i0 = (int)fi, j0 = (int)fj;
+    if (k0 < -1 || k0 >= g.Nk || i0 < -1 || i0 >= g.Nu || j0 < -1 || j0 >= g.Nv) continue;
+    T wk = f.k - fk, wi = f.i - fi, wj = f.j - fj;
+    const T* base = Dfan + (size_t)b * g.Nk * plane;
+    T acc = T(0);
+#pragma unroll
+    for (int dk = 0; dk < 2; ++dk) {
+      int kk = k0 + dk;
+      if (kk < 0 || kk >= g.Nk) continue;
+      T wkk = dk ? wk : T(1) - wk;
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        int ii = i0 + di;
+        if (ii < 0 || ii >= g.Nu) continue;
+        T wii = di ? wi : T(1) - wi;
+        const T* colp = base + (size_t)kk * plane + (size_t)ii * g.Nv;
+        T a = (j0 >= 0) ? colp[j0] : T(0);
+        T bv = (j0 + 1 < g.Nv) ? colp[j0 + 1] : T(0);
+        acc += wkk * wii * (a + wj * (bv - a));
+      }
+    }
+    T val = mu[b] * acc;
+    T t = s + val;
+    if (fabs(s) >= fabs(val))
+      c += (s - t) + val;
+    else
+      c += (val - t) + s;
+    s = t;
+  }
+  if (last) {
+    dose[vox] = g.calib * (s + c);
+  } else {
+    dose[vox] = s;
+    comp[vox] = c;
+  }
+}
+
+template <typename T>
+hipError_t launch_gather(const Geo<T>& g, int nb, int first, int last, const T* frame, const T* mu, const T* Dfan,
+                         T* dose, T* comp, hipStream_t s) {
+  dim3 grid((g.nz + 63) / 64, (g.nx + 3) / 4, g.ny);
+  hipLaunchKernelGGL(k_gather<T>, grid, dim3(256), 0, s, g, nb, first, last, frame, mu, Dfan, dose, comp);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_fill(T* p, size_t n, T v) {
+  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; q < n; q += stride) p[q] = v;
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+#define PDRT_INST(T)                                                                                         \
+  template hipError_t launch_frame<T>(const Geo<T>&, const T*, int, T*, hipStream_t);                        \
+  template hipError_t launch_transpose_rho<T>(const Geo<T>&, const T*, T*, hipStream_t);                     \
+  template hipError_t launch_raster<T>(const Geo<T>&, int, const T*, const T*, T*, hipStream_t);             \
+  template hipError_t launch_ca_depth<T>(const Geo<T>&, int, const T*, const T*, T*, hipStream_t);           \
+  template hipError_t launch_march<T>(const Geo<T>&, int, const T*, const T*, const T*, const T*, const T*, T*, \
+                                      hipStream_t);                                                          \
+  template hipError_t launch_march_adj<T>(const Geo<T>&, int, const T*, const T*, const T*, const T*, const T*, \
+                                          T*, hipStream_t);                                                  \
+  template hipError_t launch_conv_direct<T>(const Geo<T>&, int, const T*, const T*, T*, hipStream_t);        \
+  template hipError_t launch_gather<T>(const Geo<T>&, int, int, int, const T*, const T*, const T*, T*, T*,    \
+                                       hipStream_t);                                                         \
+  template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);
+
+PDRT_INST(float)
+PDRT_INST(double)
+
+}  // namespace pdrt

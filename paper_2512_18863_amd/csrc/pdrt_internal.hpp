@@ -1,0 +1,100 @@
+// pdrt_internal.hpp — shared definitions of the HIP dose library (not part of the ABI).
+//
+// Fan-grid ("beam frame") storage is [cp][Nk][Nu][Nv] with v (the leaf-stacking
+// axis, parallel to patient z) fastest.  Because v is always patient z
+// (collimator 0), consecutive v along a ray plane map to consecutive z in the CT,
+// and the density copy the ray march reads is stored z-fastest ([ny][nx][nz]):
+// lanes that walk along v then load neighbouring words.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pdrt.h"
+
+namespace pdrt {
+
+// Geometry and model constants, passed to kernels by value.  Everything is
+// stored relative to the isocentre so that FP32 never handles the 1000 mm source
+// distance directly.
+template <typename T>
+struct Geo {
+  // CT grid
+  int nx, ny, nz;
+  T sx, sy, sz;
+  T inv_sx, inv_sy, inv_sz;
+  T rel_ox, rel_oy, rel_oz;  // centre of voxel (0,0,0) minus the isocentre
+  T iso_ix, iso_iy, iso_iz;  // continuous voxel index of the isocentre
+  // beam frame
+  int Nu, Nv, Nk;
+  T cu, cv;           // (N - 1) / 2
+  T lat, inv_lat;     // ray spacing at the isocentre plane
+  T dstep, inv_dstep; // plane spacing along the central axis
+  T e0;               // first plane distance minus SAD (= -R)
+  T sad, inv_sad;
+  // model
+  int n_taps, h;
+  int wepl_mode;
+  T tau, calib;
+  int n_dd;
+  T inv_dd_step;
+  T kpoly[4][4];
+  T kz_max;
+  int L;
+  T leaf_edges[PDRT_MAX_LEAF_PAIRS + 1];
+};
+
+// Workspace layout (byte offsets) plus sizes, computed on the host.
+struct Layout {
+  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, total;
+  int batch;
+};
+
+template <typename T>
+struct Launch {
+  const Geo<T>* g;
+  hipStream_t stream;
+};
+
+// --- launchers (defined in the kernel translation units) -------------------
+template <typename T>
+hipError_t launch_frame(const Geo<T>& g, const T* gantry_deg, int n_cp, T* frame, hipStream_t s);
+hipError_t launch_hu_to_density(long n, const float* hu, float* rho, int n_pts, const float* hp, const float* rp,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_transpose_rho(const Geo<T>& g, const T* rho, T* rho_t, hipStream_t s);
+template <typename T>
+hipError_t launch_raster(const Geo<T>& g, int nb, const T* leaves, const T* jaws, T* F, hipStream_t s);
+template <typename T>
+hipError_t launch_ca_depth(const Geo<T>& g, int nb, const T* frame, const T* rho_t, T* z, hipStream_t s);
+template <typename T>
+hipError_t launch_march(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* F, const T* z,
+                        const T* dd, T* P, hipStream_t s);
+template <typename T>
+hipError_t launch_march_adj(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* z, const T* dd,
+                            const T* H, T* A, hipStream_t s);
+template <typename T>
+hipError_t launch_conv_direct(const Geo<T>& g, int nb, const T* z, const T* in, T* out, hipStream_t s);
+hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
+                                hipStream_t s);
+hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
+                                 hipStream_t s);
+template <typename T>
+hipError_t launch_gather(const Geo<T>& g, int nb, int first, int last, const T* frame, const T* mu,
+                         const T* Dfan, T* dose, T* comp, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s);
+template <typename T>
+hipError_t launch_scatter(const Geo<T>& g, int nb, const T* frame, const T* grad, T* Ghat, hipStream_t s);
+template <typename T>
+hipError_t launch_param_grad(const Geo<T>& g, int nb, const T* leaves, const T* jaws, const T* mu, const T* A,
+                             T* gleaves, T* gjaws, T* gmu, hipStream_t s);
+hipError_t launch_project(int n_cp, int L, const float* lv, const float* jw, const float* mu, double leaf_lim,
+                          double jx_lim, double jy_lim, double w_min, double mu_min, float* lo, float* jo,
+                          float* mo, hipStream_t s);
+hipError_t launch_project_bwd(int n_cp, int L, const float* lv, const float* jw, const float* mu, double leaf_lim,
+                              double jx_lim, double jy_lim, double w_min, double mu_min, int ste,
+                              const float* gl, const float* gj, const float* gm, float* ol, float* oj, float* om,
+                              hipStream_t s);
+
+}  // namespace pdrt

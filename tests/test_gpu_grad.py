@@ -1,0 +1,172 @@
+"""GPU reverse mode: the hand-written adjoint against the FP64 oracle's gradient
+and against central finite differences of the GPU's own FP64 forward.
+
+Bars: FP32 adjoint vs oracle <= 1e-4 * max|grad| per group (leaves, jaws, MU);
+FP64 finite differences vs the oracle gradient <= 1e-6 relative (the dose is
+piecewise linear in every leaf and jaw, so central differences are exact away
+from the kinks).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2512_18863_amd import inputs
+from tests.test_gpu_parity import _say, _t, subset
+
+pytestmark = pytest.mark.gpu
+
+TOL_GRAD = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _grads_gpu(case, w, **kw):
+    from paper_2512_18863_amd.engine import DoseEngine
+    eng = DoseEngine(case, **kw)
+    gl, gj, gm = eng.backward(_t(case.leaves), _t(case.jaws), _t(case.mu), _t(w))
+    torch.cuda.synchronize()
+    return gl.cpu().numpy(), gj.cpu().numpy(), gm.cpu().numpy(), eng
+
+
+def _grads_oracle(case, w):
+    m = oracle.Model(case)
+    rho = oracle.density(m)
+    return oracle.backward(m, rho, case.gantry, case.leaves, case.jaws, case.mu, w)
+
+
+def _check(name, got, ref):
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max() / scale if scale > 0 else np.abs(got).max()
+    _say("%s: max|dg|/max|g| = %.3e (max|g| = %.3e)" % (name, err, scale))
+    assert err <= TOL_GRAD, name
+
+
+@pytest.mark.parametrize("seed,n_taps", [(31, 3), (32, 5), (33, 15)])
+def test_tiny_gradient_parity(seed, n_taps):
+    _say("tiny gradients seed=%d n=%d" % (seed, n_taps))
+    c = inputs.tiny_case(seed=seed, n_cp=3, n_taps=n_taps, shape=(6, 7, 6), spacing=8.0, field=30.0)
+    w = np.random.default_rng(seed).uniform(size=c.shape)
+    gl, gj, gm, _ = _grads_gpu(c, w)
+    rl, rj, rm = _grads_oracle(c, w)
+    _check("leaves", gl, rl)
+    _check("jaws", gj, rj)
+    _check("mu", gm, rm)
+
+
+def test_c1_gradient_parity():
+    _say("C1 gradients, 90 CPs, L = sum w D")
+    c = inputs.config_c1()
+    gl, gj, gm, _ = _grads_gpu(c, c.loss_w)
+    rl, rj, rm = _grads_oracle(c, c.loss_w)
+    _check("leaves", gl, rl)
+    _check("jaws", gj, rj)
+    _check("mu", gm, rm)
+
+
+def test_c4bench_gradient_parity_subset():
+    _say("C4-bench gradients n=61, 3 CPs")
+    c = subset(inputs.config_c4_plan(2000, bench=True), np.array([10, 80, 140]))
+    w = np.random.default_rng(4004).uniform(size=c.shape)
+    gl, gj, gm, _ = _grads_gpu(c, w)
+    rl, rj, rm = _grads_oracle(c, w)
+    _check("leaves", gl, rl)
+    _check("jaws", gj, rj)
+    _check("mu", gm, rm)
+
+
+def _fd_edges(case, n_edges, seed, h):
+    """Leaf edges in rows inside the Y jaws, in open pairs, with no pixel boundary
+    (kink of the overlap) within 2h."""
+    D = case.lat_step
+    m = oracle.Model(case)
+    bounds = (np.arange(m.Nu + 1) - m.Nu / 2.0) * D
+    edges = case.machine.leaf_edges
+    out = []
+    rng = np.random.default_rng(seed)
+    cps = rng.permutation(case.n_cp)
+    for b in cps:
+        lv = case.leaves[b]
+        jw = case.jaws[b]
+        cand = []
+        for l in range(case.machine.n_leaf):
+            if edges[l + 1] <= jw[2] or edges[l] >= jw[3]:
+                continue
+            if lv[1, l] - lv[0, l] < 4 * h:
+                continue
+            for side in (0, 1):
+                x = lv[side, l]
+                if np.min(np.abs(bounds - x)) > 2 * h and np.min(np.abs(jw[:2] - x)) > 2 * h:
+                    cand.append((b, side, l))
+        if cand:
+            pick = rng.choice(len(cand), size=min(4, len(cand)), replace=False)
+            out.extend(cand[i] for i in pick)
+        if len(out) >= n_edges:
+            break
+    return out[:n_edges]
+
+
+def test_c2_fd_fp64_vs_adjoint_vs_oracle():
+    """64 leaf edges of the two-arc C2 plan (16 control points drawn by seed 2004):
+    GPU FP64 central differences (h = 0.01 mm) vs the oracle gradient vs the GPU FP32
+    adjoint."""
+    from paper_2512_18863_amd.engine import DoseEngine
+    h = 0.01
+    full = inputs.config_c2()
+    picks = _fd_edges(full, 64, 2004, h)
+    cps = sorted(set(b for b, _, _ in picks))
+    c = subset(full, np.array(cps))
+    _say("C2 FD: %d edges over %d CPs" % (len(picks), len(cps)))
+    w = np.random.default_rng(2005).uniform(size=c.shape)
+    wt = _t(w, torch.float64)
+    eng = DoseEngine(c, with_f64=True)
+    m = oracle.Model(c)
+    rho = oracle.density(m)
+    eng.set_density_f64(_t(rho, torch.float64))
+    rl, rj, rm = oracle.backward(m, rho, c.gantry, c.leaves, c.jaws, c.mu, w)
+    gl, _, _ = eng.backward(_t(c.leaves), _t(c.jaws), _t(c.mu), _t(w))
+    gl = gl.cpu().numpy()
+    lv = _t(c.leaves, torch.float64)
+    jw = _t(c.jaws, torch.float64)
+    mu = _t(c.mu, torch.float64)
+    fd, ref, adj = [], [], []
+    for (b, side, l) in picks:
+        bi = cps.index(b)
+        lp = lv.clone()
+        lp[bi, side, l] += h
+        Lp = float((eng.forward_f64(lp, jw, mu) * wt).sum())
+        lp[bi, side, l] -= 2 * h
+        Lm = float((eng.forward_f64(lp, jw, mu) * wt).sum())
+        fd.append((Lp - Lm) / (2 * h))
+        ref.append(rl[bi, side, l])
+        adj.append(gl[bi, side, l])
+    fd, ref, adj = map(np.array, (fd, ref, adj))
+    scale = np.abs(ref).max()
+    e_fd = np.abs(fd - ref).max() / scale
+    e_adj = np.abs(adj - ref).max() / scale
+    _say("FD(fp64 GPU) vs oracle: %.3e ; adjoint(fp32 GPU) vs oracle: %.3e ; max|g| %.3e"
+         % (e_fd, e_adj, scale))
+    assert np.count_nonzero(ref) >= 32
+    assert e_fd <= 1e-6
+    assert e_adj <= TOL_GRAD
+
+
+def test_autograd_function_matches_backward():
+    _say("autograd.Function on C0")
+    from paper_2512_18863_amd.engine import DoseEngine
+    c = inputs.config_c0()
+    eng = DoseEngine(c)
+    lv = _t(c.leaves).requires_grad_()
+    jw = _t(c.jaws).requires_grad_()
+    mu = _t(c.mu).requires_grad_()
+    w = _t(np.random.default_rng(1).uniform(size=c.shape))
+    loss = (eng(lv, jw, mu) * w).sum()
+    loss.backward()
+    gl, gj, gm = eng.backward(_t(c.leaves), _t(c.jaws), _t(c.mu), w)
+    assert torch.equal(lv.grad, gl) or torch.allclose(lv.grad, gl, rtol=1e-5, atol=1e-6 * gl.abs().max())
+    assert torch.allclose(mu.grad, gm, rtol=1e-5)
+    assert torch.allclose(jw.grad, gj, rtol=1e-5, atol=1e-6 * gj.abs().max())
