@@ -140,9 +140,8 @@ int pdrt_dose_forward(const pdrt_grid* grid, const float* rho, const pdrt_beam* 
  * [n_cp] (device, overwritten).  Beam-frame volumes are recomputed per control
  * point, nothing is kept from the forward call.  The fluence map is piecewise
  * linear; at its kinks the one-sided derivative with strict inequalities is used
- * (a leaf exactly on a pixel boundary contributes zero there).  Uses float atomics
- * in the back-projection adjoint, so results may differ in the last bits between
- * runs.  ws_bytes >= pdrt_workspace_bytes(..., 1, 4). */
+ * (a leaf exactly on a pixel boundary contributes zero there).  Deterministic:
+ * no atomics, every sum in a fixed order.  ws_bytes >= pdrt_workspace_bytes(..., 1, 4). */
 int pdrt_dose_backward(const pdrt_grid* grid, const float* rho, const pdrt_beam* beam, const float* leaves,
                        const float* jaws, const float* mu, const pdrt_kernel_spec* spec, const float* grad_dose,
                        float* grad_leaves, float* grad_jaws, float* grad_mu, void* ws, size_t ws_bytes,

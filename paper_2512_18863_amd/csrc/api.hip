@@ -278,17 +278,17 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
   T* vol0 = (T*)(w + P.lay.vol0);
   T* vol1 = (T*)(w + P.lay.vol1);
   T* A = (T*)(w + P.lay.adj);
+  T* g_t = (T*)(w + P.lay.comp);  // dose gradient, z fastest
   const T* dd = (const T*)spec->dd;
   const int L = beam->n_leaf_pairs, n_cp = beam->n_cp;
-  const size_t plane = (size_t)P.Nu * P.Nv;
   LAUNCH("frame", launch_frame<T>(g, (const T*)beam->gantry_deg, n_cp, frame, s));
   LAUNCH("transpose_rho", launch_transpose_rho<T>(g, rho, rho_t, s));
+  LAUNCH("transpose_grad", launch_transpose_rho<T>(g, grad, g_t, s));
   for (int cp0 = 0; cp0 < n_cp; cp0 += P.batch) {
     int nb = n_cp - cp0 < P.batch ? n_cp - cp0 : P.batch;
     const T* fr = frame + 2 * cp0;
     LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
-    LAUNCH("fill", launch_fill<T>(vol0, (size_t)nb * P.Nk * plane, T(0), s));
-    LAUNCH("scatter", launch_scatter<T>(g, nb, fr, grad, vol0, s));
+    LAUNCH("backproject_adj", launch_backproject_adj<T>(g, nb, fr, g_t, vol0, s));
     LAUNCH(conv_name<T>(g, spec->conv_mode), run_conv<T>(g, spec->conv_mode, nb, z, vol0, vol1, s));
     LAUNCH("march_adj", launch_march_adj<T>(g, nb, fr, rho_t, z, dd, vol1, A, s));
     LAUNCH("param_grad", launch_param_grad<T>(g, nb, leaves + (size_t)2 * L * cp0, jaws + (size_t)4 * cp0, mu + cp0, A,

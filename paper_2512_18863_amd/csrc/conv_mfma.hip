@@ -6,16 +6,21 @@
 //   out[i][j0..j0+15] += in[i+p][j0-h .. j0+15+h] * T_p,  T_p[c][n] = K[p][c - h - n],
 // so a 16 x 16 output tile is a GEMM with K-dimension 16 + 2h over input columns.
 // The Toeplitz operand depends only on (p, column step), never on the tile, so a
-// wavefront keeps it in registers and streams the input rows of all its tiles past
-// it.  A workgroup (4 wavefronts) owns a region of up to 6 x 6 tiles (96 x 96
-// outputs) of one (control point, plane); the input region with its halo and the
-// plane's taps are staged in LDS once.
+// wavefront loads it once per step and streams the input rows of all its tiles
+// past it.  A workgroup owns a region of up to 6 x 6 tiles (96 x 96 outputs) of
+// one (control point, plane); the input region with its halo and the plane's
+// taps are staged in LDS once, then NW wavefronts each run TPW tiles.  The inner
+// loop is branch free and software pipelined: the operands of step t+1 are
+// loaded from LDS before the matrix instructions of step t are issued.
 //
 //   FP32: v_mfma_f32_16x16x4_f32.  Tap rows p and -p are equal (the kernel is
 //         radially symmetric), so rows i+p and i-p are added before the product
 //         and only h+1 tap rows are multiplied (row 0 with halved taps).
 //   BF16: v_mfma_f32_16x16x32_bf16, operands rounded to BF16 (round to nearest
-//         even), FP32 accumulation; all n tap rows.
+//         even), FP32 accumulation; all n tap rows.  Each lane's eight Toeplitz
+//         entries are one aligned 16-byte LDS read from one of eight copies of
+//         the tap row, shifted so that every lane's run starts on a 16-byte
+//         boundary.
 #include "taps.hpp"
 
 namespace pdrt {
@@ -25,6 +30,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int MT = 16;      // MFMA output tile edge
 constexpr int RMAX = 6;     // region edge in tiles
+constexpr size_t LDS_MAX = 160 * 1024;
 
 struct RegionShape {
   int TI, TJ;               // tiles per region along u (rows) and v (columns)
@@ -41,9 +47,46 @@ static RegionShape region_shape(int Nu, int Nv, int rmax) {
   return r;
 }
 
-// Row pitch (elements) congruent to 4 mod 32 so that the 16 rows x 4 columns an
-// FP32 A-fragment touches fall in distinct LDS banks.
-static int pitch_f32(int cols) { return ((cols + 27) / 32) * 32 + 4; }
+// Unique taps K[p][q], 0 <= p, q <= h, of the plane into `kq` ((h+1) x (h+1)).
+__device__ __forceinline__ void unique_taps(const Geo<float>& g, int k, float zk, float* kq, int tid, int nt) {
+  TapParams<float> tp = tap_params(g, k, zk);
+  const int h1 = g.h + 1;
+  for (int idx = tid; idx < h1 * h1; idx += nt) kq[idx] = tap_value(tp, idx / h1, idx % h1);
+}
+
+// Stage the input region (rows I0-h .., columns J0-h ..) of one plane; zero
+// outside the plane and beyond `cols_valid`.
+template <typename E>
+__device__ __forceinline__ void stage_tile(const Geo<float>& g, const float* __restrict__ src, int I0, int J0,
+                                           int rows, int pitch, int cols_valid, E* tile, int tid, int nt) {
+  const int h = g.h;
+  for (int idx = tid; idx < rows * pitch; idx += nt) {
+    int rr = idx / pitch, cc = idx - rr * pitch;
+    int i = I0 - h + rr, j = J0 - h + cc;
+    float v = 0.f;
+    if (i >= 0 && i < g.Nu && j >= 0 && j < g.Nv && cc < cols_valid) v = src[(size_t)i * g.Nv + j];
+    tile[idx] = (E)v;
+  }
+}
+
+template <int TPW>
+__device__ __forceinline__ void store_tiles(const Geo<float>& g, const RegionShape& rs, int NW, int wave, int I0,
+                                            int J0, int lane, const f32x4 (&acc)[TPW], const bool (&active)[TPW],
+                                            float* dst) {
+  const int m = lane & 15, r4 = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    if (!active[q]) continue;
+    int t = wave + NW * q;
+    int ti = t / rs.TJ, tj = t - ti * rs.TJ;
+    int j = J0 + MT * tj + m;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int i = I0 + MT * ti + 4 * r4 + r;
+      if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[q][r];
+    }
+  }
+}
 
 // ------------------------------------------------------------------ FP32
 
@@ -52,6 +95,10 @@ struct F32Shape {
   int E;       // extended tap row length: 4 S + 16
   int rows, pitch;
 };
+
+// Row pitch (elements) congruent to 4 mod 32 so that the 16 rows x 4 columns an
+// FP32 A-fragment touches fall in distinct LDS banks.
+static int pitch_f32(int cols) { return ((cols + 27) / 32) * 32 + 4; }
 
 static F32Shape f32_shape(int h, const RegionShape& r) {
   F32Shape s;
@@ -62,274 +109,246 @@ static F32Shape f32_shape(int h, const RegionShape& r) {
   return s;
 }
 
-static size_t f32_lds(const Geo<float>& g, const F32Shape& fs) {
-  return sizeof(float) * ((size_t)fs.rows * fs.pitch + (size_t)(g.h + 1) * fs.E);
+static size_t f32_lds(int h, const F32Shape& fs) {
+  return sizeof(float) * ((size_t)fs.rows * fs.pitch + (size_t)(h + 1) * fs.E + (size_t)(h + 1) * (h + 1));
 }
 
-template <int TPW>
-__global__ void __launch_bounds__(256) k_conv_mfma_f32(Geo<float> g, RegionShape rs, F32Shape fs,
-                                                       const float* __restrict__ zca, const float* __restrict__ in,
-                                                       float* __restrict__ out) {
+template <int NW, int TPW>
+__global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionShape rs, F32Shape fs,
+                                                           const float* __restrict__ zca,
+                                                           const float* __restrict__ in, float* __restrict__ out) {
   extern __shared__ __align__(16) float lds[];
+  constexpr int NT = 64 * NW;
   const int h = g.h;
   const int rows = fs.rows, pitch = fs.pitch, E = fs.E, S = fs.S;
   float* tile = lds;
   float* kx = lds + rows * pitch;  // (h + 1) x E, zero outside |q| <= h, row 0 halved
+  float* kq = kx + (h + 1) * E;    // (h + 1) x (h + 1) unique taps
   const int k = blockIdx.y, b = blockIdx.z;
   const int I0 = (blockIdx.x / rs.regions_j) * rs.TI * MT;
   const int J0 = (blockIdx.x % rs.regions_j) * rs.TJ * MT;
   const int plane = g.Nu * g.Nv;
-  const float* src = in + ((size_t)b * g.Nk + k) * plane;
   const int tid = threadIdx.x;
 
-  for (int idx = tid; idx < rows * pitch; idx += 256) {
-    int rr = idx / pitch, cc = idx - rr * pitch;
-    int i = I0 - h + rr, j = J0 - h + cc;
+  stage_tile(g, in + ((size_t)b * g.Nk + k) * plane, I0, J0, rows, pitch, MT * rs.TJ + 2 * h, tile, tid, NT);
+  unique_taps(g, k, zca[(size_t)b * g.Nk + k], kq, tid, NT);
+  __syncthreads();
+  const int off = h + 15;
+  for (int idx = tid; idx < (h + 1) * E; idx += NT) {
+    int p = idx / E, c = idx - p * E;
+    int q = c - off;
     float v = 0.f;
-    if (i >= 0 && i < g.Nu && j >= 0 && j < g.Nv && cc < MT * rs.TJ + 2 * h) v = src[(size_t)i * g.Nv + j];
-    tile[idx] = v;
-  }
-  {
-    TapParams<float> tp = tap_params(g, k, zca[(size_t)b * g.Nk + k]);
-    const int off = h + 15;
-    for (int idx = tid; idx < (h + 1) * E; idx += 256) {
-      int p = idx / E, c = idx - p * E;
-      int q = c - off;
-      float v = 0.f;
-      if (q >= -h && q <= h) {
-        v = tap_value(tp, p, q);
-        if (p == 0) v *= 0.5f;
-      }
-      kx[idx] = v;
-    }
+    if (q >= -h && q <= h) v = kq[p * (h + 1) + (q < 0 ? -q : q)] * (p == 0 ? 0.5f : 1.f);
+    kx[idx] = v;
   }
   __syncthreads();
 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int m = lane & 15, kk = lane >> 4;
-  int rowbase[TPW], colbase[TPW];
+  const float* abase[TPW];
   bool active[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
-    int t = wave + 4 * q;
-    int ti = t / rs.TJ, tj = t - ti * rs.TJ;
-    active[q] = t < rs.TI * rs.TJ && I0 + MT * ti < g.Nu && J0 + MT * tj < g.Nv;
-    rowbase[q] = (MT * ti + m + h) * pitch;
-    colbase[q] = MT * tj + kk;
+    int t = wave + NW * q;
+    bool valid = t < rs.TI * rs.TJ;
+    int ti = valid ? t / rs.TJ : 0, tj = valid ? t - (t / rs.TJ) * rs.TJ : 0;
+    active[q] = valid && I0 + MT * ti < g.Nu && J0 + MT * tj < g.Nv;
+    abase[q] = tile + (MT * ti + m + h) * pitch + MT * tj + kk;
   }
+  const float* bbase = kx + 15 + kk - m;
   f32x4 acc[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int p = 0; p <= h; ++p) {
-    const float* krow = kx + p * E + 15 + kk - m;
-    const int up = p * pitch;
-    for (int s = 0; s < S; ++s) {
-      float bv = krow[4 * s];
-#pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        if (active[q]) {
-          const float* a0 = tile + rowbase[q] + colbase[q] + 4 * s;
-          float av = a0[up] + a0[-up];
-          acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[q], 0, 0, 0);
-        }
-      }
-    }
-  }
-
-  float* dst = out + ((size_t)b * g.Nk + k) * plane;
+  const int total = (h + 1) * S;
+  float bn = bbase[0];
+  float an0[TPW], an1[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
-    if (!active[q]) continue;
-    int t = wave + 4 * q;
-    int ti = t / rs.TJ, tj = t - ti * rs.TJ;
-    int j = J0 + MT * tj + m;
+    an0[q] = abase[q][0];
+    an1[q] = an0[q];
+  }
+  int p = 0, s = 0;
+  for (int it = 0; it < total; ++it) {
+    const float bc = bn;
+    float ac[TPW];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int i = I0 + MT * ti + 4 * kk + r;
-      if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[q][r];
+    for (int q = 0; q < TPW; ++q) ac[q] = an0[q] + an1[q];
+    if (++s == S) {
+      s = 0;
+      ++p;
     }
+    if (it + 1 < total) {
+      const int op = p * pitch + 4 * s, om = 4 * s - p * pitch;
+      bn = bbase[p * E + 4 * s];
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        an0[q] = abase[q][op];
+        an1[q] = abase[q][om];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[q], bc, acc[q], 0, 0, 0);
   }
-}
-
-template <int TPW>
-static hipError_t launch_f32_tpw(const Geo<float>& g, const RegionShape& rs, const F32Shape& fs, int nb,
-                                 const float* z, const float* in, float* out, hipStream_t s) {
-  size_t lds = f32_lds(g, fs);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_conv_mfma_f32<TPW>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  dim3 grid(rs.regions_i * rs.regions_j, g.Nk, nb);
-  hipLaunchKernelGGL(k_conv_mfma_f32<TPW>, grid, dim3(256), lds, s, g, rs, fs, z, in, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
-                                hipStream_t s) {
-  // the largest region (in tiles) whose LDS image fits
-  RegionShape rs;
-  F32Shape fs;
-  for (int rmax = RMAX; rmax >= 1; --rmax) {
-    rs = region_shape(g.Nu, g.Nv, rmax);
-    fs = f32_shape(g.h, rs);
-    if (f32_lds(g, fs) <= 160 * 1024) break;
-  }
-  int tpw = (rs.TI * rs.TJ + 3) / 4;
-  if (tpw <= 1) return launch_f32_tpw<1>(g, rs, fs, nb, z, in, out, s);
-  if (tpw <= 2) return launch_f32_tpw<2>(g, rs, fs, nb, z, in, out, s);
-  if (tpw <= 3) return launch_f32_tpw<3>(g, rs, fs, nb, z, in, out, s);
-  if (tpw <= 4) return launch_f32_tpw<4>(g, rs, fs, nb, z, in, out, s);
-  if (tpw <= 6) return launch_f32_tpw<6>(g, rs, fs, nb, z, in, out, s);
-  return launch_f32_tpw<9>(g, rs, fs, nb, z, in, out, s);
+  store_tiles<TPW>(g, rs, NW, wave, I0, J0, lane, acc, active, out + ((size_t)b * g.Nk + k) * plane);
 }
 
 // ------------------------------------------------------------------ BF16
 
 struct BF16Shape {
   int S;       // K-steps of 32 input columns: ceil((16 + 2h) / 32)
-  int E;       // extended tap row length: 32 S + 16
+  int CL;      // length of one shifted tap-row copy: 32 S + 24 (a multiple of 8)
   int rows, pitch;
 };
 
 static BF16Shape bf16_shape(int h, const RegionShape& r) {
   BF16Shape s;
   s.S = (MT + 2 * h + 31) / 32;
-  s.E = 32 * s.S + 16;
+  s.CL = 32 * s.S + 24;
   s.rows = MT * r.TI + 2 * h;
   int cols = MT * r.TJ + 32 * s.S;  // covers the last K-step's overrun
   s.pitch = ((cols + 7) / 8) * 8 + 8;
   return s;
 }
 
-static size_t bf16_lds(const Geo<float>& g, const BF16Shape& bs) {
-  size_t tile_bytes = ((size_t)bs.rows * bs.pitch * 2 + 15) & ~(size_t)15;
-  return tile_bytes + sizeof(float) * (size_t)(g.h + 1) * bs.E;
+__host__ __device__ static size_t bf16_tile_bytes(const BF16Shape& bs) { return ((size_t)bs.rows * bs.pitch * 2 + 15) & ~(size_t)15; }
+__host__ __device__ static size_t bf16_copy_bytes(int h, const BF16Shape& bs) { return (size_t)(h + 1) * 8 * bs.CL * 2; }
+static size_t bf16_lds(int h, const BF16Shape& bs) {
+  return bf16_tile_bytes(bs) + bf16_copy_bytes(h, bs) + sizeof(float) * (size_t)(h + 1) * (h + 1);
 }
 
-template <int TPW>
-__global__ void __launch_bounds__(256) k_conv_mfma_bf16(Geo<float> g, RegionShape rs, BF16Shape bs,
-                                                        const float* __restrict__ zca, const float* __restrict__ in,
-                                                        float* __restrict__ out) {
+template <int NW, int TPW>
+__global__ void __launch_bounds__(64 * NW) k_conv_mfma_bf16(Geo<float> g, RegionShape rs, BF16Shape bs,
+                                                            const float* __restrict__ zca,
+                                                            const float* __restrict__ in, float* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int NT = 64 * NW;
   const int h = g.h;
-  const int rows = bs.rows, pitch = bs.pitch, E = bs.E, S = bs.S;
+  const int rows = bs.rows, pitch = bs.pitch, CL = bs.CL, S = bs.S;
   __bf16* tile = reinterpret_cast<__bf16*>(smem_raw);
-  size_t tile_bytes = ((size_t)rows * pitch * sizeof(__bf16) + 15) & ~(size_t)15;
-  float* kx = reinterpret_cast<float*>(smem_raw + tile_bytes);  // (h + 1) x E taps, zero outside |q| <= h
+  __bf16* bcopy = reinterpret_cast<__bf16*>(smem_raw + bf16_tile_bytes(bs));  // [h+1][8][CL]
+  float* kq = reinterpret_cast<float*>(smem_raw + bf16_tile_bytes(bs) + bf16_copy_bytes(h, bs));
   const int k = blockIdx.y, b = blockIdx.z;
   const int I0 = (blockIdx.x / rs.regions_j) * rs.TI * MT;
   const int J0 = (blockIdx.x % rs.regions_j) * rs.TJ * MT;
   const int plane = g.Nu * g.Nv;
-  const float* src = in + ((size_t)b * g.Nk + k) * plane;
   const int tid = threadIdx.x;
 
-  for (int idx = tid; idx < rows * pitch; idx += 256) {
-    int rr = idx / pitch, cc = idx - rr * pitch;
-    int i = I0 - h + rr, j = J0 - h + cc;
-    float v = 0.f;
-    if (i >= 0 && i < g.Nu && j >= 0 && j < g.Nv && cc < MT * rs.TJ + 2 * h) v = src[(size_t)i * g.Nv + j];
-    tile[idx] = (__bf16)v;
-  }
-  {
-    TapParams<float> tp = tap_params(g, k, zca[(size_t)b * g.Nk + k]);
-    const int off = h + 15;
-    for (int idx = tid; idx < (h + 1) * E; idx += 256) {
-      int p = idx / E, c = idx - p * E;
-      int q = c - off;
-      kx[idx] = (q >= -h && q <= h) ? tap_value(tp, p, q) : 0.f;
-    }
+  stage_tile(g, in + ((size_t)b * g.Nk + k) * plane, I0, J0, rows, pitch, MT * rs.TJ + 2 * h, tile, tid, NT);
+  unique_taps(g, k, zca[(size_t)b * g.Nk + k], kq, tid, NT);
+  __syncthreads();
+  // Extended tap row x (x = q + h + 15) stored in copy r at position x + sigma_r,
+  // sigma_r = (8 - r) % 8, so that a run starting at x with x % 8 == r is aligned.
+  for (int idx = tid; idx < (h + 1) * 8 * CL; idx += NT) {
+    int p = idx / (8 * CL), rem = idx - p * 8 * CL;
+    int r = rem / CL, y = rem - r * CL;
+    int x = y - ((8 - r) & 7);
+    int q = x - (h + 15);
+    float v = (x >= 0 && q >= -h && q <= h) ? kq[p * (h + 1) + (q < 0 ? -q : q)] : 0.f;
+    bcopy[idx] = (__bf16)v;
   }
   __syncthreads();
 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int m = lane & 15, kq = lane >> 4;  // A: row m, K-columns 8 kq .. 8 kq + 7
-  int rowbase[TPW], colbase[TPW];
+  const int m = lane & 15, kq4 = lane >> 4;  // A: row m, K-columns 8 kq4 .. 8 kq4 + 7; B: column m
+  const __bf16* abase[TPW];
   bool active[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
-    int t = wave + 4 * q;
-    int ti = t / rs.TJ, tj = t - ti * rs.TJ;
-    active[q] = t < rs.TI * rs.TJ && I0 + MT * ti < g.Nu && J0 + MT * tj < g.Nv;
-    rowbase[q] = (MT * ti + m + h) * pitch;
-    colbase[q] = MT * tj + 8 * kq;
+    int t = wave + NW * q;
+    bool valid = t < rs.TI * rs.TJ;
+    int ti = valid ? t / rs.TJ : 0, tj = valid ? t - (t / rs.TJ) * rs.TJ : 0;
+    active[q] = valid && I0 + MT * ti < g.Nu && J0 + MT * tj < g.Nv;
+    abase[q] = tile + (MT * ti + m + h) * pitch + MT * tj + 8 * kq4;
   }
+  // B[kk][n] = K[p][32 s - h + kk - n]: lane (n = m, kk = 8 kq4 + e) needs extended
+  // entries x0 + e with x0 = 32 s + 8 kq4 + 15 - m; residue r = x0 % 8 = (15 - m) % 8.
+  const int r = (15 - m) & 7;
+  const __bf16* bbase = bcopy + r * CL + 8 * kq4 + 15 - m + ((8 - r) & 7);
   f32x4 acc[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int p = -h; p <= h; ++p) {
-    const int ap = p < 0 ? -p : p;
-    // B[kk][n] = T_p[c0 + kk][j0 + n] = K[p][c0 + kk - j0 - n], c0 - j0 = 32 s - h;
-    // lane (n = m, kk = 8 kq + e) reads extended index 32 s + 8 kq + e - m + 15.
-    const float* krow = kx + ap * E + 15 + 8 * kq - m;
-    const int up = p * pitch;
-    for (int s = 0; s < S; ++s) {
-      bf16x8 bv;
+  const int total = (2 * h + 1) * S;
+  int p = -h, s = 0;
+  bf16x8 bn = *reinterpret_cast<const bf16x8*>(bbase + h * 8 * CL);
+  bf16x8 an[TPW];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) bv[e] = (__bf16)krow[32 * s + e];
+  for (int q = 0; q < TPW; ++q) an[q] = *reinterpret_cast<const bf16x8*>(abase[q] - h * pitch);
+  for (int it = 0; it < total; ++it) {
+    const bf16x8 bc = bn;
+    bf16x8 ac[TPW];
 #pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        if (active[q]) {
-          const bf16x8 av = *reinterpret_cast<const bf16x8*>(tile + rowbase[q] + up + colbase[q] + 32 * s);
-          acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
-        }
-      }
+    for (int q = 0; q < TPW; ++q) ac[q] = an[q];
+    if (++s == S) {
+      s = 0;
+      ++p;
     }
-  }
-
-  float* dst = out + ((size_t)b * g.Nk + k) * plane;
+    if (it + 1 < total) {
+      const int ap = p < 0 ? -p : p;
+      bn = *reinterpret_cast<const bf16x8*>(bbase + ap * 8 * CL + 32 * s);
+      const int oa = p * pitch + 32 * s;
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) {
-    if (!active[q]) continue;
-    int t = wave + 4 * q;
-    int ti = t / rs.TJ, tj = t - ti * rs.TJ;
-    int j = J0 + MT * tj + m;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int i = I0 + MT * ti + 4 * kq + r;
-      if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[q][r];
+      for (int q = 0; q < TPW; ++q) an[q] = *reinterpret_cast<const bf16x8*>(abase[q] + oa);
     }
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[q], bc, acc[q], 0, 0, 0);
   }
+  store_tiles<TPW>(g, rs, NW, wave, I0, J0, lane, acc, active, out + ((size_t)b * g.Nk + k) * plane);
 }
 
-template <int TPW>
-static hipError_t launch_bf16_tpw(const Geo<float>& g, const RegionShape& rs, const BF16Shape& bs, int nb,
-                                  const float* z, const float* in, float* out, hipStream_t s) {
-  size_t lds = bf16_lds(g, bs);
+// ------------------------------------------------------------------ launch
+
+template <int NW, int TPW, typename Shape, typename Kern>
+static hipError_t launch_cfg(Kern kern, const Geo<float>& g, const RegionShape& rs, const Shape& sh, size_t lds,
+                             int nb, const float* z, const float* in, float* out, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_conv_mfma_bf16<TPW>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  if (lds > LDS_MAX) return hipErrorInvalidConfiguration;
   dim3 grid(rs.regions_i * rs.regions_j, g.Nk, nb);
-  hipLaunchKernelGGL(k_conv_mfma_bf16<TPW>, grid, dim3(256), lds, s, g, rs, bs, z, in, out);
+  hipLaunchKernelGGL(kern, grid, dim3(64 * NW), lds, s, g, rs, sh, z, in, out);
   return hipGetLastError();
+}
+
+// Wavefronts x tiles per wavefront for a region of `tiles` tiles.
+#define PDRT_CONV_DISPATCH(KERN, SHAPE)                                                          \
+  int tiles = rs.TI * rs.TJ;                                                                     \
+  if (tiles <= 4) return launch_cfg<4, 1>(KERN<4, 1>, g, rs, SHAPE, lds, nb, z, in, out, s);     \
+  if (tiles <= 8) return launch_cfg<8, 1>(KERN<8, 1>, g, rs, SHAPE, lds, nb, z, in, out, s);     \
+  if (tiles <= 16) return launch_cfg<8, 2>(KERN<8, 2>, g, rs, SHAPE, lds, nb, z, in, out, s);    \
+  if (tiles <= 24) return launch_cfg<8, 3>(KERN<8, 3>, g, rs, SHAPE, lds, nb, z, in, out, s);    \
+  return launch_cfg<12, 3>(KERN<12, 3>, g, rs, SHAPE, lds, nb, z, in, out, s);
+
+hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
+                                hipStream_t s) {
+  RegionShape rs;
+  F32Shape fs;
+  size_t lds = 0;
+  for (int rmax = RMAX; rmax >= 1; --rmax) {  // the largest region whose LDS image fits
+    rs = region_shape(g.Nu, g.Nv, rmax);
+    fs = f32_shape(g.h, rs);
+    lds = f32_lds(g.h, fs);
+    if (lds <= LDS_MAX) break;
+  }
+  PDRT_CONV_DISPATCH(k_conv_mfma_f32, fs)
 }
 
 hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                  hipStream_t s) {
   RegionShape rs;
   BF16Shape bs;
+  size_t lds = 0;
   for (int rmax = RMAX; rmax >= 1; --rmax) {
     rs = region_shape(g.Nu, g.Nv, rmax);
     bs = bf16_shape(g.h, rs);
-    if (bf16_lds(g, bs) <= 160 * 1024) break;
+    lds = bf16_lds(g.h, bs);
+    if (lds <= LDS_MAX) break;
   }
-  int tpw = (rs.TI * rs.TJ + 3) / 4;
-  if (tpw <= 1) return launch_bf16_tpw<1>(g, rs, bs, nb, z, in, out, s);
-  if (tpw <= 2) return launch_bf16_tpw<2>(g, rs, bs, nb, z, in, out, s);
-  if (tpw <= 3) return launch_bf16_tpw<3>(g, rs, bs, nb, z, in, out, s);
-  if (tpw <= 4) return launch_bf16_tpw<4>(g, rs, bs, nb, z, in, out, s);
-  if (tpw <= 6) return launch_bf16_tpw<6>(g, rs, bs, nb, z, in, out, s);
-  return launch_bf16_tpw<9>(g, rs, bs, nb, z, in, out, s);
+  PDRT_CONV_DISPATCH(k_conv_mfma_bf16, bs)
 }
 
 }  // namespace pdrt

@@ -1,7 +1,7 @@
 // dose_bwd.hip — reverse-mode kernels of the dose path and the projection layer.
 //
 // Given g = dL/dD the backward of one control-point batch runs
-//   k_scatter     Ghat_b = (trilinear back-projection)^T g        (adjoint of §2.2.7)
+//   k_backproject_adj  Ghat_b = (trilinear back-projection)^T g   (adjoint of §2.2.7)
 //   conv          H = K_k (*) Ghat_k (the taps are point symmetric, so the
 //                 transposed convolution is the convolution itself; §2.2.6)
 //   k_march<ADJ>  A = sum_k H_k (SAD/d_k)^2 DD(W_k), W recomputed    (§2.2.3-2.2.4)
@@ -24,49 +24,90 @@ __device__ __forceinline__ T overlap_db(T x, T a, T b, T D, T invD) {
   return (hi - lo > T(0) && b < x + T(0.5) * D) ? invD : T(0);
 }
 
-// ------------------------------------------------------------------ scatter
+// ------------------------------------------------------------------ adjoint of the back-projection
 
+// Ghat_b = G_b^T g, where G_b is the trilinear back-projection of control point b
+// (§2.2.7), computed in gather form: one wavefront per beam-frame column (k, i),
+// lanes along v.  A voxel contributes to node (k, i, j) iff its continuous indices
+// fall in [k-1, k+1) x [i-1, i+1) x [j-1, j+1); (kappa, iota) depend only on the
+// voxel's (x, y) column, jota is increasing in z.  The wavefront bounds the
+// candidate voxel columns by the rotated box around the trapezoid of beam-frame
+// points with kappa, iota in range, evaluates each candidate with the forward's
+// own index arithmetic, and for each lane walks the few z values whose jota lies
+// in [j-1, j+1).  No atomics: every node is written once, summation order fixed.
+// g_t is the dose gradient in z-fastest order [ny][nx][nz].
 template <typename T>
-__global__ void __launch_bounds__(256) k_scatter(Geo<T> g, int nb, const T* __restrict__ frame,
-                                                 const T* __restrict__ grad, T* __restrict__ Ghat) {
-  int z = blockIdx.x * 64 + (threadIdx.x & 63);
-  int x = blockIdx.y * 4 + (threadIdx.x >> 6);
-  int y = blockIdx.z;
-  if (z >= g.nz || x >= g.nx) return;
-  T gv = grad[((size_t)z * g.ny + y) * g.nx + x];
-  if (gv == T(0)) return;
-  T tx = g.rel_ox + T(x) * g.sx, ty = g.rel_oy + T(y) * g.sy, tz = g.rel_oz + T(z) * g.sz;
-  const int plane = g.Nu * g.Nv;
-  for (int b = 0; b < nb; ++b) {
-    T sn = frame[2 * b], cs = frame[2 * b + 1];
-    FanIdx<T> f = voxel_to_fan(g, sn, cs, tx, ty, tz);
-    T fk = dfloor(f.k), fi = dfloor(f.i), fj = dfloor(f.j);
-    int k0 = (int)fk, i0 = (int)fi, j0 = (int)fj;
-    if (k0 < -1 || k0 >= g.Nk || i0 < -1 || i0 >= g.Nu || j0 < -1 || j0 >= g.Nv) continue;
-    T wk = f.k - fk, wi = f.i - fi, wj = f.j - fj;
-    T* base = Ghat + (size_t)b * g.Nk * plane;
+__global__ void __launch_bounds__(256) k_backproject_adj(Geo<T> g, const T* __restrict__ frame,
+                                                         const T* __restrict__ g_t, T* __restrict__ Ghat) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int col = blockIdx.x * 4 + wave;
+  const int b = blockIdx.y;
+  if (col >= g.Nk * g.Nu) return;
+  const int k = col / g.Nu, i = col - k * g.Nu;
+  const T sn = frame[2 * b], cs = frame[2 * b + 1];
+  // beam-frame box: e = d - SAD in [e_{k-1}, e_{k+1}], lateral l = u d / SAD
+  const T e_lo = g.e0 + T(k - 1) * g.dstep, e_hi = g.e0 + T(k + 1) * g.dstep;
+  const T u_lo = (T(i - 1) - g.cu) * g.lat, u_hi = (T(i + 1) - g.cu) * g.lat;
+  const T s_lo = T(1) + e_lo * g.inv_sad, s_hi = T(1) + e_hi * g.inv_sad;
+  const T l_lo = fmin(u_lo * s_lo, u_lo * s_hi), l_hi = fmax(u_hi * s_lo, u_hi * s_hi);
+  T xmin = T(1e30), xmax = T(-1e30), ymin = T(1e30), ymax = T(-1e30);
 #pragma unroll
-    for (int dk = 0; dk < 2; ++dk) {
-      int kk = k0 + dk;
-      if (kk < 0 || kk >= g.Nk) continue;
-      T wkk = dk ? wk : T(1) - wk;
-#pragma unroll
-      for (int di = 0; di < 2; ++di) {
-        int ii = i0 + di;
-        if (ii < 0 || ii >= g.Nu) continue;
-        T w2 = wkk * (di ? wi : T(1) - wi) * gv;
-        T* colp = base + (size_t)kk * plane + (size_t)ii * g.Nv;
-        if (j0 >= 0) atomicAdd(colp + j0, w2 * (T(1) - wj));
-        if (j0 + 1 < g.Nv) atomicAdd(colp + j0 + 1, w2 * wj);
+  for (int c = 0; c < 4; ++c) {
+    T e = (c & 1) ? e_hi : e_lo, l = (c & 2) ? l_hi : l_lo;
+    T X = (-sn * e + cs * l - g.rel_ox) * g.inv_sx;
+    T Y = (cs * e + sn * l - g.rel_oy) * g.inv_sy;
+    xmin = fmin(xmin, X);
+    xmax = fmax(xmax, X);
+    ymin = fmin(ymin, Y);
+    ymax = fmax(ymax, Y);
+  }
+  T* out = Ghat + ((size_t)b * g.Nk + k) * ((size_t)g.Nu * g.Nv) + (size_t)i * g.Nv;
+  if (xmax < T(-1) || ymax < T(-1) || xmin > T(g.nx) || ymin > T(g.ny)) {
+    for (int j = lane; j < g.Nv; j += 64) out[j] = T(0);
+    return;
+  }
+  const int x0 = max(0, (int)dfloor(xmin) - 1), x1 = min(g.nx - 1, (int)dfloor(xmax) + 2);
+  const int y0 = max(0, (int)dfloor(ymin) - 1), y1 = min(g.ny - 1, (int)dfloor(ymax) + 2);
+  for (int jc = 0; jc < g.Nv; jc += 64) {
+    const int j = jc + lane;
+    T acc = T(0);
+    for (int y = y0; y <= y1; ++y) {
+      const T ty = g.rel_oy + T(y) * g.sy;
+      for (int x = x0; x <= x1; ++x) {
+        const T tx = g.rel_ox + T(x) * g.sx;
+        FanIdx<T> f = voxel_to_fan(g, sn, cs, tx, ty, T(0));
+        const T fk = dfloor(f.k), fi = dfloor(f.i);
+        const int k0 = (int)fk, i0 = (int)fi;
+        if ((k0 != k && k0 != k - 1) || (i0 != i && i0 != i - 1)) continue;
+        const T wk = f.k - fk, wi = f.i - fi;
+        const T w2 = (k0 == k ? T(1) - wk : wk) * (i0 == i ? T(1) - wi : wi);
+        const T q = T(1) / (T(1) + (-sn * tx + cs * ty) * g.inv_sad);  // SAD / d, as in voxel_to_fan
+        // tz range with jota in [j-1, j+1), widened by one voxel each side
+        const T za = ((T(j - 1) - g.cv) * g.lat / q - g.rel_oz) * g.inv_sz;
+        const T zb = ((T(j + 1) - g.cv) * g.lat / q - g.rel_oz) * g.inv_sz;
+        const int z0 = max(0, (int)dfloor(za) - 1), z1 = min(g.nz - 1, (int)dfloor(zb) + 1);
+        const T* gcol = g_t + ((size_t)y * g.nx + x) * g.nz;
+        T part = T(0);
+        for (int z = z0; z <= z1; ++z) {
+          const T tz = g.rel_oz + T(z) * g.sz;
+          const T jj = tz * q * g.inv_lat + g.cv;
+          const T fj = dfloor(jj);
+          const int j0 = (int)fj;
+          const T wj = jj - fj;
+          const T w = j0 == j ? T(1) - wj : (j0 == j - 1 ? wj : T(0));
+          part += w * gcol[z];
+        }
+        acc += w2 * part;
       }
     }
+    if (j < g.Nv) out[j] = acc;
   }
 }
 
 template <typename T>
-hipError_t launch_scatter(const Geo<T>& g, int nb, const T* frame, const T* grad, T* Ghat, hipStream_t s) {
-  dim3 grid((g.nz + 63) / 64, (g.nx + 3) / 4, g.ny);
-  hipLaunchKernelGGL(k_scatter<T>, grid, dim3(256), 0, s, g, nb, frame, grad, Ghat);
+hipError_t launch_backproject_adj(const Geo<T>& g, int nb, const T* frame, const T* g_t, T* Ghat, hipStream_t s) {
+  dim3 grid((g.Nk * g.Nu + 3) / 4, nb);
+  hipLaunchKernelGGL(k_backproject_adj<T>, grid, dim3(256), 0, s, g, frame, g_t, Ghat);
   return hipGetLastError();
 }
 
@@ -261,9 +302,10 @@ hipError_t launch_project_bwd(int n_cp, int L, const float* lv, const float* jw,
   return hipGetLastError();
 }
 
-template hipError_t launch_scatter<float>(const Geo<float>&, int, const float*, const float*, float*, hipStream_t);
-template hipError_t launch_scatter<double>(const Geo<double>&, int, const double*, const double*, double*,
-                                           hipStream_t);
+template hipError_t launch_backproject_adj<float>(const Geo<float>&, int, const float*, const float*, float*,
+                                                  hipStream_t);
+template hipError_t launch_backproject_adj<double>(const Geo<double>&, int, const double*, const double*, double*,
+                                                   hipStream_t);
 template hipError_t launch_param_grad<float>(const Geo<float>&, int, const float*, const float*, const float*,
                                              const float*, float*, float*, float*, hipStream_t);
 template hipError_t launch_param_grad<double>(const Geo<double>&, int, const double*, const double*, const double*,

@@ -418,22 +418,6 @@ hipError_t launch_gather(const Geo<T>& g, int nb, int first, int last, const T* 
   return hipGetLastError();
 }
 
-template <typename T>
-__global__ void k_fill(T* p, size_t n, T v) {
-  size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; q < n; q += stride) p[q] = v;
-}
-
-template <typename T>
-hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
-  return hipGetLastError();
-}
-
 #define PDRT_INST(T)                                                                                         \
   template hipError_t launch_frame<T>(const Geo<T>&, const T*, int, T*, hipStream_t);                        \
   template hipError_t launch_transpose_rho<T>(const Geo<T>&, const T*, T*, hipStream_t);                     \
@@ -445,8 +429,7 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
                                           T*, hipStream_t);                                                  \
   template hipError_t launch_conv_direct<T>(const Geo<T>&, int, const T*, const T*, T*, hipStream_t);        \
   template hipError_t launch_gather<T>(const Geo<T>&, int, int, int, const T*, const T*, const T*, T*, T*,    \
-                                       hipStream_t);                                                         \
-  template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);
+                                       hipStream_t);
 
 PDRT_INST(float)
 PDRT_INST(double)

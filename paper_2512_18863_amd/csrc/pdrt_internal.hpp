@@ -50,12 +50,6 @@ struct Layout {
   int batch;
 };
 
-template <typename T>
-struct Launch {
-  const Geo<T>* g;
-  hipStream_t stream;
-};
-
 // --- launchers (defined in the kernel translation units) -------------------
 template <typename T>
 hipError_t launch_frame(const Geo<T>& g, const T* gantry_deg, int n_cp, T* frame, hipStream_t s);
@@ -83,9 +77,7 @@ template <typename T>
 hipError_t launch_gather(const Geo<T>& g, int nb, int first, int last, const T* frame, const T* mu,
                          const T* Dfan, T* dose, T* comp, hipStream_t s);
 template <typename T>
-hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s);
-template <typename T>
-hipError_t launch_scatter(const Geo<T>& g, int nb, const T* frame, const T* grad, T* Ghat, hipStream_t s);
+hipError_t launch_backproject_adj(const Geo<T>& g, int nb, const T* frame, const T* g_t, T* Ghat, hipStream_t s);
 template <typename T>
 hipError_t launch_param_grad(const Geo<T>& g, int nb, const T* leaves, const T* jaws, const T* mu, const T* A,
                              T* gleaves, T* gjaws, T* gmu, hipStream_t s);

@@ -1,0 +1,54 @@
+"""BF16 convolution variant: error against the FP64 oracle, stated per result.
+
+The BF16 path rounds the primary fluence and the kernel taps to BF16 (8-bit
+significand, relative rounding <= 2^-9) and accumulates in FP32; its bar is the
+1 %/1 mm global gamma pass rate >= 99.5 % (10 % threshold) against the oracle,
+with the maximum dose error reported.  A bound derived from the arithmetic:
+each product carries <= 2 * 2^-9 relative error, so the dose error stays below
+2^-8 (0.4 %) of the local dose; the test asserts that bound on max dose.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2512_18863_amd import gamma, inputs
+from tests.test_gpu_parity import _say, gpu_dose, oracle_dose, subset
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("name,mk,idx", [
+    ("C2", inputs.config_c2, np.arange(0, 180, 12)),
+    ("C4-bench", lambda: inputs.config_c4_plan(2000, bench=True), np.array([5, 50, 95, 140])),
+])
+def test_bf16_error_vs_oracle(name, mk, idx):
+    c = subset(mk(), idx)
+    ref, _, _ = oracle_dose(c)
+    got, _ = gpu_dose(c, conv="bf16")
+    err = float(np.abs(got - ref).max() / ref.max())
+    gp = gamma.pass_rate(ref, got, c.spacing, 1.0, 1.0)
+    _say("%s bf16 (%d CPs): max|dD|/maxD = %.3e, gamma(1%%/1mm) = %.4f %%" % (name, len(idx), err, 100 * gp))
+    assert err <= 2.0 ** -8
+    assert gp >= 0.995
+
+
+def test_bf16_gradients_close_to_fp32():
+    _say("C1 bf16 gradients vs fp32 gradients (12 CPs)")
+    from paper_2512_18863_amd.engine import DoseEngine
+    from tests.test_gpu_parity import _t
+    c = subset(inputs.config_c1(), np.arange(0, 90, 8))
+    w = _t(c.loss_w)
+    out = {}
+    for conv in ("fp32", "bf16"):
+        eng = DoseEngine(c, conv=conv)
+        out[conv] = [t.cpu().numpy() for t in eng.backward(_t(c.leaves), _t(c.jaws), _t(c.mu), w)]
+    for name, a, b in zip(("leaves", "jaws", "mu"), out["fp32"], out["bf16"]):
+        e = np.abs(a - b).max() / np.abs(a).max()
+        _say("%s: bf16 vs fp32 max|dg|/max|g| = %.3e" % (name, e))
+        assert e <= 2.0 ** -7

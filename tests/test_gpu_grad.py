@@ -170,3 +170,15 @@ def test_autograd_function_matches_backward():
     assert torch.equal(lv.grad, gl) or torch.allclose(lv.grad, gl, rtol=1e-5, atol=1e-6 * gl.abs().max())
     assert torch.allclose(mu.grad, gm, rtol=1e-5)
     assert torch.allclose(jw.grad, gj, rtol=1e-5, atol=1e-6 * gj.abs().max())
+
+
+def test_backward_is_deterministic():
+    _say("C1 backward twice, bitwise equal (no atomics)")
+    from paper_2512_18863_amd.engine import DoseEngine
+    c = subset(inputs.config_c1(), np.arange(0, 90, 5))
+    eng = DoseEngine(c)
+    w = _t(c.loss_w)
+    a = [t.cpu().numpy() for t in eng.backward(_t(c.leaves), _t(c.jaws), _t(c.mu), w)]
+    b = [t.cpu().numpy() for t in eng.backward(_t(c.leaves), _t(c.jaws), _t(c.mu), w)]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
