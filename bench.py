@@ -108,6 +108,27 @@ def cpu_baseline(case, w, budget_s=12.0, max_cp=24):
                       "%.1f s" % (done, case.n_cp, dt)}
 
 
+def counter_run(case, w):
+    """A copy kernel of known size (1 GiB read + 1 GiB written) followed by one
+    FP32 forward and one backward of the benchmark plan."""
+    import torch
+    from paper_2512_18863_amd import engine as E
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    eng = E.DoseEngine(case, conv="fp32")
+    dev = eng.device
+    lv = torch.tensor(case.leaves, dtype=torch.float32, device=dev)
+    jw = torch.tensor(case.jaws, dtype=torch.float32, device=dev)
+    mu = torch.tensor(case.mu, dtype=torch.float32, device=dev)
+    eng.forward(lv, jw, mu)
+    eng.backward(lv, jw, mu, torch.tensor(w, dtype=torch.float32, device=dev))
+    torch.cuda.synchronize()
+    print("counter run done", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +136,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="one copy of 1 GiB (the counter calibration) then one FP32 forward + backward; "
+                         "for rocprofv3 --pmc runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the dose path is built and timed on a single MI355X; "
@@ -127,6 +151,9 @@ def main():
 
     case = inputs.config_c4_plan(2000, bench=True)
     w = np.random.default_rng(4001).uniform(0.0, 1.0, size=case.shape)
+    if args.counter_run:
+        counter_run(case, w)
+        return
     n_cp = case.n_cp
     print("[bench] fp32 fwd+bwd, %d CPs, 128^3, n=61: warmup %d, steps %d" % (n_cp, args.warmup, args.steps),
           file=sys.stderr, flush=True)

@@ -193,6 +193,77 @@ typedef struct {
 int pdrt_profile_begin(int32_t max_launches);
 int pdrt_profile_end(pdrt_kernel_time* out, int32_t max_entries, int32_t* n_entries);
 
+/* ------------------------------------------------------------------------
+ * Primitives of the small 3-D convolutional network that maps a small-kernel
+ * dose plus the density to a large-kernel dose (a learned correction of the
+ * kernel-size effect of Table 5; "smaller kernel sizes first", §4.1).
+ * Tensors are channels-last [D][H][W][C].  "bf16" pointers are device arrays of
+ * IEEE bfloat16 (2 bytes), 16-byte aligned; weights are FP32 masters
+ * w[cout][27][cin] (tap = 9 kd + 3 kh + kw over offsets -1..1) converted by
+ * pdrt_conv3d_prepare_weights into the two operand layouts wt (forward,
+ * [cout][pdrt_conv3d_kpad(cin)]) and wd (data gradient, [cin][pdrt_conv3d_kpad(cout)]).
+ * All 3 x 3 x 3 convolutions use "same" zero padding and stride 1, BF16
+ * operands and FP32 accumulation.  Same error conventions as above. */
+typedef struct {
+  int32_t D, H, W;
+} pdrt_vol;
+
+/* K extent of the operand layouts: 27 cin rounded up to a multiple of 32. */
+int32_t pdrt_conv3d_kpad(int32_t cin);
+int pdrt_conv3d_prepare_weights(int32_t cout, int32_t cin, const float* w, void* wt, void* wd, void* stream);
+/* y = act(bias + conv(x1 ++ x2, w)); x1 has c1 channels, x2 (may be NULL when
+ * c2 == 0) c2 channels, read as their channel concatenation; act = ReLU if relu.
+ * c1, c2 multiples of 8 with c1 + c2 a multiple of 16; cout 16, 32 or 64. */
+int pdrt_conv3d_forward(const pdrt_vol* vol, int32_t c1, int32_t c2, const void* x1, const void* x2, int32_t cout,
+                        const void* wt, const float* bias, int32_t relu, void* y, void* stream);
+/* dx1 ++ dx2 = conv^T(dy * [y_act > 0], w) (y_act NULL: no activation); c1 + c2 in
+ * {16, 32, 48, 64, 96}. */
+int pdrt_conv3d_backward_data(const pdrt_vol* vol, int32_t cout, const void* dy, const void* y_act, int32_t c1,
+                              int32_t c2, const void* wd, void* dx1, void* dx2, void* stream);
+/* dw[cout][27][c1 + c2] and db[cout] = sums over positions of the masked dy (FP32),
+ * split over nsplit position chunks whose partial sums (ws) are added in a fixed
+ * order; cout <= 64. */
+size_t pdrt_conv3d_wgrad_ws_bytes(int32_t cout, int32_t cin, int32_t nsplit);
+int pdrt_conv3d_backward_weight(const pdrt_vol* vol, int32_t c1, int32_t c2, const void* x1, const void* x2,
+                                int32_t cout, const void* dy, const void* y_act, int32_t nsplit, float* ws,
+                                size_t ws_bytes, float* dw, float* db, void* stream);
+/* x[p][16] = (dose[p] * scale[0], rho[p], 0, ..., 0) as bf16; n = D H W. */
+int pdrt_net_input(int32_t n, const float* dose, const float* scale, const float* rho, void* x, void* stream);
+/* Gradient w.r.t. the dose fed to pdrt_net_input and pdrt_net_head:
+ * ddose[p] = scale[0] (gp[p] + dx0[p][0]). */
+int pdrt_net_input_backward(int32_t n, const void* dx0, const float* gp, const float* scale, float* ddose,
+                            void* stream);
+/* scale[0] = 1 / max(dose) (1 if the dose is zero). */
+int pdrt_net_scale(int32_t n, const float* dose, float* scale, void* stream);
+/* out = a * scale[0] (inverse == 0) or a / scale[0] (inverse != 0); out may alias a. */
+int pdrt_scale_by(int32_t n, const float* a, const float* scale, int32_t inverse, float* out, void* stream);
+/* out = a + b over n bf16 elements (out may alias a or b). */
+int pdrt_add_bf16(size_t n, const void* a, const void* b, void* out, void* stream);
+/* 2 x 2 x 2 average pooling of the fine volume `fine` (even dims) and its
+ * backward (backward != 0: x = gradient w.r.t. the pooled output, y = gradient
+ * w.r.t. the fine input). */
+int pdrt_pool2(const pdrt_vol* fine, int32_t c, const void* x, void* y, int32_t backward, void* stream);
+/* Nearest-neighbour x2 upsampling to `fine` and its backward. */
+int pdrt_upsample2(const pdrt_vol* fine, int32_t c, const void* x, void* y, int32_t backward, void* stream);
+/* Output head (FP32): pred = dose * scale + hb[0] + hw[0] . x, resid = hb[1] + hw[1] . x. */
+int pdrt_net_head(int32_t n, int32_t c, const void* x, const float* hw, const float* hb, const float* dose,
+                  const float* scale, float* pred, float* resid, void* stream);
+/* Backward of the head: dx (bf16) and dhead = (dhw[2][c], dhb[2]); gr may be NULL. */
+size_t pdrt_net_head_ws_bytes(int32_t n, int32_t c);
+int pdrt_net_head_backward(int32_t n, int32_t c, const void* x, const float* hw, const float* gp, const float* gr,
+                           void* dx, float* ws, size_t ws_bytes, float* dhead, void* stream);
+/* Training loss L = inv_count sum mask [(pred - t s)^2 + lam (resid - |pred - t s|)^2]
+ * (t = target, s = tscale[0]) and its gradients gp, gr; loss[0] = L. */
+size_t pdrt_net_loss_ws_bytes(int32_t n);
+int pdrt_net_train_loss(int32_t n, const float* pred, const float* resid, const float* target, const float* tscale,
+                        const float* mask, float inv_count, float lam, float* gp, float* gr, float* ws,
+                        size_t ws_bytes, float* loss, void* stream);
+/* stats[0] = max pred, stats[1] = max resid over pred >= frac * max pred. */
+int pdrt_net_fallback_stats(int32_t n, const float* pred, const float* resid, float frac, float* stats, void* stream);
+/* One Adam update of n FP32 parameters (step t >= 1, bias-corrected). */
+int pdrt_adam_step(size_t n, float* w, const float* g, float* m, float* v, float lr, float beta1, float beta2,
+                   float eps, int32_t t, void* stream);
+
 /* Human-readable text of a status code (static storage). */
 const char* pdrt_status_string(int status);
 

@@ -36,7 +36,7 @@ __device__ __forceinline__ T overlap_db(T x, T a, T b, T D, T invD) {
 // own index arithmetic, and for each lane walks the few z values whose jota lies
 // in [j-1, j+1).  No atomics: every node is written once, summation order fixed.
 // g_t is the dose gradient in z-fastest order [ny][nx][nz].
-template <typename T>
+template <typename T, int NCH>
 __global__ void __launch_bounds__(256) k_backproject_adj(Geo<T> g, const T* __restrict__ frame,
                                                          const T* __restrict__ g_t, T* __restrict__ Ghat) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -62,31 +62,34 @@ __global__ void __launch_bounds__(256) k_backproject_adj(Geo<T> g, const T* __re
     ymax = fmax(ymax, Y);
   }
   T* out = Ghat + ((size_t)b * g.Nk + k) * ((size_t)g.Nu * g.Nv) + (size_t)i * g.Nv;
-  if (xmax < T(-1) || ymax < T(-1) || xmin > T(g.nx) || ymin > T(g.ny)) {
-    for (int j = lane; j < g.Nv; j += 64) out[j] = T(0);
-    return;
-  }
-  const int x0 = max(0, (int)dfloor(xmin) - 1), x1 = min(g.nx - 1, (int)dfloor(xmax) + 2);
-  const int y0 = max(0, (int)dfloor(ymin) - 1), y1 = min(g.ny - 1, (int)dfloor(ymax) + 2);
-  for (int jc = 0; jc < g.Nv; jc += 64) {
-    const int j = jc + lane;
-    T acc = T(0);
-    for (int y = y0; y <= y1; ++y) {
-      const T ty = g.rel_oy + T(y) * g.sy;
-      for (int x = x0; x <= x1; ++x) {
-        const T tx = g.rel_ox + T(x) * g.sx;
-        FanIdx<T> f = voxel_to_fan(g, sn, cs, tx, ty, T(0));
-        const T fk = dfloor(f.k), fi = dfloor(f.i);
-        const int k0 = (int)fk, i0 = (int)fi;
-        if ((k0 != k && k0 != k - 1) || (i0 != i && i0 != i - 1)) continue;
-        const T wk = f.k - fk, wi = f.i - fi;
-        const T w2 = (k0 == k ? T(1) - wk : wk) * (i0 == i ? T(1) - wi : wi);
-        const T q = T(1) / (T(1) + (-sn * tx + cs * ty) * g.inv_sad);  // SAD / d, as in voxel_to_fan
-        // tz range with jota in [j-1, j+1), widened by one voxel each side
-        const T za = ((T(j - 1) - g.cv) * g.lat / q - g.rel_oz) * g.inv_sz;
-        const T zb = ((T(j + 1) - g.cv) * g.lat / q - g.rel_oz) * g.inv_sz;
+  // candidate voxel columns: centres inside the box, widened by a rounding margin
+  const T eps = T(1e-3);
+  const int x0 = max(0, (int)dfloor(xmin - eps) + 1), x1 = min(g.nx - 1, (int)dfloor(xmax + eps));
+  const int y0 = max(0, (int)dfloor(ymin - eps) + 1), y1 = min(g.ny - 1, (int)dfloor(ymax + eps));
+  T acc[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc[c] = T(0);
+  for (int y = y0; y <= y1; ++y) {
+    const T ty = g.rel_oy + T(y) * g.sy;
+    for (int x = x0; x <= x1; ++x) {
+      const T tx = g.rel_ox + T(x) * g.sx;
+      FanIdx<T> f = voxel_to_fan(g, sn, cs, tx, ty, T(0));
+      const T fk = dfloor(f.k), fi = dfloor(f.i);
+      const int k0 = (int)fk, i0 = (int)fi;
+      if ((k0 != k && k0 != k - 1) || (i0 != i && i0 != i - 1)) continue;
+      const T wk = f.k - fk, wi = f.i - fi;
+      const T w2 = (k0 == k ? T(1) - wk : wk) * (i0 == i ? T(1) - wi : wi);
+      const T q = T(1) / (T(1) + (-sn * tx + cs * ty) * g.inv_sad);  // SAD / d, as in voxel_to_fan
+      const T dq = T(1) + (-sn * tx + cs * ty) * g.inv_sad;          // d / SAD
+      const T* gcol = g_t + ((size_t)y * g.nx + x) * g.nz;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int j = 64 * c + lane;
+        if (64 * c >= g.Nv) break;
+        // z with jota in [j-1, j+1), widened by one voxel each side
+        const T za = ((T(j - 1) - g.cv) * g.lat * dq - g.rel_oz) * g.inv_sz;
+        const T zb = ((T(j + 1) - g.cv) * g.lat * dq - g.rel_oz) * g.inv_sz;
         const int z0 = max(0, (int)dfloor(za) - 1), z1 = min(g.nz - 1, (int)dfloor(zb) + 1);
-        const T* gcol = g_t + ((size_t)y * g.nx + x) * g.nz;
         T part = T(0);
         for (int z = z0; z <= z1; ++z) {
           const T tz = g.rel_oz + T(z) * g.sz;
@@ -97,17 +100,33 @@ __global__ void __launch_bounds__(256) k_backproject_adj(Geo<T> g, const T* __re
           const T w = j0 == j ? T(1) - wj : (j0 == j - 1 ? wj : T(0));
           part += w * gcol[z];
         }
-        acc += w2 * part;
+        acc[c] += w2 * part;
       }
     }
-    if (j < g.Nv) out[j] = acc;
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int j = 64 * c + lane;
+    if (j < g.Nv) out[j] = acc[c];
   }
 }
 
 template <typename T>
 hipError_t launch_backproject_adj(const Geo<T>& g, int nb, const T* frame, const T* g_t, T* Ghat, hipStream_t s) {
   dim3 grid((g.Nk * g.Nu + 3) / 4, nb);
-  hipLaunchKernelGGL(k_backproject_adj<T>, grid, dim3(256), 0, s, g, frame, g_t, Ghat);
+  int nch = (g.Nv + 63) / 64;
+  if (nch <= 1)
+    hipLaunchKernelGGL((k_backproject_adj<T, 1>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
+  else if (nch <= 2)
+    hipLaunchKernelGGL((k_backproject_adj<T, 2>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
+  else if (nch <= 4)
+    hipLaunchKernelGGL((k_backproject_adj<T, 4>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
+  else if (nch <= 8)
+    hipLaunchKernelGGL((k_backproject_adj<T, 8>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
+  else if (nch <= 16)
+    hipLaunchKernelGGL((k_backproject_adj<T, 16>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
+  else
+    hipLaunchKernelGGL((k_backproject_adj<T, 64>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
   return hipGetLastError();
 }
 

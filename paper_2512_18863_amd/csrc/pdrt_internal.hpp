@@ -89,4 +89,37 @@ hipError_t launch_project_bwd(int n_cp, int L, const float* lv, const float* jw,
                               const float* gl, const float* gj, const float* gm, float* ol, float* oj, float* om,
                               hipStream_t s);
 
+// --- network primitives (net.hip) -------------------------------------------
+struct Vol {
+  int D, H, W;
+};
+hipError_t launch_conv3d_fwd(Vol v, int C1, int C2, const __bf16* X1, const __bf16* X2, int Cout, const __bf16* Wt,
+                             int Kp, const float* bias, int relu, __bf16* Y, hipStream_t s);
+hipError_t launch_conv3d_dgrad(Vol v, int Cout, const __bf16* dY, const __bf16* Yact, int Cin, const __bf16* Wd,
+                               int Kp, int C1, __bf16* dX1, __bf16* dX2, hipStream_t s);
+hipError_t launch_conv3d_wgrad(Vol v, int C1, int C2, const __bf16* X1, const __bf16* X2, int Cout, const __bf16* dY,
+                               const __bf16* Yact, int nsplit, float* part, float* dW, float* db, hipStream_t s);
+hipError_t launch_prep_weights(int Cout, int Cin, int Kpf, int Kpd, const float* W, __bf16* Wt, __bf16* Wd,
+                               hipStream_t s);
+hipError_t launch_net_input(int P, const float* dose, const float* scale, const float* rho, __bf16* X, hipStream_t s);
+hipError_t launch_pool2(Vol v, int C, const __bf16* X, __bf16* Y, int backward, hipStream_t s);
+hipError_t launch_up2(Vol v, int C, const __bf16* X, __bf16* Y, int backward, hipStream_t s);
+hipError_t launch_head(int P, int C, const __bf16* X, const float* hw, const float* hb, const float* dose,
+                       const float* scale, float* pred, float* resid, hipStream_t s);
+hipError_t launch_head_bwd(int P, int C, const __bf16* X, const float* hw, const float* gp, const float* gr,
+                           __bf16* dX, float* part, hipStream_t s);
+hipError_t launch_train_loss(int P, const float* pred, const float* resid, const float* target, const float* tscale,
+                             const float* mask, float inv_count, float lam, float* gp, float* gr, float* part,
+                             hipStream_t s);
+hipError_t launch_reduce_splits(int nsplit, size_t n, const float* part, float* out, hipStream_t s);
+hipError_t launch_fallback_stats(int P, const float* pred, const float* resid, float frac, float* stats,
+                                 hipStream_t s);
+hipError_t launch_inv_max(int P, const float* dose, float* scale, hipStream_t s);
+hipError_t launch_scale_by(int P, const float* a, const float* scale, int inv, float* out, hipStream_t s);
+hipError_t launch_add_bf16(size_t n, const __bf16* a, const __bf16* b, __bf16* out, hipStream_t s);
+hipError_t launch_net_input_bwd(int P, const __bf16* dX0, const float* gp, const float* scale, float* ddose,
+                                hipStream_t s);
+hipError_t launch_adam(size_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+                       float c1, float c2, hipStream_t s);
+
 }  // namespace pdrt

@@ -1,0 +1,190 @@
+"""Network primitives of the learned correction against plain PyTorch FP32 CPU
+references of the same ops (operands rounded to BF16 the way the kernels see
+them).  The kernels store BF16 outputs (relative rounding <= 2^-9) and sum in
+FP32, so each comparison allows 2^-7 of the reference's largest magnitude."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as Fn
+
+from tests.test_gpu_parity import _say
+
+pytestmark = pytest.mark.gpu
+TOL = 2.0 ** -7
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _bf(x):
+    return torch.tensor(x, dtype=torch.float32).to(torch.bfloat16)
+
+
+def _to_ncdhw(x_dhwc):
+    return x_dhwc.permute(3, 0, 1, 2)[None]
+
+
+def _w_torch(w):  # [cout][27][cin] -> [cout][cin][3][3][3]
+    cout, _, cin = w.shape
+    return w.reshape(cout, 3, 3, 3, cin).permute(0, 4, 1, 2, 3)
+
+
+def _close(name, got, ref):
+    scale = ref.abs().max().item()
+    err = (got - ref).abs().max().item() / max(scale, 1e-30)
+    _say("%s: max err / max|ref| = %.3e" % (name, err))
+    assert err <= TOL, name
+
+
+@pytest.mark.parametrize("dims,c1,c2,cout,relu", [
+    ((4, 6, 8), 16, 0, 16, 1), ((6, 5, 7), 16, 0, 32, 1), ((4, 4, 4), 32, 0, 64, 0),
+    ((4, 6, 6), 64, 32, 32, 1), ((5, 4, 6), 32, 16, 16, 1),
+])
+def test_conv3d_forward_backward(dims, c1, c2, cout, relu):
+    from paper_2512_18863_amd.learned import Vol, _lib
+    _say("conv3d %s c1=%d c2=%d cout=%d relu=%d" % (dims, c1, c2, cout, relu))
+    lib = _lib()
+    rng = np.random.default_rng(c1 + 7 * cout)
+    D, H, W = dims
+    cin = c1 + c2
+    x = _bf(rng.normal(size=(D, H, W, cin)))
+    w = rng.normal(0, 0.2, size=(cout, 27, cin)).astype(np.float32)
+    b = rng.normal(0, 0.1, size=cout).astype(np.float32)
+    dy = _bf(rng.normal(size=(D, H, W, cout)))
+    dev = "cuda"
+    s = torch.cuda.current_stream().cuda_stream
+    x1 = x[..., :c1].contiguous().to(dev)
+    x2 = x[..., c1:].contiguous().to(dev) if c2 else None
+    wg = torch.tensor(w, device=dev)
+    bg = torch.tensor(b, device=dev)
+    wt = torch.empty(cout * lib.pdrt_conv3d_kpad(cin), dtype=torch.bfloat16, device=dev)
+    wd = torch.empty(cin * lib.pdrt_conv3d_kpad(cout), dtype=torch.bfloat16, device=dev)
+    assert lib.pdrt_conv3d_prepare_weights(cout, cin, wg.data_ptr(), wt.data_ptr(), wd.data_ptr(), s) == 0
+    y = torch.empty((D, H, W, cout), dtype=torch.bfloat16, device=dev)
+    v = Vol(D, H, W)
+    assert lib.pdrt_conv3d_forward(ctypes.byref(v), c1, c2, x1.data_ptr(), x2.data_ptr() if c2 else None, cout,
+                                   wt.data_ptr(), bg.data_ptr(), relu, y.data_ptr(), s) == 0
+    # reference in FP32 on the CPU with the operands the kernel sees
+    xr = _to_ncdhw(x.float()).requires_grad_()
+    wr = _w_torch(torch.tensor(w).to(torch.bfloat16).float()).requires_grad_()
+    br = torch.tensor(b).requires_grad_()
+    yr = Fn.conv3d(xr, wr, br, padding=1)
+    if relu:
+        yr = torch.relu(yr)
+    _close("forward", _to_ncdhw(y.float().cpu()), yr.detach())
+    # data gradient (through the activation of the kernel's own output)
+    dx1 = torch.empty((D, H, W, c1), dtype=torch.bfloat16, device=dev)
+    dx2 = torch.empty((D, H, W, c2), dtype=torch.bfloat16, device=dev) if c2 else None
+    dyg = dy.to(dev)
+    assert lib.pdrt_conv3d_backward_data(ctypes.byref(v), cout, dyg.data_ptr(), y.data_ptr() if relu else None, c1, c2,
+                                         wd.data_ptr(), dx1.data_ptr(), dx2.data_ptr() if c2 else None, s) == 0
+    # weight gradient
+    nsplit = 3
+    wsb = lib.pdrt_conv3d_wgrad_ws_bytes(cout, cin, nsplit)
+    ws = torch.empty(wsb // 4, dtype=torch.float32, device=dev)
+    dw = torch.empty((cout, 27, cin), dtype=torch.float32, device=dev)
+    db = torch.empty(cout, dtype=torch.float32, device=dev)
+    assert lib.pdrt_conv3d_backward_weight(ctypes.byref(v), c1, c2, x1.data_ptr(), x2.data_ptr() if c2 else None,
+                                           cout, dyg.data_ptr(), y.data_ptr() if relu else None, nsplit,
+                                           ws.data_ptr(), wsb, dw.data_ptr(), db.data_ptr(), s) == 0
+    torch.cuda.synchronize()
+    # the kernel masks with its own (BF16) activation; use the same mask in the reference
+    mask = (_to_ncdhw(y.float().cpu()) > 0).float() if relu else 1.0
+    yl = Fn.conv3d(xr, wr, br, padding=1)
+    yl.backward(_to_ncdhw(dy.float()) * mask)
+    dx = torch.cat([dx1.float().cpu(), dx2.float().cpu()], dim=-1) if c2 else dx1.float().cpu()
+    _close("data grad", _to_ncdhw(dx), xr.grad)
+    _close("weight grad", _w_torch(dw.cpu()), wr.grad)
+    _close("bias grad", db.cpu(), br.grad)
+
+
+def test_pool_upsample_head_loss_adam():
+    from paper_2512_18863_amd.learned import Vol, _lib
+    _say("pool / upsample / head / loss / adam")
+    lib = _lib()
+    dev = "cuda"
+    s = torch.cuda.current_stream().cuda_stream
+    rng = np.random.default_rng(3)
+    D, H, W, C = 4, 6, 8, 16
+    x = _bf(rng.normal(size=(D, H, W, C)))
+    xg = x.to(dev)  # keep a reference while the kernels are in flight
+    v = Vol(D, H, W)
+    y = torch.empty((D // 2, H // 2, W // 2, C), dtype=torch.bfloat16, device=dev)
+    assert lib.pdrt_pool2(ctypes.byref(v), C, xg.data_ptr(), y.data_ptr(), 0, s) == 0
+    ref = Fn.avg_pool3d(_to_ncdhw(x.float()), 2)
+    _close("pool", _to_ncdhw(y.float().cpu()), ref)
+    u = torch.empty((D, H, W, C), dtype=torch.bfloat16, device=dev)
+    assert lib.pdrt_upsample2(ctypes.byref(v), C, y.data_ptr(), u.data_ptr(), 0, s) == 0
+    _close("upsample", _to_ncdhw(u.float().cpu()), Fn.interpolate(_to_ncdhw(y.float().cpu()), scale_factor=2,
+                                                                   mode="nearest"))
+    # backward of pooling and upsampling are the transposes: <A x, y> = <x, A^T y>
+    g = _bf(rng.normal(size=(D // 2, H // 2, W // 2, C))).to(dev)
+    gx = torch.empty((D, H, W, C), dtype=torch.bfloat16, device=dev)
+    assert lib.pdrt_pool2(ctypes.byref(v), C, g.data_ptr(), gx.data_ptr(), 1, s) == 0
+    lhs = (y.float() * g.float()).sum().item()
+    rhs = (xg.float() * gx.float()).sum().item()
+    assert abs(lhs - rhs) <= 1e-2 * max(1.0, abs(lhs))
+    n = 500
+    xh = _bf(rng.normal(size=(n, C))).to(dev)
+    hw = torch.tensor(rng.normal(size=(2, C)), dtype=torch.float32, device=dev)
+    hb = torch.tensor([0.1, -0.2], dtype=torch.float32, device=dev)
+    dose = torch.tensor(rng.uniform(size=n), dtype=torch.float32, device=dev)
+    sc = torch.tensor([2.0], dtype=torch.float32, device=dev)
+    pred = torch.empty(n, dtype=torch.float32, device=dev)
+    resid = torch.empty(n, dtype=torch.float32, device=dev)
+    assert lib.pdrt_net_head(n, C, xh.data_ptr(), hw.data_ptr(), hb.data_ptr(), dose.data_ptr(), sc.data_ptr(),
+                             pred.data_ptr(), resid.data_ptr(), s) == 0
+    ref_p = dose * 2.0 + hb[0] + xh.float() @ hw[0]
+    ref_r = hb[1] + xh.float() @ hw[1]
+    assert torch.allclose(pred, ref_p, rtol=1e-5, atol=1e-5)
+    assert torch.allclose(resid, ref_r, rtol=1e-5, atol=1e-5)
+    # Adam against torch.optim.Adam on the CPU
+    wv = torch.tensor(rng.normal(size=300), dtype=torch.float32)
+    gv = torch.tensor(rng.normal(size=300), dtype=torch.float32)
+    wref = wv.clone().requires_grad_()
+    opt = torch.optim.Adam([wref], lr=1e-2)
+    wgpu, ggpu = wv.clone().to(dev), gv.to(dev)
+    m, vv = torch.zeros_like(wgpu), torch.zeros_like(wgpu)
+    for t in range(1, 4):
+        wref.grad = gv.clone()
+        opt.step()
+        assert lib.pdrt_adam_step(300, wgpu.data_ptr(), ggpu.data_ptr(), m.data_ptr(), vv.data_ptr(), 1e-2, 0.9,
+                                  0.999, 1e-8, t, s) == 0
+    assert torch.allclose(wgpu.cpu(), wref.detach(), rtol=1e-5, atol=1e-6)
+
+
+def test_learned_training_reduces_loss_and_fallback_is_plain():
+    """A few hundred steps on a handful of 64^3 plans reduce the training loss;
+    forced to fall back, the learned path and returns the plain
+    large-kernel dose bit for bit."""
+    from paper_2512_18863_amd import engine as E
+    from paper_2512_18863_amd import inputs, learned
+    _say("learned path: short training on 64^3 plans, forced fallback")
+    import copy
+    plans = []
+    for p in range(4):
+        c = inputs.config_c4_plan(p, n_taps=61)
+        c.hu = c.hu[32:96, 32:96, 32:96].copy()
+        c.origin = inputs._centred_origin(c.hu.shape, c.spacing)
+        c.gantry, c.leaves, c.jaws, c.mu = c.gantry[:20], c.leaves[:20], c.jaws[:20], c.mu[:20]
+        es = E.DoseEngine(c, n_taps=9)
+        el = E.DoseEngine(c, n_taps=61)
+        t = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+        ds = es.forward(t(c.leaves), t(c.jaws), t(c.mu)).reshape(-1).clone()
+        dl = el.forward(t(c.leaves), t(c.jaws), t(c.mu)).reshape(-1).clone()
+        mask = (dl >= 0.05 * dl.max()).float()
+        plans.append((ds, dl, es.rho.reshape(-1).clone(), mask, float(mask.sum())))
+        last = c
+    net = learned.Net3D((64, 64, 64), seed=1)
+    hist = learned.train(net, plans, 120, lr=2e-3, log_every=40, log=_say)
+    assert hist[-1][1] < 0.7 * hist[0][1]
+    ld = learned.LearnedDose(net, last, mode="always")
+    t = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    out = ld.forward(t(last.leaves), t(last.jaws), t(last.mu))
+    plain = E.DoseEngine(last, n_taps=61).forward(t(last.leaves), t(last.jaws), t(last.mu))
+    assert ld.fell_back and torch.equal(out, plain)
