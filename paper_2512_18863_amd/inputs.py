@@ -309,3 +309,41 @@ def structures_c3(case: Case) -> dict:
     rectum = (X ** 2 + (Y - 42.0) ** 2 <= 12.0 ** 2) & (np.abs(Z) <= 50.0) & ~ptv
     bladder = ((X / 40.0) ** 2 + ((Y + 35.0) / 30.0) ** 2 + ((Z - 35.0) / 30.0) ** 2 <= 1.0) & ~ptv
     return {"ptv": ptv, "rectum": rectum, "bladder": bladder}
+
+
+# --------------------------------------------------------------------------- reference conditions
+
+def reference_case(machine: Machine, n_taps: int, spacing: float = 2.0, size_mm: float = 300.0,
+                   field_mm: float = 100.0, depth_mm: float = 100.0, ssd_mm: float = 900.0):
+    """A water cube for gantry 0 (source at y = -SAD, beam along +y) whose entrance
+    face lies at y = -depth_mm, so the surface is at SSD = SAD - depth_mm and the
+    isocentre at the reference depth; one control point, 1 MU, the field set by
+    the jaws to field_mm x field_mm at the isocentre with the leaves retracted
+    10 mm behind them.
+
+    The density is sampled trilinearly with zero outside the grid, so the water
+    edge seen by a ray lies half a voxel before the first voxel centre.  The
+    lateral size is odd so that x = z = 0 are voxel centres; along y the reference
+    point falls between voxels j_ref and j_ref + 1 when depth_mm / spacing is an
+    integer, and its dose is their linear interpolation (weight `w`).
+    Returns (case, (ix, j_ref, iz, w))."""
+    if abs(machine.sad - (ssd_mm + depth_mm)) > 1e-9:
+        raise ValueError("reference depth + SSD must equal the SAD")
+    n = int(round(size_mm / spacing))
+    n += (n + 1) % 2
+    c = (n - 1) // 2
+    hu = np.zeros((n, n, n), dtype=np.float32)
+    oy = -depth_mm + 0.5 * spacing                   # first voxel centre, half a voxel inside the face
+    t = (0.0 - oy) / spacing                         # continuous y index of the isocentre
+    j_ref = int(np.floor(t))
+    w = float(t - j_ref)
+    if not (0 <= j_ref and j_ref + 1 < n):
+        raise ValueError("reference point outside the phantom")
+    origin = (-c * spacing, oy, -c * spacing)
+    half = field_mm / 2.0
+    m = machine
+    leaves = np.stack([np.full(m.n_leaf, -half - 10.0), np.full(m.n_leaf, half + 10.0)])[None]
+    jaws = jaws_square(1, half, half)
+    case = Case("reference", hu, (spacing,) * 3, origin, (0.0, 0.0, 0.0), np.array([0.0]), leaves, jaws,
+                np.array([1.0]), n_taps, (half, half), m)
+    return case, (c, j_ref, c, w)

@@ -1,0 +1,92 @@
+"""Output calibration at reference conditions (§2.4): 10 cm x 10 cm field, 10 cm
+depth in water, SSD 90 cm, one control point at gantry 0.
+
+CPU pins (oracle): in water the central ray's water-equivalent depth at the
+isocentre is the geometric depth up to the depth step, the open field is far
+wider than the kernel so the central dose is the primary itself, and a symmetric
+kernel across a straight field edge leaves half the central value at the edge.
+GPU: `calibration.calibrate` equals 1 / (oracle dose at the reference point)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_18863_amd import inputs
+
+SP = 5.0      # coarse voxels keep the oracle run to a second
+TAPS = 7      # +-15 mm support, well inside the +-50 mm field
+
+
+def _oracle_reference(n_taps=TAPS, spacing=SP):
+    case, ref = inputs.reference_case(inputs.Machine(), n_taps, spacing)
+    m = oracle.Model(case)
+    rho = oracle.density(m)
+    dose = oracle.forward(m, rho, case.gantry, case.leaves, case.jaws, case.mu)
+    ix, j, iz, w = ref
+    d_ref = (1 - w) * dose[iz, j, ix] + w * dose[iz, j + 1, ix]
+    return case, ref, dose, d_ref
+
+
+def test_reference_geometry():
+    """The entrance face sits at SSD = 900 mm from the source and the reference
+    point 100 mm below it, on the beam axis."""
+    case, (ix, j, iz, w) = inputs.reference_case(inputs.Machine(), TAPS, SP)
+    face = case.origin[1] - 0.5 * case.spacing[1]
+    assert face - (-case.machine.sad) == pytest.approx(900.0)
+    y = case.origin[1] + (j + w) * case.spacing[1]
+    assert y == pytest.approx(0.0) and case.origin[1] + j * SP <= 0 < case.origin[1] + (j + 1) * SP
+    assert case.origin[0] + ix * SP == pytest.approx(0.0) and case.origin[2] + iz * SP == pytest.approx(0.0)
+
+
+def test_reference_dose_is_depth_dose_at_10cm():
+    """Eqs. 6-9 in water on the central axis, with the field wider than the kernel:
+    D = calib MU (SAD/d)^2 DD(W) times the mass of the plane's taps.  W differs from
+    the 100 mm geometric depth by at most one depth step (the discrete sum over
+    planes) and the reference point lies within one plane of d = SAD, so D_ref is
+    bracketed by the depth-dose table, the inverse square and the tap mass over
+    that window (the tap mass is pinned on its own against the kernel's integral)."""
+    case, ref, dose, d_ref = _oracle_reference()
+    m = case.machine
+    mod = oracle.Model(case)
+    depths = np.arange(0, m.dd.size) * m.dd_step
+    win = (depths >= 100 - SP) & (depths <= 100 + SP)
+    mass = [oracle.taps(mod, d, z).sum() for d in (m.sad - SP, m.sad + SP) for z in (100 - SP, 100 + SP)]
+    lo = m.dd[win].min() * (m.sad / (m.sad + SP)) ** 2 * min(mass)
+    hi = m.dd[win].max() * (m.sad / (m.sad - SP)) ** 2 * max(mass)
+    assert lo <= d_ref <= hi
+
+
+def test_wider_kernel_raises_output_until_it_spans_the_field():
+    """More taps collect more scatter: the reference dose grows with the kernel
+    size until the kernel covers the whole open field, then stays exactly the same
+    (the primary outside the jaws is zero)."""
+    d = {n: _oracle_reference(n_taps=n)[3] for n in (7, 15, 31, 61)}
+    assert d[7] < d[15] < d[31]
+    assert d[61] == d[31]
+
+
+def test_profile_half_value_at_field_edge():
+    """The jaw edge at +-50 mm falls on a fan-pixel centre, whose overlap with the
+    opening is one half (§2.2.2); the leaves are retracted, so the fluence steps
+    1 -> 1/2 -> 0 there.  A kernel symmetric in u then gives exactly half of the
+    central value at the edge (the taps left and right of the edge column weigh the
+    same), up to the slight lateral variation of the primary at the isocentre plane."""
+    case, (ix, j, iz, w), dose, _ = _oracle_reference()
+    row = (1 - w) * dose[iz, j, :] + w * dose[iz, j + 1, :]
+    x = case.origin[0] + np.arange(row.size) * SP
+    prof = row / row[ix]
+    for edge in (-50.0, 50.0):
+        assert np.interp(edge, x, prof) == pytest.approx(0.5, abs=2e-3)
+    assert prof[np.abs(x) <= 20].min() > 0.99          # flat inside the field
+    assert np.all(prof[np.abs(x) >= 50 + 0.5 * TAPS * SP + SP] == 0.0)   # beyond the jaws and the kernel
+
+
+@pytest.mark.gpu
+def test_calibrate_matches_oracle():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_18863_amd import calibration
+    _, _, _, d_ref = _oracle_reference()
+    got = calibration.calibrate(inputs.Machine(), n_taps=TAPS, spacing=SP)
+    print("calibrate: gpu %.9e oracle %.9e" % (got, 1.0 / d_ref), flush=True)
+    assert got == pytest.approx(1.0 / d_ref, rel=1e-5)
