@@ -28,9 +28,15 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
 PEAK_HBM_GBS = 8000.0
 
 
-def kernel_source_hash() -> str:
+# sources that make up each kernel whose counters are recorded in profiles/traffic.json
+KERNEL_SOURCES = {
+    "conv_mfma_f32": ["conv_mfma.hip", "taps.hpp", "device_math.hpp", "pdrt_internal.hpp"],
+}
+
+
+def kernel_source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2512_18863_amd", "csrc"))):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2512_18863_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -38,7 +44,7 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources; otherwise None."""
+    taken on the kernel's current sources; otherwise None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -46,9 +52,87 @@ def measured_traffic(kernel: str, workload: str):
     except (OSError, ValueError):
         return None
     e = rec.get(workload, {}).get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != kernel_source_hash(kernel):
         return None
     return e.get("bytes_per_launch")
+
+
+KERNEL_SYMBOLS = {"conv_mfma_f32": "k_conv_mfma_f32<"}
+COPY_BYTES = 1 << 30   # the counter run's calibration copy
+
+
+def traffic_from_counters(fetch_csv, write_csv, workload="c4bench_fp32"):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs of `bench.py
+    --counter-run` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Each counter is
+    scaled by what it reads for the run's 1 GiB copy, so that the copy counts as
+    1 GiB read and 1 GiB written."""
+    import csv
+    import re
+
+    def load(path):
+        rows = list(csv.DictReader(open(path)))
+        return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in rows]
+
+    fetch, write = load(fetch_csv), load(write_csv)
+    f_copy = max(v for n, v in fetch if "copyBuffer" in n)
+    w_copy = max(v for n, v in write if "copyBuffer" in n)
+    kf, kw = COPY_BYTES / (f_copy * 1024.0), COPY_BYTES / (w_copy * 1024.0)
+
+    def short(name):
+        m = re.search(r"pdrt::(k_\w+(<[^(]*>)?)", name)
+        return m.group(1).replace(" ", "") if m else None
+
+    per = {}
+    for (n, v), (n2, v2) in zip(fetch, write):
+        if n != n2:
+            raise ValueError("the two counter runs dispatched different kernels")
+        k = short(n)
+        if k:
+            e = per.setdefault(k, [0, 0.0, 0.0])
+            e[0] += 1
+            e[1] += v * 1024.0 * kf
+            e[2] += v2 * 1024.0 * kw
+    rec = {"calibration": {"copy_bytes": COPY_BYTES, "fetch_kib_for_copy": f_copy, "write_kib_for_copy": w_copy,
+                           "fetch_factor": kf, "write_factor": kw},
+           "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- python3 bench.py --counter-run",
+                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o write -- python3 bench.py --counter-run"],
+           workload: {}, "all_kernels_" + workload: {}}
+    for k, (cnt, fb, wb) in per.items():
+        rec["all_kernels_" + workload][k] = {"dispatches": cnt, "fetch_bytes_per_launch": fb / cnt,
+                                             "write_bytes_per_launch": wb / cnt}
+    for name, sym in KERNEL_SYMBOLS.items():
+        hits = [(n, v, v2) for (n, v), (_, v2) in zip(fetch, write) if sym in n]
+        if hits:
+            fb = sum(h[1] for h in hits) * 1024.0 * kf / len(hits)
+            wb = sum(h[2] for h in hits) * 1024.0 * kw / len(hits)
+            rec[workload][name] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                                   "dispatches": len(hits), "source_hash": kernel_source_hash(name)}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print("wrote", path)
+
+
+def hbm_table(kernels, steps, n_cp, nodes, plane, vox):
+    """Achieved bandwidth of the memory-bound kernels from their algorithmic bytes
+    (each byte the kernel must move once): nodes = beam-frame nodes of the plan,
+    plane = fluence pixels per control point, vox = CT voxels."""
+    b = {
+        "march": 4 * nodes + 4 * n_cp * plane + 4 * vox,              # write P; read F, rho
+        "gather": 4 * nodes + 2 * 4 * vox,                            # read Dfan; write dose + compensation
+        "backproject_adj": 4 * nodes + 4 * vox,                       # write G; read g
+        "march_adj": 4 * nodes + 4 * n_cp * plane + 4 * vox,          # read H; write A; read rho
+    }
+    out = {}
+    for k, by in b.items():
+        if k not in kernels:
+            continue
+        launches, total = kernels[k]
+        avg = total / max(launches, 1) / 1e3
+        gbs = by / avg / 1e9 if avg > 0 else 0.0
+        out[k] = {"algorithmic_bytes": by, "avg_launch_ms": round(avg * 1e3, 4), "achieved_GBs": round(gbs, 1),
+                  "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    return out
 
 
 def run_gpu(case, conv, steps, warmup, w):
@@ -82,6 +166,54 @@ def run_gpu(case, conv, steps, warmup, w):
     fwd_dose = eng.forward(lv, jw, mu).cpu().numpy()
     torch.cuda.synchronize()
     return ms, kernels, fwd_dose, eng
+
+
+LEARNED_WEIGHTS = os.path.join(ROOT, "paper_2512_18863_amd", "data", "learned_c4.npz")
+
+
+def run_learned(case, steps, warmup, w, d_ref):
+    """The learned path (9 x 9 dose + U-Net, falling back to the plain 61 x 61 path
+    when its own error estimate is too large), forward + backward, timed like the
+    plain path; its dose is compared with the plain FP32 61 x 61 dose."""
+    import numpy as np
+    import torch
+    from paper_2512_18863_amd import engine as E
+    from paper_2512_18863_amd import gamma, learned
+    st = np.load(LEARNED_WEIGHTS)
+    net = learned.Net3D(case.shape, seed=0)
+    net.load({"params": st["params"], "m": st["m"], "v": st["v"], "t": int(st["t"])})
+    ld = learned.LearnedDose(net, case, mode="auto")
+    dev = ld.small.device
+    lv = torch.tensor(case.leaves, dtype=torch.float32, device=dev)
+    jw = torch.tensor(case.jaws, dtype=torch.float32, device=dev)
+    mu = torch.tensor(case.mu, dtype=torch.float32, device=dev)
+    g = torch.tensor(w, dtype=torch.float32, device=dev)
+
+    def step():
+        ld.forward(lv, jw, mu)
+        return ld.backward(lv, jw, mu, g)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    E.profile_begin(64 * steps + 64)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    kernels = E.profile_end()
+    dose = ld.forward(lv, jw, mu).cpu().numpy().astype(np.float64)
+    fell_back = ld.fell_back
+    raw = learned.LearnedDose(net, case, mode="never").forward(lv, jw, mu).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    return {"value": round(case.n_cp / (ms / 1e3), 3), "ms_per_step": round(ms, 4), "fell_back": fell_back,
+            "max_abs_err_vs_fp32_61_over_max": float(np.abs(dose - d_ref).max() / np.abs(d_ref).max()),
+            "gamma_1pct_1mm_vs_fp32_61": round(gamma.pass_rate(d_ref, dose, case.spacing, 1.0, 1.0), 6),
+            "network_only": {"max_abs_err_over_max": float(np.abs(raw - d_ref).max() / np.abs(d_ref).max()),
+                             "gamma_1pct_1mm": round(gamma.pass_rate(d_ref, raw, case.spacing, 1.0, 1.0), 6)},
+            "kernels_ms_per_step": {k: round(v[1] / steps, 4) for k, v in sorted(kernels.items())},
+            "note": "wall clock per step (the fallback decision reads two numbers back to the host)"}
 
 
 def cpu_baseline(case, w, budget_s=12.0, max_cp=24):
@@ -136,10 +268,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from the two counter runs' CSV files and exit")
     ap.add_argument("--counter-run", action="store_true",
                     help="one copy of 1 GiB (the counter calibration) then one FP32 forward + backward; "
                          "for rocprofv3 --pmc runs")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from_counters(*args.traffic_from)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the dose path is built and timed on a single MI355X; "
               "multi-GPU control-point sharding is a design note only (got --gpus %d)" % args.gpus,
@@ -190,6 +328,7 @@ def main():
                      "flops_per_launch": flops, "avg_launch_ms": round(avg_s * 1e3, 4),
                      "launches": launches},
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(kernels.items())},
+        "hbm_kernels": hbm_table(kernels, args.steps, n_cp, nodes, eng.Nu * eng.Nv, int(np.prod(case.shape))),
         "paper_context": {"value": 35.3, "unit": "control points/s (fwd+bwd)", "hardware": "NVIDIA A40",
                           "workload": "105x224x224 grid, 180 control points, kernel 55 (Table 6: 5.102 s)"},
     }
@@ -211,6 +350,10 @@ def main():
                          "frac": round(a16 / PEAK_BF16_MFMA_TFLOPS, 4)},
             "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(k16.items())}}}
         del eng16
+    if not args.no_learned and os.path.exists(LEARNED_WEIGHTS):
+        print("[bench] learned variant", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out.setdefault("variants", {})["learned"] = run_learned(case, args.steps, args.warmup, w, d32)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, w)

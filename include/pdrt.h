@@ -229,12 +229,18 @@ int pdrt_conv3d_backward_weight(const pdrt_vol* vol, int32_t c1, int32_t c2, con
                                 size_t ws_bytes, float* dw, float* db, void* stream);
 /* x[p][16] = (dose[p] * scale[0], rho[p], 0, ..., 0) as bf16; n = D H W. */
 int pdrt_net_input(int32_t n, const float* dose, const float* scale, const float* rho, void* x, void* stream);
-/* Gradient w.r.t. the dose fed to pdrt_net_input and pdrt_net_head:
- * ddose[p] = scale[0] (gp[p] + dx0[p][0]). */
-int pdrt_net_input_backward(int32_t n, const void* dx0, const float* gp, const float* scale, float* ddose,
-                            void* stream);
-/* scale[0] = 1 / max(dose) (1 if the dose is zero). */
-int pdrt_net_scale(int32_t n, const float* dose, float* scale, void* stream);
+/* Gradient w.r.t. the dose fed to pdrt_net_scale, pdrt_net_input and pdrt_net_head,
+ * given gp = dL/dpred (and dx0 = dL/dx from the first convolution's data gradient):
+ * ddose[p] = scale[0] (gp[p] + dx0[p][0]) at fixed scale; with dose, pred and argmax
+ * (all three, from the same forward) it adds the dependence of scale = 1/max(dose)
+ * on the dose at the argmax m:
+ *   ddose[m] -= scale[0] (sum_p dose[p] ddose[p] - sum_p gp[p] pred[p]).
+ * dose, pred, argmax all NULL: the scale is treated as a constant. */
+int pdrt_net_input_backward(int32_t n, const void* dx0, const float* gp, const float* scale, const float* dose,
+                            const float* pred, const int32_t* argmax, float* ddose, void* stream);
+/* scale[0] = 1 / max(dose) (1 if no dose is positive); argmax (may be NULL) receives
+ * the first index of the maximum, or -1 if no dose is positive. */
+int pdrt_net_scale(int32_t n, const float* dose, float* scale, int32_t* argmax, void* stream);
 /* out = a * scale[0] (inverse == 0) or a / scale[0] (inverse != 0); out may alias a. */
 int pdrt_scale_by(int32_t n, const float* a, const float* scale, int32_t inverse, float* out, void* stream);
 /* out = a + b over n bf16 elements (out may alias a or b). */

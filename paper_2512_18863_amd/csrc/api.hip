@@ -9,6 +9,43 @@
 
 using namespace pdrt;
 
+namespace pdrt {
+
+namespace {
+struct ProfRec {
+  const char* name;
+  int a, b;  // indices into the event pool
+};
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<ProfRec> recs;
+  bool overflow = false;
+};
+Profiler& prof() {
+  static Profiler p;
+  return p;
+}
+}  // namespace
+
+bool prof_enabled() { return prof().on; }
+
+int prof_mark(hipStream_t s) {
+  Profiler& P = prof();
+  if (P.used >= P.pool.size()) {
+    P.overflow = true;
+    return -1;
+  }
+  int i = (int)P.used++;
+  if (hipEventRecord(P.pool[i], s) != hipSuccess) return -1;
+  return i;
+}
+
+void prof_record(const char* name, int a, int b) { prof().recs.push_back(ProfRec{name, a, b}); }
+
+}  // namespace pdrt
+
 namespace {
 
 struct Problem {
@@ -161,43 +198,7 @@ void make_geo(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_sp
     if ((x) != hipSuccess) return PDRT_E_HIP; \
   } while (0)
 
-// Optional per-launch timing (pdrt_profile_begin / pdrt_profile_end): a pair of
-// HIP events is recorded around every kernel the dose entry points enqueue.
-struct ProfRec {
-  const char* name;
-  int a, b;  // indices into the event pool
-};
-struct Profiler {
-  bool on = false;
-  std::vector<hipEvent_t> pool;
-  size_t used = 0;
-  std::vector<ProfRec> recs;
-  bool overflow = false;
-};
-Profiler& prof() {
-  static Profiler p;
-  return p;
-}
-int prof_mark(hipStream_t s) {
-  Profiler& P = prof();
-  if (P.used >= P.pool.size()) {
-    P.overflow = true;
-    return -1;
-  }
-  int i = (int)P.used++;
-  if (hipEventRecord(P.pool[i], s) != hipSuccess) return -1;
-  return i;
-}
-
-#define LAUNCH(name, x)                                           \
-  do {                                                            \
-    int pa_ = prof().on ? prof_mark(s) : -1;                      \
-    if ((x) != hipSuccess) return PDRT_E_HIP;                     \
-    if (prof().on && pa_ >= 0) {                                  \
-      int pb_ = prof_mark(s);                                     \
-      if (pb_ >= 0) prof().recs.push_back(ProfRec{name, pa_, pb_}); \
-    }                                                             \
-  } while (0)
+#define LAUNCH(name, x) PDRT_TIMED(name, s, x)
 
 template <typename T>
 hipError_t run_conv(const Geo<T>& g, int conv_mode, int nb, const T* z, const T* in, T* out, hipStream_t s);
@@ -412,7 +413,7 @@ int pdrt_project_params_backward(int32_t n_cp, int32_t n_leaf_pairs, const float
 
 int pdrt_profile_begin(int32_t max_launches) {
   if (max_launches < 1) return PDRT_E_INVALID;
-  Profiler& P = prof();
+  auto& P = pdrt::prof();
   size_t need = 2 * (size_t)max_launches;
   while (P.pool.size() < need) {
     hipEvent_t e;
@@ -427,12 +428,12 @@ int pdrt_profile_begin(int32_t max_launches) {
 }
 
 int pdrt_profile_end(pdrt_kernel_time* out, int32_t max_entries, int32_t* n_entries) {
-  Profiler& P = prof();
+  auto& P = pdrt::prof();
   if (!P.on) return PDRT_E_INVALID;
   P.on = false;
   if (!out || !n_entries || max_entries < 1) return PDRT_E_INVALID;
   int n = 0;
-  for (const ProfRec& r : P.recs) {
+  for (const auto& r : P.recs) {
     if (hipEventSynchronize(P.pool[r.b]) != hipSuccess) return PDRT_E_HIP;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, P.pool[r.a], P.pool[r.b]) != hipSuccess) return PDRT_E_HIP;

@@ -397,17 +397,32 @@ __global__ void k_adam(size_t n, float* __restrict__ w, const float* __restrict_
 }
 
 // scale[0] = 1 / max(dose) (single block).
-__global__ void __launch_bounds__(1024) k_inv_max(int P, const float* __restrict__ dose, float* __restrict__ scale) {
-  __shared__ float red[1024];
+__global__ void __launch_bounds__(1024) k_inv_max(int P, const float* __restrict__ dose, float* __restrict__ scale,
+                                                  int* __restrict__ argmax) {
+  // max with its first index (ties keep the smallest index), one block, fixed order
+  __shared__ float rv[1024];
+  __shared__ int ri[1024];
   float mx = 0.f;
-  for (int p = threadIdx.x; p < P; p += 1024) mx = fmaxf(mx, dose[p]);
-  red[threadIdx.x] = mx;
+  int im = -1;
+  for (int p = threadIdx.x; p < P; p += 1024) {
+    float d = dose[p];
+    if (d > mx) mx = d, im = p;
+  }
+  rv[threadIdx.x] = mx;
+  ri[threadIdx.x] = im;
   __syncthreads();
   for (int off = 512; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
+    if (threadIdx.x < off) {
+      float a = rv[threadIdx.x], b = rv[threadIdx.x + off];
+      int ia = ri[threadIdx.x], ib = ri[threadIdx.x + off];
+      if (b > a || (b == a && ib >= 0 && (ia < 0 || ib < ia))) rv[threadIdx.x] = b, ri[threadIdx.x] = ib;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) scale[0] = red[0] > 0.f ? 1.f / red[0] : 1.f;
+  if (threadIdx.x == 0) {
+    scale[0] = rv[0] > 0.f ? 1.f / rv[0] : 1.f;
+    if (argmax) argmax[0] = rv[0] > 0.f ? ri[0] : -1;
+  }
 }
 
 // out[p] = a[p] * f, f = scale[0] (inv = 0) or 1 / scale[0] (inv = 1).
@@ -433,6 +448,28 @@ __global__ void k_net_input_bwd(int P, const __bf16* __restrict__ dX0, const flo
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   ddose[p] = scale[0] * (gp[p] + (float)dX0[(size_t)p * 16]);
+}
+
+// The normalisation s = 1 / max(dose) depends on the dose at its argmax m:
+// ddose[m] -= s (sum_p dose[p] ddose[p] - sum_p gp[p] pred[p]), with ddose the
+// gradient at fixed s.  One block; FP64 sums in a fixed order.
+__global__ void __launch_bounds__(1024) k_scale_adjoint(int P, const float* __restrict__ dose,
+                                                        const float* __restrict__ gp, const float* __restrict__ pred,
+                                                        const float* __restrict__ scale, const int* __restrict__ argmax,
+                                                        float* __restrict__ ddose) {
+  __shared__ double red[1024];
+  const int m = argmax[0];
+  if (m < 0) return;  // zero dose: s is the constant 1 (uniform across the block)
+  double t = 0.0;
+  for (int p = threadIdx.x; p < P; p += 1024)
+    t += (double)dose[p] * (double)ddose[p] - (double)gp[p] * (double)pred[p];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ddose[m] = (float)((double)ddose[m] - (double)scale[0] * red[0]);
 }
 
 // Fallback statistics: stats[0] = max pred, stats[1] = max resid over voxels with
@@ -580,8 +617,8 @@ hipError_t launch_fallback_stats(int P, const float* pred, const float* resid, f
   return hipGetLastError();
 }
 
-hipError_t launch_inv_max(int P, const float* dose, float* scale, hipStream_t s) {
-  hipLaunchKernelGGL(k_inv_max, dim3(1), dim3(1024), 0, s, P, dose, scale);
+hipError_t launch_inv_max(int P, const float* dose, float* scale, int* argmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_inv_max, dim3(1), dim3(1024), 0, s, P, dose, scale, argmax);
   return hipGetLastError();
 }
 
@@ -598,6 +635,12 @@ hipError_t launch_add_bf16(size_t n, const __bf16* a, const __bf16* b, __bf16* o
 hipError_t launch_net_input_bwd(int P, const __bf16* dX0, const float* gp, const float* scale, float* ddose,
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_net_input_bwd, dim3(nblk(P)), dim3(256), 0, s, P, dX0, gp, scale, ddose);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_adjoint(int P, const float* dose, const float* gp, const float* pred, const float* scale,
+                                const int* argmax, float* ddose, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_adjoint, dim3(1), dim3(1024), 0, s, P, dose, gp, pred, scale, argmax, ddose);
   return hipGetLastError();
 }
 

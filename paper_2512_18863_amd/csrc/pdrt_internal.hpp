@@ -114,7 +114,9 @@ hipError_t launch_train_loss(int P, const float* pred, const float* resid, const
 hipError_t launch_reduce_splits(int nsplit, size_t n, const float* part, float* out, hipStream_t s);
 hipError_t launch_fallback_stats(int P, const float* pred, const float* resid, float frac, float* stats,
                                  hipStream_t s);
-hipError_t launch_inv_max(int P, const float* dose, float* scale, hipStream_t s);
+hipError_t launch_inv_max(int P, const float* dose, float* scale, int* argmax, hipStream_t s);
+hipError_t launch_scale_adjoint(int P, const float* dose, const float* gp, const float* pred, const float* scale,
+                                const int* argmax, float* ddose, hipStream_t s);
 hipError_t launch_scale_by(int P, const float* a, const float* scale, int inv, float* out, hipStream_t s);
 hipError_t launch_add_bf16(size_t n, const __bf16* a, const __bf16* b, __bf16* out, hipStream_t s);
 hipError_t launch_net_input_bwd(int P, const __bf16* dX0, const float* gp, const float* scale, float* ddose,
@@ -122,4 +124,22 @@ hipError_t launch_net_input_bwd(int P, const __bf16* dX0, const float* gp, const
 hipError_t launch_adam(size_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
                        float c1, float c2, hipStream_t s);
 
+// Per-launch timing shared by every entry point (pdrt_profile_begin / _end): an
+// event is recorded on the launch stream before and after each timed launch.
+bool prof_enabled();
+int prof_mark(hipStream_t s);                       // event index, or -1 (pool exhausted / error)
+void prof_record(const char* name, int a, int b);
+
 }  // namespace pdrt
+
+// Enqueue `x` (a hipError_t expression) on stream `s`, timed under `name` when
+// profiling is on; returns PDRT_E_HIP from the enclosing function on failure.
+#define PDRT_TIMED(name, s, x)                                         \
+  do {                                                                 \
+    int pa_ = ::pdrt::prof_enabled() ? ::pdrt::prof_mark(s) : -1;      \
+    if ((x) != hipSuccess) return PDRT_E_HIP;                          \
+    if (pa_ >= 0) {                                                    \
+      int pb_ = ::pdrt::prof_mark(s);                                  \
+      if (pb_ >= 0) ::pdrt::prof_record(name, pa_, pb_);               \
+    }                                                                  \
+  } while (0)

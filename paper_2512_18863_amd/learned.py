@@ -53,8 +53,8 @@ def _lib():
             "pdrt_conv3d_backward_weight": (ctypes.c_int, [P(Vol), I32, I32, V, V, I32, V, V, I32, V,
                                                            ctypes.c_size_t, V, V, V]),
             "pdrt_net_input": (ctypes.c_int, [I32, V, V, V, V, V]),
-            "pdrt_net_input_backward": (ctypes.c_int, [I32, V, V, V, V, V]),
-            "pdrt_net_scale": (ctypes.c_int, [I32, V, V, V]),
+            "pdrt_net_input_backward": (ctypes.c_int, [I32, V, V, V, V, V, V, V, V]),
+            "pdrt_net_scale": (ctypes.c_int, [I32, V, V, V, V]),
             "pdrt_scale_by": (ctypes.c_int, [I32, V, V, I32, V, V]),
             "pdrt_add_bf16": (ctypes.c_int, [ctypes.c_size_t, V, V, V, V]),
             "pdrt_pool2": (ctypes.c_int, [P(Vol), I32, V, V, I32, V]),
@@ -150,6 +150,8 @@ class Net3D:
         self.pred = torch.empty(n0, **f32)
         self.resid = torch.empty(n0, **f32)
         self.scale = torch.empty(1, **f32)
+        self.argmax = torch.empty(1, dtype=torch.int32, device=self.dev)
+        self._dose = None
         self.gp = torch.empty(n0, **f32)
         self.gr = torch.empty(n0, **f32)
         self.stats = torch.empty(2, **f32)
@@ -197,7 +199,8 @@ class Net3D:
         normalised by the dose maximum (self.scale)."""
         lib, s = _lib(), self._s()
         n0 = self.npos[0]
-        _ck(lib.pdrt_net_scale(n0, _p(dose), _p(self.scale), s), "net_scale")
+        self._dose = dose
+        _ck(lib.pdrt_net_scale(n0, _p(dose), _p(self.scale), _p(self.argmax), s), "net_scale")
         _ck(lib.pdrt_net_input(n0, _p(dose), _p(self.scale), _p(rho), _p(self.x0), s), "net_input")
         a = self._conv("e1a", self.x0)
         s1 = self._conv("e1b", a)
@@ -237,7 +240,8 @@ class Net3D:
     def backward(self, gp, gr, dose_grad=None, weights=True):
         """Back-propagate dL/dpred (gp) and dL/dresid (gr, may be None); accumulates
         nothing: weight gradients are overwritten.  If dose_grad is given, writes
-        dL/d dose (the small-kernel input dose) into it."""
+        dL/d dose (the input dose of the last forward, including its effect through
+        the normalisation 1 / max dose) into it."""
         lib, s = _lib(), self._s()
         n0 = self.npos[0]
         hw, _ = self.head()
@@ -262,8 +266,8 @@ class Net3D:
         self._back("e1b", g["e1b"], self.act["e1a"], None, g["e1a"], None, weights)
         self._back("e1a", g["e1a"], self.x0, None, self.gx0 if dose_grad is not None else None, None, weights)
         if dose_grad is not None:
-            _ck(lib.pdrt_net_input_backward(n0, _p(self.gx0), _p(gp), _p(self.scale), _p(dose_grad), s),
-                "input_bwd")
+            _ck(lib.pdrt_net_input_backward(n0, _p(self.gx0), _p(gp), _p(self.scale), _p(self._dose), _p(self.pred),
+                                            _p(self.argmax), _p(dose_grad), s), "input_bwd")
 
     def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         # (the first layer's padding input channels are zero, so their weight gradients
@@ -346,6 +350,7 @@ class LearnedDose:
         self.shape = case.shape
         self.out = torch.empty(self.n, dtype=torch.float32, device=self.small.device)
         self.dsmall = torch.empty(self.n, dtype=torch.float32, device=self.small.device)
+        self.ddose = torch.empty(self.n, dtype=torch.float32, device=self.small.device)
         self.fell_back = False
 
     def forward(self, lv, jw, mu):
@@ -371,6 +376,5 @@ class LearnedDose:
         gflat = g.reshape(-1)
         # dose = pred / s  ->  dL/dpred = g / s
         _ck(lib.pdrt_scale_by(self.n, _p(gflat), _p(self.net.scale), 1, _p(self.net.gp), s), "scale")
-        ddose = self.dsmall  # reuse: the small dose is not needed after the forward
-        self.net.backward(self.net.gp, None, dose_grad=ddose, weights=False)
-        return self.small.backward(lv, jw, mu, ddose.view(*self.shape))
+        self.net.backward(self.net.gp, None, dose_grad=self.ddose, weights=False)
+        return self.small.backward(lv, jw, mu, self.ddose.view(*self.shape))

@@ -188,3 +188,108 @@ def test_learned_training_reduces_loss_and_fallback_is_plain():
     out = ld.forward(t(last.leaves), t(last.jaws), t(last.mu))
     plain = E.DoseEngine(last, n_taps=61).forward(t(last.leaves), t(last.jaws), t(last.mu))
     assert ld.fell_back and torch.equal(out, plain)
+
+
+class _RoundBF16(torch.autograd.Function):
+    """BF16 storage of an activation in the forward, identity in the backward."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return x.to(torch.bfloat16).float()
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+def _torch_unet(net, ds, rho, dims):
+    """The learned correction's forward in FP32 torch on the CPU (weights rounded to
+    BF16 as the kernels see them, activations stored as BF16), returning the dose
+    out = pred / s with s = 1 / max(ds)."""
+    from paper_2512_18863_amd.learned import HEAD_C, LAYERS
+    D, H, W = dims
+    r = _RoundBF16.apply
+    s = 1.0 / ds.max()
+    x0 = torch.zeros(1, 16, D, H, W)
+    x0 = torch.cat([(ds * s).reshape(1, 1, D, H, W), rho.reshape(1, 1, D, H, W), x0[:, 2:]], dim=1)
+    x0 = r(x0)
+    prm = net.params.detach().cpu()
+    act = {}
+
+    def conv(name, x):
+        (_, c1, c2, cout, _) = next(l for l in LAYERS if l[0] == name)
+        o, nw, bo, _ = net.slices[name]
+        w = prm[o:o + nw].reshape(cout, 27, c1 + c2).to(torch.bfloat16).float()
+        y = torch.relu(Fn.conv3d(x, _w_torch(w), prm[bo:bo + cout], padding=1))
+        act[name] = r(y)
+        return act[name]
+
+    s1 = conv("e1b", conv("e1a", x0))
+    s2 = conv("e2b", conv("e2a", r(Fn.avg_pool3d(s1, 2))))
+    b = conv("bb", conv("ba", r(Fn.avg_pool3d(s2, 2))))
+    c2 = conv("d2b", conv("d2a", torch.cat([Fn.interpolate(b, scale_factor=2, mode="nearest"), s2], dim=1)))
+    c1 = conv("d1b", conv("d1a", torch.cat([Fn.interpolate(c2, scale_factor=2, mode="nearest"), s1], dim=1)))
+    ho = net.head_off
+    hw = prm[ho:ho + 2 * HEAD_C].reshape(2, HEAD_C)
+    hb = prm[ho + 2 * HEAD_C:ho + 2 * HEAD_C + 2]
+    feat = c1.reshape(HEAD_C, -1)
+    pred = ds * s + hb[0] + hw[0] @ feat
+    return pred / s
+
+
+def test_learned_dose_gradient_matches_torch_autograd():
+    """d(sum g * out)/d(small dose) through the whole network, including the
+    normalisation by the maximum dose (its argmax voxel gets the extra term),
+    against torch autograd of the same network on the CPU."""
+    from paper_2512_18863_amd import learned
+    _say("learned input gradient vs torch autograd, 16^3")
+    lib = learned._lib()
+    dims = (16, 16, 16)
+    n = 16 ** 3
+    net = learned.Net3D(dims, seed=5)
+    rng = np.random.default_rng(11)
+    # larger weights than the initialisation so every layer matters
+    p = net.params.detach().cpu().numpy()
+    for (name, c1, c2, cout, lvl) in learned.LAYERS:
+        o, nw, bo, _ = net.slices[name]
+        p[o:o + nw] = rng.normal(0.0, np.sqrt(2.0 / (27 * (c1 + c2))), size=nw)
+        p[bo:bo + cout] = rng.normal(0.0, 0.05, size=cout)
+    ho = net.head_off
+    p[ho:ho + 2 * learned.HEAD_C + 2] = rng.normal(0.0, 0.3, size=2 * learned.HEAD_C + 2)
+    net.params.copy_(torch.tensor(p))
+    net.prepare()
+    ds_h = torch.tensor(rng.uniform(0.1, 1.0, size=n), dtype=torch.float32)
+    ds_h[1234] = 1.7                         # a unique maximum
+    rho_h = torch.tensor(rng.uniform(0.0, 1.5, size=n), dtype=torch.float32)
+    g_h = torch.tensor(rng.normal(size=n), dtype=torch.float32)
+    ds, rho, g = ds_h.cuda(), rho_h.cuda(), g_h.cuda()
+    s = torch.cuda.current_stream().cuda_stream
+    pred, _ = net.forward(ds, rho)
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    assert lib.pdrt_scale_by(n, pred.data_ptr(), net.scale.data_ptr(), 1, out.data_ptr(), s) == 0
+    gp = torch.empty(n, dtype=torch.float32, device="cuda")
+    assert lib.pdrt_scale_by(n, g.data_ptr(), net.scale.data_ptr(), 1, gp.data_ptr(), s) == 0
+    ddose = torch.empty(n, dtype=torch.float32, device="cuda")
+    net.backward(gp, None, dose_grad=ddose, weights=False)
+    torch.cuda.synchronize()
+    assert int(net.argmax.item()) == 1234
+    x = ds_h.clone().requires_grad_()
+    ref_out = _torch_unet(net, x, rho_h, dims)
+    (ref_out * g_h).sum().backward()
+    _close("learned dose", out.cpu(), ref_out.detach())
+    got = ddose.cpu()
+    # ten BF16 layers forward and back: each stores activations and gradients with
+    # <= 2^-9 relative rounding, so allow 2^-5 of the largest reference gradient
+    m = 1234
+    keep = torch.ones(n, dtype=torch.bool)
+    keep[m] = False
+    err = (got[keep] - x.grad[keep]).abs().max().item() / x.grad[keep].abs().max().item()
+    err_m = abs(got[m].item() - x.grad[m].item()) / abs(x.grad[m].item())
+    _say("input gradient: max err / max|ref| %.3e; argmax voxel got %.6e ref %.6e (rel %.2e)" %
+         (err, got[m].item(), x.grad[m].item(), err_m))
+    assert err <= 2.0 ** -5 and err_m <= 2.0 ** -5
+    # the output is homogeneous of degree one in the dose, so <grad, ds> = <g, out>
+    # (this fails without the normalisation's term at the argmax)
+    lhs = float((got.double() * ds_h.double()).sum())
+    rhs = float((g_h.double() * out.cpu().double()).sum())
+    assert abs(lhs - rhs) <= 1e-4 * float((g_h.abs().double() * out.cpu().abs().double()).sum())
