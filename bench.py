@@ -179,9 +179,7 @@ def run_learned(case, steps, warmup, w, d_ref):
     import torch
     from paper_2512_18863_amd import engine as E
     from paper_2512_18863_amd import gamma, learned
-    st = np.load(LEARNED_WEIGHTS)
-    net = learned.Net3D(case.shape, seed=0)
-    net.load({"params": st["params"], "m": st["m"], "v": st["v"], "t": int(st["t"])})
+    net = learned.Net3D.from_file(LEARNED_WEIGHTS, case.shape)
     ld = learned.LearnedDose(net, case, mode="auto")
     dev = ld.small.device
     lv = torch.tensor(case.leaves, dtype=torch.float32, device=dev)

@@ -291,11 +291,29 @@ class Net3D:
                 "t": self.t}
 
     def load(self, st):
-        self.params.copy_(torch.tensor(st["params"], device=self.dev))
-        self.m.copy_(torch.tensor(st["m"], device=self.dev))
-        self.v.copy_(torch.tensor(st["v"], device=self.dev))
-        self.t = int(st["t"])
+        """Parameters (and, if present, the Adam state) from a dict or npz archive."""
+        if "layers" in st and [str(x) for x in st["layers"]] != [l[0] for l in LAYERS]:
+            raise ValueError("the stored network has a different layer list")
+        p = np.asarray(st["params"], dtype=np.float32)
+        if p.size != self.params.numel():
+            raise ValueError("stored parameter count %d != %d" % (p.size, self.params.numel()))
+        self.params.copy_(torch.tensor(p, device=self.dev))
+        if "m" in st and "v" in st:
+            self.m.copy_(torch.tensor(st["m"], device=self.dev))
+            self.v.copy_(torch.tensor(st["v"], device=self.dev))
+            self.t = int(st["t"])
+        else:
+            self.m.zero_()
+            self.v.zero_()
+            self.t = 0
         self.prepare()
+
+    @classmethod
+    def from_file(cls, path, dims, device="cuda"):
+        net = cls(dims, device=device)
+        with np.load(path) as st:
+            net.load({k: st[k] for k in st.files})
+        return net
 
 
 # ---------------------------------------------------------------------- data

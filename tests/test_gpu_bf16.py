@@ -26,6 +26,9 @@ def _need_gpu():
 @pytest.mark.parametrize("name,mk,idx", [
     ("C2", inputs.config_c2, np.arange(0, 180, 12)),
     ("C4-bench", lambda: inputs.config_c4_plan(2000, bench=True), np.array([5, 50, 95, 140])),
+    # 131 x 131 beam-frame planes: several convolution regions in both directions
+    ("wide", lambda: inputs.tiny_case(seed=16, n_taps=31, shape=(10, 12, 11), spacing=3.0, field=150.0,
+                                      n_leaf=30, leaf_width=10.0), np.arange(2)),
 ])
 def test_bf16_error_vs_oracle(name, mk, idx):
     c = subset(mk(), idx)

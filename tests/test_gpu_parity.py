@@ -128,6 +128,8 @@ TINY = [
     dict(seed=13, n_taps=15, shape=(9, 8, 10), spacing=6.0, field=40.0),      # MFMA path, ragged tiles
     dict(seed=14, n_taps=31, shape=(8, 8, 8), spacing=5.0, field=30.0, n_cp=3),
     dict(seed=15, n_taps=13, shape=(1, 5, 4), spacing=8.0, field=20.0),      # a single slice
+    # a 115 x 115 beam-frame plane: several convolution regions in both directions
+    dict(seed=16, n_taps=15, shape=(10, 12, 11), spacing=3.0, field=150.0, n_leaf=30, leaf_width=10.0),
 ]
 
 
