@@ -45,6 +45,8 @@ class _Model(ctypes.Structure):
         ("tau", ctypes.c_double), ("calib", ctypes.c_double),
         ("n_dd", ctypes.c_int), ("dd_step", ctypes.c_double), ("dd", ctypes.POINTER(ctypes.c_double)),
         ("kpoly", (ctypes.c_double * 4) * 4), ("kz_max", ctypes.c_double),
+        ("fcorr", ctypes.c_int), ("pen_fwhm_u", ctypes.c_double), ("pen_fwhm_v", ctypes.c_double),
+        ("hs_amp", ctypes.c_double), ("hs_sigma", ctypes.c_double), ("oar", ctypes.c_double * 2),
     ]
 
 
@@ -62,6 +64,7 @@ def _lib_handle():
             "or_fan_dims": (I, [M, ctypes.POINTER(I), _P]),
             "or_hu_to_density": (None, [ctypes.c_long, _P, _P, I, _P, _P]),
             "or_raster": (None, [M, _P, _P, _P]),
+            "or_fluence_correct": (None, [M, _P, _P, I]),
             "or_rho_sample": (D, [M, _P, D, D, D]),
             "or_ca_depth": (None, [M, _P, D, _P]),
             "or_wepl": (None, [M, _P, D, _P]),
@@ -121,6 +124,10 @@ class Model:
             for b in range(4):
                 s.kpoly[a][b] = float(m.kpoly[a][b])
         s.kz_max = m.kz_max
+        s.fcorr = 1 if m.fcorr else 0
+        s.pen_fwhm_u, s.pen_fwhm_v = m.pen_fwhm_u, m.pen_fwhm_v
+        s.hs_amp, s.hs_sigma = m.hs_amp, m.hs_sigma
+        s.oar[:] = [float(m.oar[0]), float(m.oar[1])]
         self.s = s
         dims = (ctypes.c_int * 3)()
         d0 = ctypes.c_double()
@@ -161,6 +168,15 @@ def raster(model: Model, leaves, jaws) -> np.ndarray:
     lv, jw = _f64(leaves), _f64(jaws)
     _lib_handle().or_raster(model.ref, _ptr(lv), _ptr(jw), _ptr(F))
     return F
+
+
+def fluence_correct(model: Model, F, transpose: bool = False) -> np.ndarray:
+    """Fluence corrections (source penumbra, head scatter, off-axis) of one map
+    [Nv][Nu], or their adjoint."""
+    F = _f64(F)
+    out = np.empty_like(F)
+    _lib_handle().or_fluence_correct(model.ref, _ptr(F), _ptr(out), 1 if transpose else 0)
+    return out
 
 
 def rho_sample(model: Model, rho, x, y, z) -> float:

@@ -197,6 +197,96 @@ void or_raster(const or_model* m, const double* leaves, const double* jaws, doub
   }
 }
 
+/* Unit-sum Gaussian taps g_m = exp(-(m D)^2 / (2 sigma^2)) / sum, m = -R..R with
+ * R = ceil(3 sigma / D): the Gaussian sampled at the pixel centres of the fan grid
+ * and truncated at three standard deviations.  sigma <= 0 gives the single tap 1. */
+static int gauss_taps(double sigma, double D, double* g, int rmax) {
+  if (!(sigma > 0.0)) {
+    g[0] = 1.0;
+    return 0;
+  }
+  int R = (int)ceil(3.0 * sigma / D - 1e-9);
+  if (R > rmax) R = rmax;
+  double s = 0.0;
+  for (int m = -R; m <= R; ++m) {
+    g[m + R] = exp(-(m * D) * (m * D) / (2.0 * sigma * sigma));
+    s += g[m + R];
+  }
+  for (int m = 0; m <= 2 * R; ++m) g[m] /= s;
+  return R;
+}
+
+/* out = 1-D correlation of `in` [Nv][Nu] with taps g (radius R) along u (axis 0) or v
+ * (axis 1), zero outside the map.  The taps are even, so it is its own transpose. */
+static void blur_axis(int Nu, int Nv, const double* g, int R, int axis, const double* in, double* out) {
+  for (int j = 0; j < Nv; ++j)
+    for (int i = 0; i < Nu; ++i) {
+      double acc = 0.0;
+      for (int m = -R; m <= R; ++m) {
+        int ii = axis == 0 ? i + m : i, jj = axis == 0 ? j : j + m;
+        if (ii < 0 || ii >= Nu || jj < 0 || jj >= Nv) continue;
+        acc += g[m + R] * in[(long)jj * Nu + ii];
+      }
+      out[(long)j * Nu + i] = acc;
+    }
+}
+
+/* Fluence corrections (§2.2.2 list), on the aperture fluence F (which already carries
+ * the MLC transmission):
+ *   source penumbra  F1 = G_v (G_u F), directional Gaussians of the given FWHM
+ *                    (sigma = FWHM / (2 sqrt(2 ln 2)));
+ *   head scatter     F2 = F1 + hs_amp G_hs F1, G_hs the isotropic Gaussian of hs_sigma;
+ *   off-axis         Fc = F2 (1 + oar0 r + oar1 r^2), r = sqrt(u^2 + v^2) at the isocentre plane.
+ * Every blur acts on the fan pixel grid with zero padding.  The adjoint applies the
+ * transposes in reverse order (each blur and the pointwise factor is symmetric). */
+void or_fluence_correct(const or_model* m, const double* F, double* Fc, int transpose) {
+  int dims[3];
+  double d0;
+  or_fan_dims(m, dims, &d0);
+  int Nu = dims[0], Nv = dims[1];
+  long plane = (long)Nu * Nv;
+  if (!m->fcorr) {
+    memcpy(Fc, F, sizeof(double) * plane);
+    return;
+  }
+  enum { RMAX = 512 };
+  double* gu = (double*)malloc(sizeof(double) * (2 * RMAX + 1));
+  double* gv = (double*)malloc(sizeof(double) * (2 * RMAX + 1));
+  double* gh = (double*)malloc(sizeof(double) * (2 * RMAX + 1));
+  const double k = 2.0 * sqrt(2.0 * log(2.0)), D = m->lat_step;
+  int Ru = gauss_taps(m->pen_fwhm_u / k, D, gu, RMAX), Rv = gauss_taps(m->pen_fwhm_v / k, D, gv, RMAX);
+  int Rh = gauss_taps(m->hs_sigma, D, gh, RMAX);
+  double* a = (double*)malloc(sizeof(double) * plane);
+  double* b = (double*)malloc(sizeof(double) * plane);
+  double* c = (double*)malloc(sizeof(double) * plane);
+  double cu = 0.5 * (Nu - 1), cv = 0.5 * (Nv - 1);
+  if (!transpose) {
+    blur_axis(Nu, Nv, gu, Ru, 0, F, a);
+    blur_axis(Nu, Nv, gv, Rv, 1, a, b);   /* b = F1 */
+    blur_axis(Nu, Nv, gh, Rh, 0, b, a);
+    blur_axis(Nu, Nv, gh, Rh, 1, a, c);   /* c = G_hs F1 */
+    for (int j = 0; j < Nv; ++j)
+      for (int i = 0; i < Nu; ++i) {
+        double u = (i - cu) * D, v = (j - cv) * D, r = sqrt(u * u + v * v);
+        long q = (long)j * Nu + i;
+        Fc[q] = (b[q] + m->hs_amp * c[q]) * (1.0 + m->oar[0] * r + m->oar[1] * r * r);
+      }
+  } else {
+    for (int j = 0; j < Nv; ++j)
+      for (int i = 0; i < Nu; ++i) {
+        double u = (i - cu) * D, v = (j - cv) * D, r = sqrt(u * u + v * v);
+        long q = (long)j * Nu + i;
+        c[q] = F[q] * (1.0 + m->oar[0] * r + m->oar[1] * r * r);
+      }
+    blur_axis(Nu, Nv, gh, Rh, 1, c, a);
+    blur_axis(Nu, Nv, gh, Rh, 0, a, b);
+    for (long q = 0; q < plane; ++q) c[q] += m->hs_amp * b[q];
+    blur_axis(Nu, Nv, gv, Rv, 1, c, a);
+    blur_axis(Nu, Nv, gu, Ru, 0, a, Fc);
+  }
+  free(gu); free(gv); free(gh); free(a); free(b); free(c);
+}
+
 double or_rho_sample(const or_model* m, const double* rho, double x, double y, double z) {
   return trilinear(rho, m->nx, m->ny, m->nz, (x - m->ox) / m->sx, (y - m->oy) / m->sy,
                    (z - m->oz) / m->sz);
@@ -405,6 +495,12 @@ void or_forward_cp(const or_model* m, const double* rho, double gantry_deg, cons
   double* P = P_out ? P_out : (double*)malloc(sizeof(double) * nfan);
   double* Dfan = Dfan_out ? Dfan_out : (double*)malloc(sizeof(double) * nfan);
   or_raster(m, leaves, jaws, F);
+  if (m->fcorr) {
+    double* Fr = (double*)malloc(sizeof(double) * plane);
+    memcpy(Fr, F, sizeof(double) * plane);
+    or_fluence_correct(m, Fr, F, 0);
+    free(Fr);
+  }
   or_ca_depth(m, rho, gantry_deg, z);
   or_wepl(m, rho, gantry_deg, W);
   primary(m, dims, d0, F, W, P);
@@ -504,10 +600,20 @@ void or_backward(const or_model* m, const double* rho, int n_cp, const double* g
       double c = (m->sad / dk) * (m->sad / dk);
       for (long r = 0; r < plane; ++r) A[r] += H[k * plane + r] * c * dd_lookup(m, W[k * plane + r]);
     }
+    /* dL/dMU = calib <A, Fc>; dL/dFc = calib MU A, carried to the aperture fluence by
+     * the corrections' adjoint and then to leaves and jaws */
+    if (m->fcorr) {
+      memcpy(gF, F, sizeof(double) * plane);
+      or_fluence_correct(m, gF, F, 0);
+    }
     double s = 0.0;
     for (long r = 0; r < plane; ++r) s += A[r] * F[r];
     gmu[b] = m->calib * s;
     for (long r = 0; r < plane; ++r) gF[r] = m->calib * mu[b] * A[r];
+    if (m->fcorr) {
+      memcpy(A, gF, sizeof(double) * plane);
+      or_fluence_correct(m, A, gF, 1);
+    }
     or_raster_backward(m, lv, jw, gF, gleaves + (long)b * 2 * m->n_leaf, gjaws + (long)b * 4);
   }
   free(F); free(z); free(W); free(Gh); free(H); free(A); free(gF);

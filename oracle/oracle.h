@@ -55,6 +55,14 @@ typedef struct {
   const double* dd;        /* depth-dose table DD(m * dd_step), m = 0..n_dd-1 */
   double kpoly[4][4];      /* kernel parameters A, a, B, b as cubic polynomials in depth z (mm) */
   double kz_max;           /* depth clamp [0, kz_max] for the kernel parameters, mm */
+  /* fluence corrections (§2.2.2 list), applied to the aperture fluence in this order;
+   * all off when fcorr == 0 */
+  int fcorr;
+  double pen_fwhm_u;       /* source penumbra: Gaussian FWHM along u (leaf travel), mm at the isocentre plane */
+  double pen_fwhm_v;       /* ... and along v (across the leaves, the y jaws), mm */
+  double hs_amp;           /* head scatter: F + hs_amp (G * F), G an isotropic unit-sum Gaussian ... */
+  double hs_sigma;         /* ... of standard deviation hs_sigma, mm */
+  double oar[2];           /* off-axis factor 1 + oar[0] r + oar[1] r^2, r = distance from the central axis, mm */
 } or_model;
 
 /* Fan-grid sizes; returns 0 on success. dims = {Nu, Nv, Nk}. */
@@ -66,6 +74,11 @@ void or_hu_to_density(long n, const double* hu, double* rho, int n_pts, const do
 
 /* One control point: fluence map F [Nv][Nu] (§2.2.2, Eq. 4). */
 void or_raster(const or_model* m, const double* leaves, const double* jaws, double* F);
+
+/* Fluence corrections of §2.2.2 (source penumbra, head scatter, off-axis factor) on one
+ * map [Nv][Nu], out of place; the identity copy when m->fcorr == 0.  transpose != 0
+ * applies the adjoint (the same operators in reverse order). */
+void or_fluence_correct(const or_model* m, const double* F, double* Fc, int transpose);
 
 /* Density sample at a patient-frame point, trilinear with zero padding (§2.2.4). */
 double or_rho_sample(const or_model* m, const double* rho, double x, double y, double z);

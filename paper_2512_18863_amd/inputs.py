@@ -52,11 +52,27 @@ class Machine:
         [0.030, -1e-5, 0.0, 0.0],
     ]))
     kz_max: float = 700.0
+    # fluence corrections (§2.2.2 list), off unless fcorr
+    fcorr: bool = False
+    pen_fwhm_u: float = 0.0               # source penumbra FWHM along the leaf travel, mm
+    pen_fwhm_v: float = 0.0               # ... across the leaves, mm
+    hs_amp: float = 0.0                   # head-scatter amplitude
+    hs_sigma: float = 0.0                 # head-scatter Gaussian sigma, mm
+    oar: tuple = (0.0, 0.0)               # off-axis factor 1 + oar0 r + oar1 r^2 (r in mm)
 
     @property
     def leaf_edges(self) -> np.ndarray:
         L, w = self.n_leaf, self.leaf_width
         return (np.arange(L + 1, dtype=np.float64) - L / 2.0) * w
+
+
+def with_fluence_corrections(m: "Machine") -> "Machine":
+    """The synthetic machine with its fluence corrections switched on: penumbra FWHM
+    3.5 mm (leaf travel) and 4.5 mm (across), 4 % head scatter with sigma 20 mm, and
+    an off-axis rise of +4 % at 100 mm."""
+    import dataclasses
+    return dataclasses.replace(m, fcorr=True, pen_fwhm_u=3.5, pen_fwhm_v=4.5, hs_amp=0.04, hs_sigma=20.0,
+                               oar=(0.0, 4e-6))
 
 
 def synthetic_depth_dose(max_depth: float = 800.0, step: float = 1.0) -> np.ndarray:
