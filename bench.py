@@ -267,6 +267,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-fluence-corr", action="store_true")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from the two counter runs' CSV files and exit")
     ap.add_argument("--counter-run", action="store_true",
@@ -348,6 +349,18 @@ def main():
                          "frac": round(a16 / PEAK_BF16_MFMA_TFLOPS, 4)},
             "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(k16.items())}}}
         del eng16
+    if not args.no_fluence_corr:
+        print("[bench] fp32 with fluence corrections", file=sys.stderr, flush=True)
+        import copy
+        cc = copy.copy(case)
+        cc.machine = inputs.with_fluence_corrections(case.machine)
+        msc, kc, _, engc = run_gpu(cc, "fp32", args.steps, args.warmup, w)
+        out.setdefault("variants", {})["fp32_fluence_corrections"] = {
+            "value": round(n_cp / (msc / 1e3), 3), "ms_per_step": round(msc, 4),
+            "corrections": "penumbra FWHM 3.5/4.5 mm, head scatter 4 % (sigma 20 mm), off-axis +4 % at 100 mm",
+            "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(kc.items())}}
+        del engc
+        torch.cuda.empty_cache()
     if not args.no_learned and os.path.exists(LEARNED_WEIGHTS):
         print("[bench] learned variant", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()

@@ -55,6 +55,7 @@ extern "C" {
 
 #define PDRT_MAX_LEAF_PAIRS 160
 #define PDRT_MAX_TAPS 127
+#define PDRT_MAX_BLUR_RADIUS 64
 
 /* CT grid.  Voxel (i, j, k) has its centre at (ox + i sx, oy + j sy, oz + k sz). */
 typedef struct {
@@ -90,6 +91,20 @@ typedef struct {
   double kpoly[4][4];      /* kernel parameters A, a, B, b as cubics in depth z: c0 + c1 z + c2 z^2 + c3 z^3 */
   double kz_max_mm;        /* depths are clamped to [0, kz_max] before the polynomials */
   int32_t max_cp_batch;    /* control points per internal batch; 0 = the whole plan */
+  /* Fluence corrections (§2.2.2 list), applied in this order to the aperture fluence
+   * (which already carries the transmission); all off when fluence_corr == 0:
+   *   source penumbra  directional Gaussians of FWHM pen_fwhm_mm[0] along u (leaf
+   *                    travel) and pen_fwhm_mm[1] along v;
+   *   head scatter     F + hs_amp G F, G the isotropic Gaussian of hs_sigma_mm;
+   *   off-axis factor  1 + oar[0] r + oar[1] r^2, r = distance (mm) from the central
+   *                    axis at the isocentre plane.
+   * Each Gaussian is sampled at the fan pixel centres, truncated at 3 sigma (at most
+   * PDRT_MAX_BLUR_RADIUS pixels, else PDRT_E_UNSUPPORTED) and normalised to unit sum;
+   * the maps are zero outside the beam-frame grid. */
+  int32_t fluence_corr;
+  double pen_fwhm_mm[2];
+  double hs_amp, hs_sigma_mm;
+  double oar[2];
 } pdrt_kernel_spec;
 
 /* Beam-frame grid of a problem (§2.2.3): Nu x Nv rays, Nk planes, first plane at
@@ -106,10 +121,11 @@ size_t pdrt_workspace_bytes(const pdrt_grid* grid, const pdrt_beam* beam, const 
 
 /* Byte offsets of the intermediates inside the workspace after a forward call
  * (debugging and tests): frame, rho_t ([ny][nx][nz]), F ([B][Nu][Nv]), z ([B][Nk]),
- * P and Dfan ([B][Nk][Nu][Nv]), A ([B][Nu][Nv]), comp; B = control points per batch;
- * the arrays hold the last batch. */
+ * P and Dfan ([B][Nk][Nu][Nv]), A ([B][Nu][Nv]), comp, and the two fluence-correction
+ * scratch maps fc_tmp (2 x [B][Nu][Nv], present only with fluence corrections); B =
+ * control points per batch; the arrays hold the last batch. */
 typedef struct {
-  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, total;
+  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, fc_tmp, total;
   int32_t batch;
 } pdrt_ws_layout;
 int pdrt_workspace_layout(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spec* spec,
@@ -229,18 +245,24 @@ int pdrt_conv3d_backward_weight(const pdrt_vol* vol, int32_t c1, int32_t c2, con
                                 size_t ws_bytes, float* dw, float* db, void* stream);
 /* x[p][16] = (dose[p] * scale[0], rho[p], 0, ..., 0) as bf16; n = D H W. */
 int pdrt_net_input(int32_t n, const float* dose, const float* scale, const float* rho, void* x, void* stream);
+/* Workspace bytes of the two-pass reductions of pdrt_net_scale,
+ * pdrt_net_fallback_stats and the exact form of pdrt_net_input_backward. */
+size_t pdrt_net_reduce_ws_bytes(int32_t n);
 /* Gradient w.r.t. the dose fed to pdrt_net_scale, pdrt_net_input and pdrt_net_head,
  * given gp = dL/dpred (and dx0 = dL/dx from the first convolution's data gradient):
  * ddose[p] = scale[0] (gp[p] + dx0[p][0]) at fixed scale; with dose, pred and argmax
- * (all three, from the same forward) it adds the dependence of scale = 1/max(dose)
- * on the dose at the argmax m:
+ * (all three, from the same forward, and a workspace of pdrt_net_reduce_ws_bytes) it
+ * adds the dependence of scale = 1/max(dose) on the dose at the argmax m:
  *   ddose[m] -= scale[0] (sum_p dose[p] ddose[p] - sum_p gp[p] pred[p]).
- * dose, pred, argmax all NULL: the scale is treated as a constant. */
+ * dose, pred, argmax all NULL: the scale is treated as a constant (ws unused). */
 int pdrt_net_input_backward(int32_t n, const void* dx0, const float* gp, const float* scale, const float* dose,
-                            const float* pred, const int32_t* argmax, float* ddose, void* stream);
+                            const float* pred, const int32_t* argmax, float* ddose, void* ws, size_t ws_bytes,
+                            void* stream);
 /* scale[0] = 1 / max(dose) (1 if no dose is positive); argmax (may be NULL) receives
- * the first index of the maximum, or -1 if no dose is positive. */
-int pdrt_net_scale(int32_t n, const float* dose, float* scale, int32_t* argmax, void* stream);
+ * the first index of the maximum, or -1 if no dose is positive.  ws: device, at
+ * least pdrt_net_reduce_ws_bytes(n). */
+int pdrt_net_scale(int32_t n, const float* dose, float* scale, int32_t* argmax, void* ws, size_t ws_bytes,
+                   void* stream);
 /* out = a * scale[0] (inverse == 0) or a / scale[0] (inverse != 0); out may alias a. */
 int pdrt_scale_by(int32_t n, const float* a, const float* scale, int32_t inverse, float* out, void* stream);
 /* out = a + b over n bf16 elements (out may alias a or b). */
@@ -254,7 +276,8 @@ int pdrt_upsample2(const pdrt_vol* fine, int32_t c, const void* x, void* y, int3
 /* Output head (FP32): pred = dose * scale + hb[0] + hw[0] . x, resid = hb[1] + hw[1] . x. */
 int pdrt_net_head(int32_t n, int32_t c, const void* x, const float* hw, const float* hb, const float* dose,
                   const float* scale, float* pred, float* resid, void* stream);
-/* Backward of the head: dx (bf16) and dhead = (dhw[2][c], dhb[2]); gr may be NULL. */
+/* Backward of the head: dx (bf16) and dhead = (dhw[2][c], dhb[2]); gr may be NULL;
+ * dhead may be NULL (no head-weight gradient; ws is then unused). */
 size_t pdrt_net_head_ws_bytes(int32_t n, int32_t c);
 int pdrt_net_head_backward(int32_t n, int32_t c, const void* x, const float* hw, const float* gp, const float* gr,
                            void* dx, float* ws, size_t ws_bytes, float* dhead, void* stream);
@@ -264,8 +287,10 @@ size_t pdrt_net_loss_ws_bytes(int32_t n);
 int pdrt_net_train_loss(int32_t n, const float* pred, const float* resid, const float* target, const float* tscale,
                         const float* mask, float inv_count, float lam, float* gp, float* gr, float* ws,
                         size_t ws_bytes, float* loss, void* stream);
-/* stats[0] = max pred, stats[1] = max resid over pred >= frac * max pred. */
-int pdrt_net_fallback_stats(int32_t n, const float* pred, const float* resid, float frac, float* stats, void* stream);
+/* stats[0] = max pred, stats[1] = max resid over pred >= frac * max pred (device);
+ * ws: device, at least pdrt_net_reduce_ws_bytes(n). */
+int pdrt_net_fallback_stats(int32_t n, const float* pred, const float* resid, float frac, float* stats, void* ws,
+                            size_t ws_bytes, void* stream);
 /* One Adam update of n FP32 parameters (step t >= 1, bias-corrected). */
 int pdrt_adam_step(size_t n, float* w, const float* g, float* m, float* v, float lr, float beta1, float beta2,
                    float eps, int32_t t, void* stream);

@@ -57,6 +57,8 @@ struct Problem {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+const double kFwhmPerSigma = 2.0 * std::sqrt(2.0 * std::log(2.0));
+
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 int validate(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spec* spec) {
@@ -89,7 +91,34 @@ int validate(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spe
       if (!std::isfinite(spec->kpoly[a][b])) return PDRT_E_INVALID;
   if (!(spec->kz_max_mm >= 0.0) || !std::isfinite(spec->kz_max_mm)) return PDRT_E_INVALID;
   if (spec->max_cp_batch < 0) return PDRT_E_INVALID;
+  if (spec->fluence_corr != 0 && spec->fluence_corr != 1) return PDRT_E_INVALID;
+  if (spec->fluence_corr) {
+    const double sig[3] = {spec->pen_fwhm_mm[0] / kFwhmPerSigma, spec->pen_fwhm_mm[1] / kFwhmPerSigma,
+                           spec->hs_sigma_mm};
+    for (double x : sig)
+      if (!(x >= 0.0) || !std::isfinite(x)) return PDRT_E_INVALID;
+    if (!std::isfinite(spec->hs_amp) || !std::isfinite(spec->oar[0]) || !std::isfinite(spec->oar[1]))
+      return PDRT_E_INVALID;
+    for (double x : sig)
+      if (std::ceil(3.0 * x / spec->lateral_step_mm - 1e-9) > PDRT_MAX_BLUR_RADIUS) return PDRT_E_UNSUPPORTED;
+  }
   return PDRT_OK;
+}
+
+// Unit-sum Gaussian taps sampled at the fan pixel centres, truncated at 3 sigma
+// (one tap of 1 for sigma = 0); computed in double, stored in T.
+template <typename T>
+void gauss_taps(double sigma, double D, BlurTaps<T>* t) {
+  if (!(sigma > 0.0)) {
+    t->R = 0;
+    t->g[0] = T(1);
+    return;
+  }
+  int R = (int)std::ceil(3.0 * sigma / D - 1e-9);
+  double w[2 * PDRT_MAX_BLUR_RADIUS + 1], sum = 0.0;
+  for (int m = -R; m <= R; ++m) sum += (w[m + R] = std::exp(-(m * D) * (m * D) / (2.0 * sigma * sigma)));
+  t->R = R;
+  for (int m = 0; m <= 2 * R; ++m) t->g[m] = (T)(w[m] / sum);
 }
 
 // Beam-frame grid (one reading of §2.2.3, stated with the oracle's): Nu = 2
@@ -144,6 +173,8 @@ int size_problem(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel
   if (with_bwd) off += align256((size_t)B * plane * elem);
   L.comp = off;
   off += align256(nvox * elem);
+  L.fc_tmp = off;
+  if (spec->fluence_corr) off += align256((size_t)2 * B * plane * elem);
   L.total = off;
   return PDRT_OK;
 }
@@ -191,6 +222,24 @@ void make_geo(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_sp
   g->kz_max = (T)spec->kz_max_mm;
   g->L = beam->n_leaf_pairs;
   for (int l = 0; l <= beam->n_leaf_pairs; ++l) g->leaf_edges[l] = (T)beam->leaf_edges_mm[l];
+  g->fcorr = spec->fluence_corr;
+  g->hs_amp = (T)spec->hs_amp;
+  g->oar0 = (T)spec->oar[0];
+  g->oar1 = (T)spec->oar[1];
+}
+
+// The three Gaussians of the fluence corrections: penumbra along u and v, head scatter.
+template <typename T>
+struct FcTaps {
+  BlurTaps<T> pu, pv, hs;
+};
+
+template <typename T>
+void make_fc_taps(const pdrt_kernel_spec* spec, FcTaps<T>* t) {
+  const double D = spec->lateral_step_mm;
+  gauss_taps<T>(spec->pen_fwhm_mm[0] / kFwhmPerSigma, D, &t->pu);
+  gauss_taps<T>(spec->pen_fwhm_mm[1] / kFwhmPerSigma, D, &t->pv);
+  gauss_taps<T>(spec->hs_sigma_mm, D, &t->hs);
 }
 
 #define CHECK_HIP(x)                    \
@@ -244,6 +293,10 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
   T* vol0 = (T*)(w + P.lay.vol0);
   T* vol1 = (T*)(w + P.lay.vol1);
   T* comp = (T*)(w + P.lay.comp);
+  T* t0 = (T*)(w + P.lay.fc_tmp);
+  T* t1 = t0 + (size_t)P.batch * P.Nu * P.Nv;
+  FcTaps<T> fct;
+  if (g.fcorr) make_fc_taps<T>(spec, &fct);
   const T* dd = (const T*)spec->dd;
   const int L = beam->n_leaf_pairs, n_cp = beam->n_cp;
   LAUNCH("frame", launch_frame<T>(g, (const T*)beam->gantry_deg, n_cp, frame, s));
@@ -252,6 +305,14 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
     int nb = n_cp - cp0 < P.batch ? n_cp - cp0 : P.batch;
     const T* fr = frame + 2 * cp0;
     LAUNCH("raster", launch_raster<T>(g, nb, leaves + (size_t)2 * L * cp0, jaws + (size_t)4 * cp0, F, s));
+    if (g.fcorr) {
+      // F1 = G_v G_u F; F <- O (F1 + a G_hv G_hu F1)
+      LAUNCH("fluence_corr", launch_blur<T>(g, nb, 0, fct.pu, F, t0, s));
+      LAUNCH("fluence_corr", launch_blur<T>(g, nb, 1, fct.pv, t0, t1, s));
+      LAUNCH("fluence_corr", launch_blur<T>(g, nb, 0, fct.hs, t1, t0, s));
+      LAUNCH("fluence_corr", launch_blur<T>(g, nb, 1, fct.hs, t0, F, s));
+      LAUNCH("fluence_corr", launch_fcorr_combine<T>(g, nb, g.hs_amp, 1, t1, F, F, s));
+    }
     LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
     LAUNCH("march", launch_march<T>(g, nb, fr, rho_t, F, z, dd, vol0, s));
     LAUNCH(conv_name<T>(g, spec->conv_mode), run_conv<T>(g, spec->conv_mode, nb, z, vol0, vol1, s));
@@ -280,6 +341,10 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
   T* vol1 = (T*)(w + P.lay.vol1);
   T* A = (T*)(w + P.lay.adj);
   T* g_t = (T*)(w + P.lay.comp);  // dose gradient, z fastest
+  T* t0 = (T*)(w + P.lay.fc_tmp);
+  T* t1 = t0 + (size_t)P.batch * P.Nu * P.Nv;
+  FcTaps<T> fct;
+  if (g.fcorr) make_fc_taps<T>(spec, &fct);
   const T* dd = (const T*)spec->dd;
   const int L = beam->n_leaf_pairs, n_cp = beam->n_cp;
   LAUNCH("frame", launch_frame<T>(g, (const T*)beam->gantry_deg, n_cp, frame, s));
@@ -292,6 +357,16 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
     LAUNCH("backproject_adj", launch_backproject_adj<T>(g, nb, fr, g_t, vol0, s));
     LAUNCH(conv_name<T>(g, spec->conv_mode), run_conv<T>(g, spec->conv_mode, nb, z, vol0, vol1, s));
     LAUNCH("march_adj", launch_march_adj<T>(g, nb, fr, rho_t, z, dd, vol1, A, s));
+    if (g.fcorr) {
+      // A <- G_u G_v (X + a G_hu G_hv X), X = O A: the corrections' adjoint, so that
+      // the parameter gradients see dL/d(aperture fluence)
+      LAUNCH("fluence_corr_adj", launch_fcorr_combine<T>(g, nb, T(0), 1, A, A, t0, s));
+      LAUNCH("fluence_corr_adj", launch_blur<T>(g, nb, 1, fct.hs, t0, t1, s));
+      LAUNCH("fluence_corr_adj", launch_blur<T>(g, nb, 0, fct.hs, t1, A, s));
+      LAUNCH("fluence_corr_adj", launch_fcorr_combine<T>(g, nb, g.hs_amp, 0, t0, A, t1, s));
+      LAUNCH("fluence_corr_adj", launch_blur<T>(g, nb, 1, fct.pv, t1, t0, s));
+      LAUNCH("fluence_corr_adj", launch_blur<T>(g, nb, 0, fct.pu, t0, A, s));
+    }
     LAUNCH("param_grad", launch_param_grad<T>(g, nb, leaves + (size_t)2 * L * cp0, jaws + (size_t)4 * cp0, mu + cp0, A,
                                    gleaves + (size_t)2 * L * cp0, gjaws + (size_t)4 * cp0, gmu + cp0, s));
   }
@@ -342,6 +417,7 @@ int pdrt_workspace_layout(const pdrt_grid* grid, const pdrt_beam* beam, const pd
   out->vol1 = P.lay.vol1;
   out->adj = P.lay.adj;
   out->comp = P.lay.comp;
+  out->fc_tmp = P.lay.fc_tmp;
   out->total = P.lay.total;
   out->batch = P.batch;
   return PDRT_OK;

@@ -7,11 +7,14 @@
 // so a 16 x 16 output tile is a GEMM with K-dimension 16 + 2h over input columns.
 // The Toeplitz operand depends only on (p, column step), never on the tile, so a
 // wavefront loads it once per step and streams the input rows of all its tiles
-// past it.  A workgroup owns a region of up to 6 x 6 tiles (96 x 96 outputs) of
-// one (control point, plane); the input region with its halo and the plane's
-// taps are staged in LDS once, then NW wavefronts each run TPW tiles.  The inner
-// loop is branch free and software pipelined: the operands of step t+1 are
-// loaded from LDS before the matrix instructions of step t are issued.
+// past it.  A workgroup owns a region of up to 6 x 6 tiles (96 x 96 outputs) and
+// walks the (control point, plane) items of that region: workgroups are
+// persistent (one per CU and LDS slot), the zero halo of the LDS image is written
+// once, and each item's input is fetched into registers while the previous item's
+// matrix instructions run, so staging costs an LDS write instead of a global-load
+// round trip.  The inner loop is branch free and software pipelined: the operands
+// of step t+1 are loaded from LDS before the matrix instructions of step t are
+// issued.
 //
 //   FP32: v_mfma_f32_16x16x4_f32.  Tap rows p and -p are equal (the kernel is
 //         radially symmetric), so rows i+p and i-p are added before the product
@@ -54,19 +57,75 @@ __device__ __forceinline__ void unique_taps(const Geo<float>& g, int k, float zk
   for (int idx = tid; idx < h1 * h1; idx += nt) kq[idx] = tap_value(tp, idx / h1, idx % h1);
 }
 
-// Stage the input region (rows I0-h .., columns J0-h ..) of one plane; zero
-// outside the plane and beyond `cols_valid`.
-template <typename E>
-__device__ __forceinline__ void stage_tile(const Geo<float>& g, const float* __restrict__ src, int I0, int J0,
-                                           int rows, int pitch, int cols_valid, E* tile, int tid, int nt) {
+// The part of the plane that a region's LDS image holds: rows [r0, r0 + nr) and
+// columns [c0, c0 + nc) of the plane, stored at LDS row r - (I0 - h), column
+// c - (J0 - h).  Everything else in the image is zero and stays zero.
+struct DataRect {
+  int r0, nr, c0, nc;
+  int lr0, lc0;  // LDS row / column of (r0, c0)
+};
+
+__device__ __forceinline__ DataRect data_rect(const Geo<float>& g, int I0, int J0, int out_rows, int out_cols) {
   const int h = g.h;
-  for (int idx = tid; idx < rows * pitch; idx += nt) {
-    int rr = idx / pitch, cc = idx - rr * pitch;
-    int i = I0 - h + rr, j = J0 - h + cc;
+  DataRect d;
+  d.r0 = max(0, I0 - h);
+  d.c0 = max(0, J0 - h);
+  d.nr = max(0, min(g.Nu, I0 + out_rows + h) - d.r0);
+  d.nc = max(0, min(g.Nv, J0 + out_cols + h) - d.c0);
+  d.lr0 = d.r0 - (I0 - h);
+  d.lc0 = d.c0 - (J0 - h);
+  return d;
+}
+
+// Issue the global loads of the first PF * nt elements of one plane's data
+// rectangle into registers (the caller consumes them after other work).
+// (The element index goes through an empty asm statement so that the compiler
+// recomputes the index arithmetic per item instead of keeping PF offsets live
+// across the matrix loop.)
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+template <int PF>
+__device__ __forceinline__ void fetch_rect(const float* __restrict__ src, int Nv, const DataRect& d, int tid, int nt,
+                                           float (&buf)[PF]) {
+  const int area = d.nr * d.nc;
+#pragma unroll
+  for (int e = 0; e < PF; ++e) {
+    const int idx = opaque(tid + e * nt);
     float v = 0.f;
-    if (i >= 0 && i < g.Nu && j >= 0 && j < g.Nv && cc < cols_valid) v = src[(size_t)i * g.Nv + j];
-    tile[idx] = (E)v;
+    if (idx < area) {
+      const int r = idx / d.nc, c = idx - r * d.nc;
+      v = src[(size_t)(d.r0 + r) * Nv + d.c0 + c];
+    }
+    buf[e] = v;
   }
+}
+
+// Write the fetched elements into the LDS image, then load and write whatever
+// lies beyond PF * nt directly.
+template <int PF, typename E>
+__device__ __forceinline__ void put_rect(const float* __restrict__ src, int Nv, const DataRect& d, int pitch,
+                                         int tid, int nt, const float (&buf)[PF], E* tile) {
+  const int area = d.nr * d.nc;
+#pragma unroll
+  for (int e = 0; e < PF; ++e) {
+    const int idx = opaque(tid + e * nt);
+    if (idx < area) {
+      const int r = idx / d.nc, c = idx - r * d.nc;
+      tile[(d.lr0 + r) * pitch + d.lc0 + c] = (E)buf[e];
+    }
+  }
+  for (int idx = tid + PF * nt; idx < area; idx += nt) {
+    const int r = idx / d.nc, c = idx - r * d.nc;
+    tile[(d.lr0 + r) * pitch + d.lc0 + c] = (E)src[(size_t)(d.r0 + r) * Nv + d.c0 + c];
+  }
+}
+
+template <typename E>
+__device__ __forceinline__ void zero_lds(E* p, int n, int tid, int nt) {
+  for (int idx = tid; idx < n; idx += nt) p[idx] = (E)0.f;
 }
 
 template <int TPW>
@@ -120,8 +179,13 @@ static size_t f32_lds(int h, const F32Shape& fs) {
   return sizeof(float) * ((size_t)fs.rows * fs.pitch + (size_t)(h + 1) * fs.E + (size_t)(h + 1) * (h + 1));
 }
 
+constexpr int PF = 12;  // prefetched elements per thread
+
+// Items it = blockIdx.x, blockIdx.x + gridDim.x, ... with region = it % regions
+// and (control point, plane) = it / regions; gridDim.x is a multiple of the
+// region count, so a workgroup keeps one region.
 template <int NW, int TPW>
-__global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionShape rs, F32Shape fs,
+__global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionShape rs, F32Shape fs, int n_items,
                                                            const float* __restrict__ zca,
                                                            const float* __restrict__ in, float* __restrict__ out) {
   extern __shared__ __align__(16) float lds[];
@@ -131,24 +195,13 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
   float* tile = lds;
   float* kx = lds + rows * pitch;  // (h + 1) x E, zero outside |q| <= h, row 0 halved
   float* kq = kx + (h + 1) * E;    // (h + 1) x (h + 1) unique taps
-  const int k = blockIdx.y, b = blockIdx.z;
-  const int I0 = (blockIdx.x / rs.regions_j) * rs.TI * MT;
-  const int J0 = (blockIdx.x % rs.regions_j) * rs.TJ * MT;
-  const int plane = g.Nu * g.Nv;
+  const int nreg = rs.regions_i * rs.regions_j;
+  const int region = blockIdx.x % nreg;
+  const int I0 = (region / rs.regions_j) * rs.TI * MT;
+  const int J0 = (region % rs.regions_j) * rs.TJ * MT;
+  const size_t plane = (size_t)g.Nu * g.Nv;
   const int tid = threadIdx.x;
-
-  stage_tile(g, in + ((size_t)b * g.Nk + k) * plane, I0, J0, rows, pitch, MT * rs.TJ + 2 * h, tile, tid, NT);
-  unique_taps(g, k, zca[(size_t)b * g.Nk + k], kq, tid, NT);
-  __syncthreads();
-  const int off = h + 15;
-  for (int idx = tid; idx < (h + 1) * E; idx += NT) {
-    int p = idx / E, c = idx - p * E;
-    int q = c - off;
-    float v = 0.f;
-    if (q >= -h && q <= h) v = kq[p * (h + 1) + (q < 0 ? -q : q)] * (p == 0 ? 0.5f : 1.f);
-    kx[idx] = v;
-  }
-  __syncthreads();
+  const DataRect dr = data_rect(g, I0, J0, MT * rs.TI, MT * rs.TJ);
 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int m = lane & 15, kk = lane >> 4;
@@ -164,49 +217,76 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
   }
   // B[k][n] of instruction s in super-step u = K[p][16 u + 4 k + s - h - n] = kx[p][16 u + 4 k + s + 15 - n]
   const float* bbase = kx + 4 * kk + 15 - m;
-  f32x4 acc[TPW];
-#pragma unroll
-  for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-
   const int total = (h + 1) * SS;
-  f32x4v an0[TPW], an1[TPW];
-  float bn[4];
-#pragma unroll
-  for (int q = 0; q < TPW; ++q) {
-    an0[q] = *reinterpret_cast<const f32x4v*>(abase[q]);
-    an1[q] = an0[q];
-  }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) bn[e] = bbase[e];
-  int p = 0, u = 0;
-  for (int it = 0; it < total; ++it) {
-    f32x4v ac[TPW];
-    float bc[4];
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) ac[q] = an0[q] + an1[q];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) bc[e] = bn[e];
-    if (++u == SS) {
-      u = 0;
-      ++p;
+  const int off = h + 15;
+
+  zero_lds(tile, rows * pitch, tid, NT);
+  float buf[PF];
+  int it = blockIdx.x;
+  if (it < n_items) fetch_rect<PF>(in + (size_t)(it / nreg) * plane, g.Nv, dr, tid, NT, buf);
+  __syncthreads();
+  for (; it < n_items; it += gridDim.x) {
+    const int bk = it / nreg;  // b * Nk + k
+    const int k = bk % g.Nk;
+    const float* src = in + (size_t)bk * plane;
+    put_rect<PF>(src, g.Nv, dr, pitch, tid, NT, buf, tile);
+    unique_taps(g, k, zca[bk], kq, tid, NT);
+    __syncthreads();
+    for (int idx = tid; idx < (h + 1) * E; idx += NT) {
+      int p = idx / E, c = idx - p * E;
+      int q = c - off;
+      float v = 0.f;
+      if (q >= -h && q <= h) v = kq[p * (h + 1) + (q < 0 ? -q : q)] * (p == 0 ? 0.5f : 1.f);
+      kx[idx] = v;
     }
-    if (it + 1 < total) {
-      const int op = p * pitch + 16 * u, om = 16 * u - p * pitch;
-      const float* br = bbase + p * E + 16 * u;
+    __syncthreads();
+    // next item's input, in flight while this item's matrix work runs
+    const int nx = it + gridDim.x;
+    if (nx < n_items) fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, dr, tid, NT, buf);
+
+    f32x4 acc[TPW];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) bn[e] = br[e];
+    for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4v an0[TPW], an1[TPW];
+    float bn[4];
 #pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        an0[q] = *reinterpret_cast<const f32x4v*>(abase[q] + op);
-        an1[q] = *reinterpret_cast<const f32x4v*>(abase[q] + om);
+    for (int q = 0; q < TPW; ++q) {
+      an0[q] = *reinterpret_cast<const f32x4v*>(abase[q]);
+      an1[q] = an0[q];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bn[e] = bbase[e];
+    int p = 0, u = 0;
+    for (int st = 0; st < total; ++st) {
+      f32x4v ac[TPW];
+      float bc[4];
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) ac[q] = an0[q] + an1[q];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bc[e] = bn[e];
+      if (++u == SS) {
+        u = 0;
+        ++p;
       }
+      if (st + 1 < total) {
+        const int op = p * pitch + 16 * u, om = 16 * u - p * pitch;
+        const float* br = bbase + p * E + 16 * u;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bn[e] = br[e];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+          an0[q] = *reinterpret_cast<const f32x4v*>(abase[q] + op);
+          an1[q] = *reinterpret_cast<const f32x4v*>(abase[q] + om);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[q][e], bc[e], acc[q], 0, 0, 0);
     }
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int q = 0; q < TPW; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[q][e], bc[e], acc[q], 0, 0, 0);
+    store_tiles<TPW>(g, rs, NW, wave, I0, J0, lane, acc, active, out + (size_t)bk * plane);
+    __syncthreads();  // the LDS image and taps are rewritten for the next item
   }
-  store_tiles<TPW>(g, rs, NW, wave, I0, J0, lane, acc, active, out + ((size_t)b * g.Nk + k) * plane);
 }
 
 // ------------------------------------------------------------------ BF16
@@ -232,11 +312,12 @@ struct BF16Shape {
 static BF16Shape bf16_shape(int Nu, int Nv, int h, int rmax) {
   BF16Shape s;
   int ti = (Nu + 31) / 32, tj = (Nv + 31) / 32;
+  s.S = (32 + 2 * h + 15) / 16;
+  const int rj_max = s.S <= 6 ? 3 : 2;  // three tiles per strip only while the registers hold them
   s.RI = ti < rmax ? ti : rmax;
-  s.RJ = tj < 3 ? tj : 3;
+  s.RJ = tj < rj_max ? tj : rj_max;
   s.regions_i = (ti + s.RI - 1) / s.RI;
   s.regions_j = (tj + s.RJ - 1) / s.RJ;
-  s.S = (32 + 2 * h + 15) / 16;
   s.CL = 16 * s.S + 40;
   s.rows = 32 * s.RI + 2 * h;
   s.pitch = 16 * (2 * s.RJ + s.S - 2) + 8;
@@ -247,45 +328,43 @@ __host__ __device__ static size_t bf16_tile_bytes(const BF16Shape& bs) {
   return ((size_t)bs.rows * bs.pitch * 2 + 15) & ~(size_t)15;
 }
 __host__ __device__ static size_t bf16_copy_bytes(int h, const BF16Shape& bs) { return (size_t)(h + 1) * 8 * bs.CL * 2; }
+__host__ __device__ static size_t bf16_taps_bytes(int h, const BF16Shape& bs) {
+  return bf16_copy_bytes(h, bs) + sizeof(float) * (size_t)(h + 1) * (h + 1);
+}
+// one quarter's partial sums (all strips and tiles of the region)
+__host__ __device__ static size_t bf16_part_bytes(const BF16Shape& bs) {
+  return sizeof(float) * (size_t)bs.RI * bs.RJ * 1024;
+}
 static size_t bf16_lds(int h, const BF16Shape& bs) {
-  size_t stage = bf16_tile_bytes(bs) + bf16_copy_bytes(h, bs) + sizeof(float) * (size_t)(h + 1) * (h + 1);
-  size_t partial = sizeof(float) * (size_t)bs.RI * (BQ - 1) * bs.RJ * 1024;
-  return stage > partial ? stage : partial;
+  size_t a = bf16_taps_bytes(h, bs), b = bf16_part_bytes(bs);
+  return bf16_tile_bytes(bs) + (a > b ? a : b);
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// Items as in the FP32 kernel.  LDS: the region's BF16 input image (zero halo
+// written once), then the tap copies, which the quarters' partial sums reuse
+// after the matrix loop (one quarter at a time, added in a fixed order).
 template <int RJ, int SMAX>
-__global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Shape bs,
+__global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Shape bs, int n_items,
                                                             const float* __restrict__ zca,
                                                             const float* __restrict__ in, float* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int NT = 64 * BQ * bs.RI;
+  const int NW = BQ * bs.RI, NT = 64 * NW;
   const int h = g.h;
   const int rows = bs.rows, pitch = bs.pitch, CL = bs.CL, S = bs.S;
   __bf16* tile = reinterpret_cast<__bf16*>(smem_raw);
-  __bf16* bcopy = reinterpret_cast<__bf16*>(smem_raw + bf16_tile_bytes(bs));  // [h+1][8][CL]
-  float* kq = reinterpret_cast<float*>(smem_raw + bf16_tile_bytes(bs) + bf16_copy_bytes(h, bs));
-  const int k = blockIdx.y, b = blockIdx.z;
-  const int I0 = (blockIdx.x / bs.regions_j) * bs.RI * 32;
-  const int J0 = (blockIdx.x % bs.regions_j) * RJ * 32;
-  const int plane = g.Nu * g.Nv;
+  unsigned char* taps_area = smem_raw + bf16_tile_bytes(bs);
+  __bf16* bcopy = reinterpret_cast<__bf16*>(taps_area);  // [h+1][8][CL]
+  float* kq = reinterpret_cast<float*>(taps_area + bf16_copy_bytes(h, bs));
+  float* part = reinterpret_cast<float*>(taps_area);
+  const int nreg = bs.regions_i * bs.regions_j;
+  const int region = blockIdx.x % nreg;
+  const int I0 = (region / bs.regions_j) * bs.RI * 32;
+  const int J0 = (region % bs.regions_j) * RJ * 32;
+  const size_t plane = (size_t)g.Nu * g.Nv;
   const int tid = threadIdx.x;
-
-  stage_tile(g, in + ((size_t)b * g.Nk + k) * plane, I0, J0, rows, pitch, 32 * RJ + 2 * h, tile, tid, NT);
-  unique_taps(g, k, zca[(size_t)b * g.Nk + k], kq, tid, NT);
-  __syncthreads();
-  // Extended tap row x (x = q + h + 31) stored in copy r at position x + sigma_r,
-  // sigma_r = (8 - r) % 8, so that a run starting at x with x % 8 == r is aligned.
-  for (int idx = tid; idx < (h + 1) * 8 * CL; idx += NT) {
-    int p = idx / (8 * CL), rem = idx - p * 8 * CL;
-    int r = rem / CL, y = rem - r * CL;
-    int x = y - ((8 - r) & 7);
-    int q = x - (h + 31);
-    float v = (x >= 0 && q >= -h && q <= h) ? kq[p * (h + 1) + (q < 0 ? -q : q)] : 0.f;
-    bcopy[idx] = (__bf16)v;
-  }
-  __syncthreads();
+  const DataRect dr = data_rect(g, I0, J0, 32 * bs.RI, 32 * RJ);
 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int strip = wave / BQ, quarter = wave - strip * BQ;
@@ -299,64 +378,120 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
   const int p_begin = -h + quarter * per, p_end = min(h + 1, p_begin + per);
   constexpr int NA = 2 * RJ + SMAX - 2;
   const int na = 2 * RJ + S - 2;
-  f32x16 acc[RJ];
-#pragma unroll
-  for (int t = 0; t < RJ; ++t)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
-  for (int p = p_begin; p < p_end; ++p) {
-    const int ap = p < 0 ? -p : p;
-    const __bf16* brow = bbase + ap * 8 * CL;
-    const __bf16* arow = abase + p * pitch;
-    bf16x8 Bf[SMAX];
-    bf16x8 Af[NA];
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s)
-      if (s < S) Bf[s] = *reinterpret_cast<const bf16x8*>(brow + 16 * s);
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-      if (a < na) Af[a] = *reinterpret_cast<const bf16x8*>(arow + 16 * a);
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      if (s < S) {
-#pragma unroll
-        for (int t = 0; t < RJ; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Af[2 * t + s], Bf[s], acc[t], 0, 0, 0);
+  float* my_part = part + (size_t)strip * RJ * 1024;
+
+  zero_lds(tile, rows * pitch, tid, NT);
+  float buf[PF];
+  int it = blockIdx.x;
+  if (it < n_items) fetch_rect<PF>(in + (size_t)(it / nreg) * plane, g.Nv, dr, tid, NT, buf);
+  __syncthreads();
+  for (; it < n_items; it += gridDim.x) {
+    const int bk = it / nreg;
+    const int k = bk % g.Nk;
+    const float* src = in + (size_t)bk * plane;
+    put_rect<PF>(src, g.Nv, dr, pitch, tid, NT, buf, tile);
+    unique_taps(g, k, zca[bk], kq, tid, NT);
+    __syncthreads();
+    // Extended tap row x (x = q + h + 31) stored in copy r at position x + sigma_r,
+    // sigma_r = (8 - r) % 8, so that a run starting at x with x % 8 == r is aligned.
+    for (int row = wave; row < (h + 1) * 8; row += NW) {
+      const int p = row >> 3, r = row & 7;
+      __bf16* dst = bcopy + (size_t)row * CL;
+      for (int y = lane; y < CL; y += 64) {
+        int x = y - ((8 - r) & 7);
+        int q = x - (h + 31);
+        float v = (x >= 0 && q >= -h && q <= h) ? kq[p * (h + 1) + (q < 0 ? -q : q)] : 0.f;
+        dst[y] = (__bf16)v;
       }
     }
-  }
-  // sum the quarters in LDS (the staged operands are dead after this barrier)
-  __syncthreads();
-  float* part = reinterpret_cast<float*>(smem_raw);
-  if (quarter > 0) {
-    float* dstp = part + ((size_t)(strip * (BQ - 1) + quarter - 1) * RJ) * 1024;
+    __syncthreads();
+    const int nx = it + gridDim.x;
+    if (nx < n_items) fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, dr, tid, NT, buf);
+
+    f32x16 acc[RJ];
 #pragma unroll
     for (int t = 0; t < RJ; ++t)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) dstp[t * 1024 + r * 64 + lane] = acc[t][r];
-  }
-  __syncthreads();
-  if (quarter == 0) {
-    float* dst = out + ((size_t)b * g.Nk + k) * plane;
+      for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+    for (int p = p_begin; p < p_end; ++p) {
+      const int ap = p < 0 ? -p : p;
+      const __bf16* brow = bbase + ap * 8 * CL;
+      const __bf16* arow = abase + p * pitch;
+      bf16x8 Bf[SMAX];
 #pragma unroll
-    for (int t = 0; t < RJ; ++t) {
+      for (int s2 = 0; s2 < SMAX; ++s2)
+        if (s2 < S) Bf[s2] = *reinterpret_cast<const bf16x8*>(brow + 16 * s2);
+      // walk the A fragments: fragment a feeds tile t at K-step a - 2 t
 #pragma unroll
-      for (int qd = 1; qd < BQ; ++qd) {
-        const float* src = part + ((size_t)(strip * (BQ - 1) + qd - 1) * RJ + t) * 1024;
+      for (int a = 0; a < NA; ++a) {
+        if (a < na) {
+          const bf16x8 Af = *reinterpret_cast<const bf16x8*>(arow + 16 * a);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[t][r] += src[r * 64 + lane];
-      }
-      const int j = J0 + 32 * t + m;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = I0 + 32 * strip + 8 * (r >> 2) + 4 * hi + (r & 3);
-        if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[t][r];
+          for (int t = 0; t < RJ; ++t) {
+            const int s2 = a - 2 * t;
+            if (s2 >= 0 && s2 < SMAX && s2 < S)
+              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Af, Bf[s2], acc[t], 0, 0, 0);
+          }
+        }
       }
     }
+    // add the quarters 1..3 into quarter 0 through LDS (the taps are dead now)
+    for (int qd = 1; qd < BQ; ++qd) {
+      __syncthreads();
+      if (quarter == qd) {
+#pragma unroll
+        for (int t = 0; t < RJ; ++t)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) my_part[t * 1024 + r * 64 + lane] = acc[t][r];
+      }
+      __syncthreads();
+      if (quarter == 0) {
+#pragma unroll
+        for (int t = 0; t < RJ; ++t)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[t][r] += my_part[t * 1024 + r * 64 + lane];
+      }
+    }
+    if (quarter == 0) {
+      float* dst = out + (size_t)bk * plane;
+#pragma unroll
+      for (int t = 0; t < RJ; ++t) {
+        const int j = J0 + 32 * t + m;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = I0 + 32 * strip + 8 * (r >> 2) + 4 * hi + (r & 3);
+          if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[t][r];
+        }
+      }
+    }
+    __syncthreads();  // the partial sums alias the next item's taps
   }
 }
 
 // ------------------------------------------------------------------ launch
+
+// Persistent grid: as many workgroups as fit on the device at once (a multiple of
+// the region count), never more than there are items.
+static int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+static int persistent_grid(const void* kern, int threads, size_t lds, int nreg, long n_items) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  long want = (long)device_cus() * per_cu;
+  if (want < nreg) want = nreg;
+  want -= want % nreg;
+  return (int)(n_items < want ? n_items : want);
+}
 
 template <int NW, int TPW, typename Shape, typename Kern>
 static hipError_t launch_cfg(Kern kern, const Geo<float>& g, const RegionShape& rs, const Shape& sh, size_t lds,
@@ -368,12 +503,14 @@ static hipError_t launch_cfg(Kern kern, const Geo<float>& g, const RegionShape& 
     attr = true;
   }
   if (lds > LDS_MAX) return hipErrorInvalidConfiguration;
-  dim3 grid(rs.regions_i * rs.regions_j, g.Nk, nb);
-  hipLaunchKernelGGL(kern, grid, dim3(64 * NW), lds, s, g, rs, sh, z, in, out);
+  const int nreg = rs.regions_i * rs.regions_j;
+  const long n_items = (long)nreg * g.Nk * nb;
+  if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;
+  const int grid = persistent_grid((const void*)kern, 64 * NW, lds, nreg, n_items);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, s, g, rs, sh, (int)n_items, z, in, out);
   return hipGetLastError();
 }
 
-// Wavefronts x tiles per wavefront for a region of `tiles` tiles.
 #define PDRT_CONV_DISPATCH(KERN, SHAPE)                                                          \
   int tiles = rs.TI * rs.TJ;                                                                     \
   if (tiles <= 4) return launch_cfg<4, 1>(KERN<4, 1>, g, rs, SHAPE, lds, nb, z, in, out, s);     \
@@ -399,16 +536,21 @@ hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, con
 template <int RJ, int SMAX>
 static hipError_t launch_bf16_cfg(const Geo<float>& g, const BF16Shape& bs, size_t lds, int nb, const float* z,
                                   const float* in, float* out, hipStream_t s) {
+  const void* kern = (const void*)k_conv_mfma_bf16<RJ, SMAX>;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_conv_mfma_bf16<RJ, SMAX>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
     if (e != hipSuccess) return e;
     attr = true;
   }
   if (lds > LDS_MAX) return hipErrorInvalidConfiguration;
-  dim3 grid(bs.regions_i * bs.regions_j, g.Nk, nb);
-  hipLaunchKernelGGL((k_conv_mfma_bf16<RJ, SMAX>), grid, dim3(64 * BQ * bs.RI), lds, s, g, bs, z, in, out);
+  const int nreg = bs.regions_i * bs.regions_j;
+  const long n_items = (long)nreg * g.Nk * nb;
+  if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;
+  const int threads = 64 * BQ * bs.RI;
+  const int grid = persistent_grid(kern, threads, lds, nreg, n_items);
+  hipLaunchKernelGGL((k_conv_mfma_bf16<RJ, SMAX>), dim3(grid), dim3(threads), lds, s, g, bs, (int)n_items, z, in,
+                     out);
   return hipGetLastError();
 }
 
@@ -433,7 +575,7 @@ hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, co
   if (bs.S > 10) return hipErrorInvalidConfiguration;
   if (bs.RJ == 1) return launch_bf16_rj<1>(g, bs, lds, nb, z, in, out, s);
   if (bs.RJ == 2) return launch_bf16_rj<2>(g, bs, lds, nb, z, in, out, s);
-  return launch_bf16_rj<3>(g, bs, lds, nb, z, in, out, s);
+  return launch_bf16_cfg<3, 6>(g, bs, lds, nb, z, in, out, s);
 }
 
 }  // namespace pdrt

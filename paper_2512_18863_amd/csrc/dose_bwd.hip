@@ -27,27 +27,76 @@ __device__ __forceinline__ T overlap_db(T x, T a, T b, T D, T invD) {
 // ------------------------------------------------------------------ adjoint of the back-projection
 
 // Ghat_b = G_b^T g, where G_b is the trilinear back-projection of control point b
-// (§2.2.7), computed in gather form: one wavefront per beam-frame column (k, i),
-// lanes along v.  A voxel contributes to node (k, i, j) iff its continuous indices
-// fall in [k-1, k+1) x [i-1, i+1) x [j-1, j+1); (kappa, iota) depend only on the
-// voxel's (x, y) column, jota is increasing in z.  The wavefront bounds the
-// candidate voxel columns by the rotated box around the trapezoid of beam-frame
-// points with kappa, iota in range, evaluates each candidate with the forward's
-// own index arithmetic, and for each lane walks the few z values whose jota lies
-// in [j-1, j+1).  No atomics: every node is written once, summation order fixed.
+// (§2.2.7), in gather form over tiles of beam-frame columns.  A voxel contributes
+// to node (k, i, j) iff its continuous indices fall in [k-1, k+1) x [i-1, i+1) x
+// [j-1, j+1); (kappa, iota) depend only on the voxel's (x, y) column and jota is
+// increasing in z.  One workgroup owns a tile of BT x BT columns (k, i) of one
+// control point:
+//   A. candidate voxel columns: the rotated box around the trapezoid of beam-frame
+//      points with kappa, iota in the tile's range (plus one), each evaluated with
+//      the forward's own index arithmetic and compacted in scan order;
+//   B. per candidate the z sum T_c[j] = sum_z w_j(z) g(x, y, z) along its column,
+//      once, shared by the up to four tile columns it touches.  The g columns of a
+//      group of candidates are read with coalesced loads that are all in flight
+//      together and parked in LDS before the sums read them;
+//   C. each wavefront owns two rows k of the tile and adds w_k w_i T_c into them,
+//      candidates in list order.
+// No atomics: every sum runs in a fixed order, so the result is deterministic.
 // g_t is the dose gradient in z-fastest order [ny][nx][nz].
-template <typename T, int NCH>
-__global__ void __launch_bounds__(256) k_backproject_adj(Geo<T> g, const T* __restrict__ frame,
+constexpr int BP_BT = 8;      // tile edge (beam-frame columns)
+constexpr int BP_CB = 32;     // candidates whose z sums are held at once
+constexpr int BP_CMAX = 256;  // candidates examined per pass (one per thread)
+constexpr int BP_ZREG = 16;   // g values per lane parked per group (group size x column chunks)
+
+template <typename T, int JS>
+struct BpLds {
+  static constexpr int JC = 64 * JS;  // beam-frame j handled per chunk
+  T tsum[BP_CB * JC];
+  T acc[BP_BT * BP_BT * JC];
+  T zbuf[4 * BP_ZREG * 64];           // per wavefront: a group's g columns
+  T c_wk[BP_CMAX], c_wi[BP_CMAX], c_q[BP_CMAX], c_dq[BP_CMAX];
+  int c_col[BP_CMAX], c_kf[BP_CMAX], c_if[BP_CMAX];
+  int wcount[4];
+};
+
+// z sum of one candidate column for beam-frame j: the z whose jota lies in
+// [j-1, j+1), widened by one voxel each side (the weight is zero outside).
+template <typename T, typename Col>
+__device__ __forceinline__ T z_sum(const Geo<T>& g, int j, T qc, T dqc, Col col) {
+  const T za = ((T(j - 1) - g.cv) * g.lat * dqc - g.rel_oz) * g.inv_sz;
+  const T zb = ((T(j + 1) - g.cv) * g.lat * dqc - g.rel_oz) * g.inv_sz;
+  const int z0 = max(0, (int)dfloor(za) - 1), z1 = min(g.nz - 1, (int)dfloor(zb) + 1);
+  T part = T(0);
+  for (int z = z0; z <= z1; ++z) {
+    const T tz = g.rel_oz + T(z) * g.sz;
+    const T jj = tz * qc * g.inv_lat + g.cv;
+    const T fj = dfloor(jj);
+    const int j0 = (int)fj;
+    const T wj = jj - fj;
+    const T w = j0 == j ? T(1) - wj : (j0 == j - 1 ? wj : T(0));
+    part += w * col(z);
+  }
+  return part;
+}
+
+// ZS = 64-element chunks of a g column parked in LDS (nz <= 64 ZS); ZS = 0 reads
+// the columns straight from global memory (very long columns).
+template <typename T, int JS, int ZS>
+__global__ void __launch_bounds__(256) k_backproject_adj(Geo<T> g, int tiles_i, const T* __restrict__ frame,
                                                          const T* __restrict__ g_t, T* __restrict__ Ghat) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int col = blockIdx.x * 4 + wave;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  BpLds<T, JS>& L = *reinterpret_cast<BpLds<T, JS>*>(smem_raw);
+  constexpr int JC = BpLds<T, JS>::JC;
+  constexpr int G = ZS > 0 ? BP_ZREG / ZS : 1;  // candidates per group
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int b = blockIdx.y;
-  if (col >= g.Nk * g.Nu) return;
-  const int k = col / g.Nu, i = col - k * g.Nu;
+  const int k0 = (blockIdx.x / tiles_i) * BP_BT, i0 = (blockIdx.x % tiles_i) * BP_BT;
+  const int kn = min(BP_BT, g.Nk - k0), in = min(BP_BT, g.Nu - i0);
   const T sn = frame[2 * b], cs = frame[2 * b + 1];
-  // beam-frame box: e = d - SAD in [e_{k-1}, e_{k+1}], lateral l = u d / SAD
-  const T e_lo = g.e0 + T(k - 1) * g.dstep, e_hi = g.e0 + T(k + 1) * g.dstep;
-  const T u_lo = (T(i - 1) - g.cu) * g.lat, u_hi = (T(i + 1) - g.cu) * g.lat;
+  // beam-frame box: e = d - SAD with kappa in [k0-1, k0+kn), lateral l = u d / SAD
+  const T e_lo = g.e0 + T(k0 - 1) * g.dstep, e_hi = g.e0 + T(k0 + kn) * g.dstep;
+  const T u_lo = (T(i0 - 1) - g.cu) * g.lat, u_hi = (T(i0 + in) - g.cu) * g.lat;
   const T s_lo = T(1) + e_lo * g.inv_sad, s_hi = T(1) + e_hi * g.inv_sad;
   const T l_lo = fmin(u_lo * s_lo, u_lo * s_hi), l_hi = fmax(u_hi * s_lo, u_hi * s_hi);
   T xmin = T(1e30), xmax = T(-1e30), ymin = T(1e30), ymax = T(-1e30);
@@ -61,73 +110,170 @@ __global__ void __launch_bounds__(256) k_backproject_adj(Geo<T> g, const T* __re
     ymin = fmin(ymin, Y);
     ymax = fmax(ymax, Y);
   }
-  T* out = Ghat + ((size_t)b * g.Nk + k) * ((size_t)g.Nu * g.Nv) + (size_t)i * g.Nv;
-  // candidate voxel columns: centres inside the box, widened by a rounding margin
-  const T eps = T(1e-3);
+  const T eps = T(1e-3);  // rounding margin (index units); membership uses the forward's arithmetic
   const int x0 = max(0, (int)dfloor(xmin - eps) + 1), x1 = min(g.nx - 1, (int)dfloor(xmax + eps));
   const int y0 = max(0, (int)dfloor(ymin - eps) + 1), y1 = min(g.ny - 1, (int)dfloor(ymax + eps));
-  T acc[NCH];
+  const int bw = x1 - x0 + 1, nbox = (x1 >= x0 && y1 >= y0) ? bw * (y1 - y0 + 1) : 0;
+  // wave w owns tile rows k0 + 2w, k0 + 2w + 1
+  const int r_lo = k0 + 2 * wave, r_hi = min(k0 + kn, r_lo + 2);
+  const size_t plane = (size_t)g.Nu * g.Nv;
+  T* out_b = Ghat + (size_t)b * g.Nk * plane;
+  T* zb_w = L.zbuf + wave * (BP_ZREG * 64);
+
+  for (int jc0 = 0; jc0 < g.Nv; jc0 += JC) {
+    for (int idx = tid; idx < BP_BT * BP_BT * JC; idx += 256) L.acc[idx] = T(0);
+    for (int base = 0; base < nbox; base += BP_CMAX) {
+      // A. candidates among box columns base .. base + 255, compacted in scan order
+      const int idx = base + tid;
+      bool is_cand = false;
+      int col = 0, kf = 0, ifl = 0;
+      T wk = T(0), wi = T(0), q = T(0), dq = T(0);
+      if (idx < nbox) {
+        const int y = y0 + idx / bw, x = x0 + idx % bw;
+        const T tx = g.rel_ox + T(x) * g.sx, ty = g.rel_oy + T(y) * g.sy;
+        FanIdx<T> f = voxel_to_fan(g, sn, cs, tx, ty, T(0));
+        const T fk = dfloor(f.k), fi = dfloor(f.i);
+        kf = (int)fk;
+        ifl = (int)fi;
+        is_cand = kf >= k0 - 1 && kf < k0 + kn && ifl >= i0 - 1 && ifl < i0 + in;
+        wk = f.k - fk;
+        wi = f.i - fi;
+        const T e = -sn * tx + cs * ty;
+        dq = T(1) + e * g.inv_sad;  // d / SAD
+        q = T(1) / dq;              // SAD / d, as in voxel_to_fan
+        col = y * g.nx + x;
+      }
+      const unsigned long long mask = __ballot(is_cand);
+      const int before = __popcll(mask & ((1ull << lane) - 1ull));
+      if (lane == 0) L.wcount[wave] = __popcll(mask);
+      __syncthreads();
+      int off = 0, ncand = 0;
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) acc[c] = T(0);
-  for (int y = y0; y <= y1; ++y) {
-    const T ty = g.rel_oy + T(y) * g.sy;
-    for (int x = x0; x <= x1; ++x) {
-      const T tx = g.rel_ox + T(x) * g.sx;
-      FanIdx<T> f = voxel_to_fan(g, sn, cs, tx, ty, T(0));
-      const T fk = dfloor(f.k), fi = dfloor(f.i);
-      const int k0 = (int)fk, i0 = (int)fi;
-      if ((k0 != k && k0 != k - 1) || (i0 != i && i0 != i - 1)) continue;
-      const T wk = f.k - fk, wi = f.i - fi;
-      const T w2 = (k0 == k ? T(1) - wk : wk) * (i0 == i ? T(1) - wi : wi);
-      const T q = T(1) / (T(1) + (-sn * tx + cs * ty) * g.inv_sad);  // SAD / d, as in voxel_to_fan
-      const T dq = T(1) + (-sn * tx + cs * ty) * g.inv_sad;          // d / SAD
-      const T* gcol = g_t + ((size_t)y * g.nx + x) * g.nz;
+      for (int w = 0; w < 4; ++w) {
+        off += w < wave ? L.wcount[w] : 0;
+        ncand += L.wcount[w];
+      }
+      if (is_cand) {
+        const int c = off + before;
+        L.c_col[c] = col;
+        L.c_kf[c] = kf;
+        L.c_if[c] = ifl;
+        L.c_wk[c] = wk;
+        L.c_wi[c] = wi;
+        L.c_q[c] = q;
+        L.c_dq[c] = dq;
+      }
+      __syncthreads();
+      for (int cb0 = 0; cb0 < ncand; cb0 += BP_CB) {
+        const int cn = min(BP_CB, ncand - cb0);
+        // B. z sums of this batch's candidates: wavefront w takes w, w + 4, ... in groups of G
+        for (int c0 = wave; c0 < cn; c0 += 4 * G) {
+          if (ZS > 0) {
+            T v[G][ZS > 0 ? ZS : 1];
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const int j = 64 * c + lane;
-        if (64 * c >= g.Nv) break;
-        // z with jota in [j-1, j+1), widened by one voxel each side
-        const T za = ((T(j - 1) - g.cv) * g.lat * dq - g.rel_oz) * g.inv_sz;
-        const T zb = ((T(j + 1) - g.cv) * g.lat * dq - g.rel_oz) * g.inv_sz;
-        const int z0 = max(0, (int)dfloor(za) - 1), z1 = min(g.nz - 1, (int)dfloor(zb) + 1);
-        T part = T(0);
-        for (int z = z0; z <= z1; ++z) {
-          const T tz = g.rel_oz + T(z) * g.sz;
-          const T jj = tz * q * g.inv_lat + g.cv;
-          const T fj = dfloor(jj);
-          const int j0 = (int)fj;
-          const T wj = jj - fj;
-          const T w = j0 == j ? T(1) - wj : (j0 == j - 1 ? wj : T(0));
-          part += w * gcol[z];
+            for (int q = 0; q < G; ++q) {
+              const int c = min(c0 + 4 * q, cn - 1);
+              const T* gcol = g_t + (size_t)L.c_col[cb0 + c] * g.nz;
+#pragma unroll
+              for (int s = 0; s < ZS; ++s) v[q][s] = gcol[min(64 * s + lane, g.nz - 1)];
+            }
+#pragma unroll
+            for (int q = 0; q < G; ++q)
+#pragma unroll
+              for (int s = 0; s < ZS; ++s) zb_w[(q * ZS + s) * 64 + lane] = v[q][s];
+            __builtin_amdgcn_wave_barrier();
+          }
+          for (int q = 0; q < G; ++q) {
+            const int c = c0 + 4 * q;
+            if (c >= cn) break;
+            const int cc = cb0 + c;
+            const T qc = L.c_q[cc], dqc = L.c_dq[cc];
+            const T* gcol = g_t + (size_t)L.c_col[cc] * g.nz;
+            const T* zcol = zb_w + q * ZS * 64;
+#pragma unroll
+            for (int s = 0; s < JS; ++s) {
+              const int j = jc0 + 64 * s + lane;
+              T part = T(0);
+              if (j < g.Nv) {
+                if (ZS > 0)
+                  part = z_sum(g, j, qc, dqc, [&](int z) { return zcol[z]; });
+                else
+                  part = z_sum(g, j, qc, dqc, [&](int z) { return gcol[z]; });
+              }
+              L.tsum[c * JC + 64 * s + lane] = part;
+            }
+          }
+          __builtin_amdgcn_wave_barrier();  // the next group overwrites this wavefront's slice
         }
-        acc[c] += w2 * part;
+        __syncthreads();
+        // C. each wavefront adds the batch into its own rows, candidates in order
+        for (int c = 0; c < cn; ++c) {
+          const int cc = cb0 + c;
+          const int ck = L.c_kf[cc];
+          if (ck + 1 < r_lo || ck >= r_hi) continue;
+          const int ci = L.c_if[cc];
+          const T cwk = L.c_wk[cc], cwi = L.c_wi[cc];
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const int k = ck + a;
+            if (k < r_lo || k >= r_hi) continue;
+            const T wkk = a ? cwk : T(1) - cwk;
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) {
+              const int i = ci + bb;
+              if (i < i0 || i >= i0 + in) continue;
+              const T w2 = wkk * (bb ? cwi : T(1) - cwi);
+              T* dst = L.acc + ((k - k0) * BP_BT + (i - i0)) * JC;
+              const T* src = L.tsum + c * JC;
+#pragma unroll
+              for (int s = 0; s < JS; ++s) dst[64 * s + lane] += w2 * src[64 * s + lane];
+            }
+          }
+        }
+        __syncthreads();
       }
     }
+    // write the tile's columns for this j chunk
+    for (int idx = tid; idx < kn * in * JC; idx += 256) {
+      const int node = idx / JC, jl = idx - node * JC;
+      const int kk = node / in, ii = node - kk * in;
+      const int j = jc0 + jl;
+      if (j < g.Nv)
+        out_b[(size_t)(k0 + kk) * plane + (size_t)(i0 + ii) * g.Nv + j] = L.acc[(kk * BP_BT + ii) * JC + jl];
+    }
+    __syncthreads();
   }
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-    const int j = 64 * c + lane;
-    if (j < g.Nv) out[j] = acc[c];
+}
+
+template <typename T, int JS, int ZS>
+static hipError_t launch_bp(const Geo<T>& g, int nb, const T* frame, const T* g_t, T* Ghat, hipStream_t s) {
+  const size_t lds = sizeof(BpLds<T, JS>);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_backproject_adj<T, JS, ZS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
   }
+  const int tiles_i = (g.Nu + BP_BT - 1) / BP_BT, tiles_k = (g.Nk + BP_BT - 1) / BP_BT;
+  dim3 grid(tiles_i * tiles_k, nb);
+  hipLaunchKernelGGL((k_backproject_adj<T, JS, ZS>), grid, dim3(256), lds, s, g, tiles_i, frame, g_t, Ghat);
+  return hipGetLastError();
+}
+
+template <typename T, int JS>
+static hipError_t launch_bp_z(const Geo<T>& g, int nb, const T* frame, const T* g_t, T* Ghat, hipStream_t s) {
+  if (g.nz <= 128) return launch_bp<T, JS, 2>(g, nb, frame, g_t, Ghat, s);
+  if (g.nz <= 256) return launch_bp<T, JS, 4>(g, nb, frame, g_t, Ghat, s);
+  if (g.nz <= 512) return launch_bp<T, JS, 8>(g, nb, frame, g_t, Ghat, s);
+  return launch_bp<T, JS, 0>(g, nb, frame, g_t, Ghat, s);
 }
 
 template <typename T>
 hipError_t launch_backproject_adj(const Geo<T>& g, int nb, const T* frame, const T* g_t, T* Ghat, hipStream_t s) {
-  dim3 grid((g.Nk * g.Nu + 3) / 4, nb);
-  int nch = (g.Nv + 63) / 64;
-  if (nch <= 1)
-    hipLaunchKernelGGL((k_backproject_adj<T, 1>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
-  else if (nch <= 2)
-    hipLaunchKernelGGL((k_backproject_adj<T, 2>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
-  else if (nch <= 4)
-    hipLaunchKernelGGL((k_backproject_adj<T, 4>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
-  else if (nch <= 8)
-    hipLaunchKernelGGL((k_backproject_adj<T, 8>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
-  else if (nch <= 16)
-    hipLaunchKernelGGL((k_backproject_adj<T, 16>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
-  else
-    hipLaunchKernelGGL((k_backproject_adj<T, 64>), grid, dim3(256), 0, s, g, frame, g_t, Ghat);
-  return hipGetLastError();
+  // j chunks of 64 or 128 (FP64: 64, to keep the LDS image small)
+  if (sizeof(T) == 8 || g.Nv <= 64) return launch_bp_z<T, 1>(g, nb, frame, g_t, Ghat, s);
+  return launch_bp_z<T, 2>(g, nb, frame, g_t, Ghat, s);
 }
 
 // ------------------------------------------------------------------ parameter gradients

@@ -205,28 +205,34 @@ __global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ f
   T ds = g.dstep * dsqrt(T(1) + (u * u + v * v) * (g.inv_sad * g.inv_sad));
   const T* zb = zca + (size_t)b * g.Nk;
   T W = T(0), c = T(0), acc = T(0);
-  for (int k = 0; k < g.Nk; ++k) {
-    T e = g.e0 + T(k) * g.dstep;
-    T gk = T(1) + e * g.inv_sad;
-    T Wk;
-    if (g.wepl_mode == PDRT_WEPL_PER_RAY) {
-      T X = g.iso_ix + (-e * sn + gk * ucs) * g.inv_sx;
-      T Y = g.iso_iy + (e * cs + gk * usn) * g.inv_sy;
-      T Z = g.iso_iz + (gk * v) * g.inv_sz;
-      T rho = sample_rho(rho_t, g.nx, g.ny, g.nz, X, Y, Z);
-      T y = rho * ds - c;  // Kahan-compensated running sum
-      T t = W + y;
-      c = (t - W) - y;
-      W = t;
-      Wk = W;
-    } else {
-      Wk = zb[k];
-    }
-    T geo = dd_lookup(tab, g.n_dd, g.inv_dd_step, Wk) / (gk * gk);
+  // one step of the march: the water-equivalent depth Wk of plane k, then the
+  // primary (or, for ADJ, its adjoint) at that plane
+  auto step = [&](int k, T Wk) {
+    const T e = g.e0 + T(k) * g.dstep;
+    const T gk = T(1) + e * g.inv_sad;
+    const T geo = dd_lookup(tab, g.n_dd, g.inv_dd_step, Wk) / (gk * gk);
     if (ADJ)
       acc += vb[(size_t)k * plane] * geo;
     else
       vb[(size_t)k * plane] = Fv * geo;
+  };
+  if (g.wepl_mode == PDRT_WEPL_PER_RAY) {
+#pragma unroll 4
+    for (int k = 0; k < g.Nk; ++k) {
+      const T e = g.e0 + T(k) * g.dstep;
+      const T gk = T(1) + e * g.inv_sad;
+      const T X = g.iso_ix + (-e * sn + gk * ucs) * g.inv_sx;
+      const T Y = g.iso_iy + (e * cs + gk * usn) * g.inv_sy;
+      const T Z = g.iso_iz + (gk * v) * g.inv_sz;
+      const T rho = sample_rho(rho_t, g.nx, g.ny, g.nz, X, Y, Z);
+      const T y = rho * ds - c;  // Kahan-compensated running sum
+      const T t = W + y;
+      c = (t - W) - y;
+      W = t;
+      step(k, W);
+    }
+  } else {
+    for (int k = 0; k < g.Nk; ++k) step(k, zb[k]);
   }
   if (ADJ) A[(size_t)b * plane + r] = acc;
 }
@@ -353,13 +359,23 @@ hipError_t launch_conv_direct(const Geo<T>& g, int nb, const T* z, const T* in, 
 // lanes along z so the 2 x 2 beam-frame columns a wavefront reads are contiguous
 // in v.  The sum over control points uses Neumaier compensation; across batches
 // the running sum lives in `dose` and its compensation in `comp`.
+//
+// Workgroups are numbered so that each of the eight XCDs (which receive
+// workgroups round robin) walks a contiguous range of y slabs: neighbouring voxel
+// columns read the same beam-frame columns, and they then share one L2.
 template <typename T>
-__global__ void __launch_bounds__(256) k_gather(Geo<T> g, int nb, int first, int last, const T* __restrict__ frame,
-                                                const T* __restrict__ mu, const T* __restrict__ Dfan,
-                                                T* __restrict__ dose, T* __restrict__ comp) {
-  int z = blockIdx.x * 64 + (threadIdx.x & 63);
-  int x = blockIdx.y * 4 + (threadIdx.x >> 6);
-  int y = blockIdx.z;
+__global__ void __launch_bounds__(256) k_gather(Geo<T> g, int nb, int first, int last, int zc, int xc,
+                                                const T* __restrict__ frame, const T* __restrict__ mu,
+                                                const T* __restrict__ Dfan, T* __restrict__ dose,
+                                                T* __restrict__ comp) {
+  const int nblk = zc * xc * g.ny;
+  const int per_xcd = (nblk + 7) / 8;
+  const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (w >= nblk) return;
+  const int zq = w % zc, xq = (w / zc) % xc;
+  int z = zq * 64 + (threadIdx.x & 63);
+  int x = xq * 4 + (threadIdx.x >> 6);
+  int y = w / (zc * xc);
   if (z >= g.nz || x >= g.nx) return;
   size_t vox = ((size_t)z * g.ny + y) * g.nx + x;
   T tx = g.rel_ox + T(x) * g.sx, ty = g.rel_oy + T(y) * g.sy, tz = g.rel_oz + T(z) * g.sz;
@@ -369,37 +385,53 @@ __global__ void __launch_bounds__(256) k_gather(Geo<T> g, int nb, int first, int
     c = comp[vox];
   }
   const int plane = g.Nu * g.Nv;
+  // Branch free per control point (clamped addresses, masked weights) and
+  // unrolled, so the loads of several control points are in flight at once; the
+  // terms and the compensated sum keep the order of a masked loop.
+#pragma unroll 4
   for (int b = 0; b < nb; ++b) {
     T sn = frame[2 * b], cs = frame[2 * b + 1];
     FanIdx<T> f = voxel_to_fan(g, sn, cs, tx, ty, tz);
     T fk = dfloor(f.k), fi = dfloor(f.i), fj = dfloor(f.j);
-    int k0 = (int)fk, i0 = (int)fi, j0 = (int)fj;
-    if (k0 < -1 || k0 >= g.Nk || i0 < -1 || i0 >= g.Nu || j0 < -1 || j0 >= g.Nv) continue;
+    // (bitwise & keeps the flags branch free)
+    const bool inside = (fk >= T(-1)) & (fk < T(g.Nk)) & (fi >= T(-1)) & (fi < T(g.Nu)) & (fj >= T(-1)) &
+                        (fj < T(g.Nv));
+    int k0 = inside ? (int)fk : 0, i0 = inside ? (int)fi : 0, j0 = inside ? (int)fj : 0;
     T wk = f.k - fk, wi = f.i - fi, wj = f.j - fj;
     const T* base = Dfan + (size_t)b * g.Nk * plane;
+    const int ja = max(j0, 0), jb = min(j0 + 1, g.Nv - 1);
+    const bool jin0 = j0 >= 0, jin1 = j0 + 1 < g.Nv;
+    T lo[2][2], hi[2][2];
+    bool ok[2][2];
+#pragma unroll
+    for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        const int kk = k0 + dk, ii = i0 + di;
+        ok[dk][di] = (kk >= 0) & (kk < g.Nk) & (ii >= 0) & (ii < g.Nu);
+        const int ck = min(max(kk, 0), g.Nk - 1), ci = min(max(ii, 0), g.Nu - 1);
+        const T* colp = base + (size_t)ck * plane + (size_t)ci * g.Nv;
+        lo[dk][di] = colp[ja];
+        hi[dk][di] = colp[jb];
+      }
     T acc = T(0);
 #pragma unroll
     for (int dk = 0; dk < 2; ++dk) {
-      int kk = k0 + dk;
-      if (kk < 0 || kk >= g.Nk) continue;
-      T wkk = dk ? wk : T(1) - wk;
+      const T wkk = dk ? wk : T(1) - wk;
 #pragma unroll
       for (int di = 0; di < 2; ++di) {
-        int ii = i0 + di;
-        if (ii < 0 || ii >= g.Nu) continue;
-        T wii = di ? wi : T(1) - wi;
-        const T* colp = base + (size_t)kk * plane + (size_t)ii * g.Nv;
-        T a = (j0 >= 0) ? colp[j0] : T(0);
-        T bv = (j0 + 1 < g.Nv) ? colp[j0 + 1] : T(0);
-        acc += wkk * wii * (a + wj * (bv - a));
+        const T wii = di ? wi : T(1) - wi;
+        // masks as 0/1 factors (not selects), so the compiler keeps every load
+        // unconditional and can issue them early; the clamped corners hold finite data
+        const T a = T(jin0) * lo[dk][di];
+        const T bv = T(jin1) * hi[dk][di];
+        acc += T(ok[dk][di]) * (wkk * wii * (a + wj * (bv - a)));
       }
     }
-    T val = mu[b] * acc;
-    T t = s + val;
-    if (fabs(s) >= fabs(val))
-      c += (s - t) + val;
-    else
-      c += (val - t) + s;
+    // outside the beam-frame grid the term is +0, which leaves s and c unchanged
+    const T val = T(inside) * (mu[b] * acc);
+    const T t = s + val;
+    c += fabs(s) >= fabs(val) ? (s - t) + val : (val - t) + s;
     s = t;
   }
   if (last) {
@@ -413,8 +445,12 @@ __global__ void __launch_bounds__(256) k_gather(Geo<T> g, int nb, int first, int
 template <typename T>
 hipError_t launch_gather(const Geo<T>& g, int nb, int first, int last, const T* frame, const T* mu, const T* Dfan,
                          T* dose, T* comp, hipStream_t s) {
-  dim3 grid((g.nz + 63) / 64, (g.nx + 3) / 4, g.ny);
-  hipLaunchKernelGGL(k_gather<T>, grid, dim3(256), 0, s, g, nb, first, last, frame, mu, Dfan, dose, comp);
+  const int zc = (g.nz + 63) / 64, xc = (g.nx + 3) / 4;
+  const long nblk = (long)zc * xc * g.ny;
+  if (nblk > 0x7ffffff0L) return hipErrorInvalidConfiguration;
+  const int grid = (int)((nblk + 7) / 8 * 8);
+  hipLaunchKernelGGL(k_gather<T>, dim3(grid), dim3(256), 0, s, g, nb, first, last, zc, xc, frame, mu, Dfan, dose,
+                     comp);
   return hipGetLastError();
 }
 

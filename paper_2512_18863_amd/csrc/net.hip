@@ -197,6 +197,23 @@ __global__ void k_bias_part(Vol v, int Cout, const __bf16* __restrict__ dY, cons
 }
 
 // dW[i] = sum over splits in order (deterministic).
+// Few outputs, many splits: one block per output, each thread a strided partial
+// sum, then a tree over the block (fixed order).
+__global__ void __launch_bounds__(256) k_reduce_splits_tall(int nsplit, size_t n, const float* __restrict__ part,
+                                                            float* __restrict__ out) {
+  __shared__ float red[256];
+  const size_t i = blockIdx.x;
+  float s = 0.f;
+  for (int k = threadIdx.x; k < nsplit; k += 256) s += part[(size_t)k * n + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
+}
+
 __global__ void k_reduce_splits(int nsplit, size_t n, const float* __restrict__ part, float* __restrict__ out) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -330,7 +347,7 @@ __global__ void __launch_bounds__(256) k_head_bwd(int P, int C, const __bf16* __
     g0 = gp[p];
     g1 = gr ? gr[p] : 0.f;
   }
-  const int np = 2 * C + 2;
+  const int np = part ? 2 * C + 2 : 0;  // no head-weight gradient wanted: skip the partial sums
   for (int j = 0; j < np; ++j) {
     float v = 0.f;
     if (p < P) {
@@ -397,31 +414,68 @@ __global__ void k_adam(size_t n, float* __restrict__ w, const float* __restrict_
 }
 
 // scale[0] = 1 / max(dose) (single block).
-__global__ void __launch_bounds__(1024) k_inv_max(int P, const float* __restrict__ dose, float* __restrict__ scale,
-                                                  int* __restrict__ argmax) {
-  // max with its first index (ties keep the smallest index), one block, fixed order
-  __shared__ float rv[1024];
-  __shared__ int ri[1024];
-  float mx = 0.f;
+// Maximum with its first index (ties keep the smallest index), two passes with
+// fixed order: blocks reduce strided slices into partials, one block reduces
+// those.  Only positive values count (max <= 0 gives index -1).
+constexpr int RED_BLOCKS = 512;
+
+__device__ __forceinline__ void better(float& v, int& i, float v2, int i2) {
+  if (v2 > v || (v2 == v && i2 >= 0 && (i < 0 || i2 < i))) v = v2, i = i2;
+}
+
+__global__ void __launch_bounds__(256) k_max_part(int P, const float* __restrict__ x, float init,
+                                                  const float* __restrict__ gate, float gate_frac,
+                                                  const float* __restrict__ gate_max, float* __restrict__ pv,
+                                                  int* __restrict__ pi) {
+  // values below init do not count; gate (optional): only p with
+  // gate[p] >= gate_frac * gate_max[0] count
+  __shared__ float rv[256];
+  __shared__ int ri[256];
+  const float thr = gate ? gate_frac * gate_max[0] : 0.f;
+  float v = init;
   int im = -1;
-  for (int p = threadIdx.x; p < P; p += 1024) {
-    float d = dose[p];
-    if (d > mx) mx = d, im = p;
+  for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256) {
+    if (gate && !(gate[p] >= thr)) continue;
+    const float d = x[p];
+    if (d > v) v = d, im = p;
   }
-  rv[threadIdx.x] = mx;
+  rv[threadIdx.x] = v;
   ri[threadIdx.x] = im;
   __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (threadIdx.x < off) {
-      float a = rv[threadIdx.x], b = rv[threadIdx.x + off];
-      int ia = ri[threadIdx.x], ib = ri[threadIdx.x + off];
-      if (b > a || (b == a && ib >= 0 && (ia < 0 || ib < ia))) rv[threadIdx.x] = b, ri[threadIdx.x] = ib;
-    }
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) better(rv[threadIdx.x], ri[threadIdx.x], rv[threadIdx.x + off], ri[threadIdx.x + off]);
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    scale[0] = rv[0] > 0.f ? 1.f / rv[0] : 1.f;
-    if (argmax) argmax[0] = rv[0] > 0.f ? ri[0] : -1;
+    pv[blockIdx.x] = rv[0];
+    pi[blockIdx.x] = ri[0];
+  }
+}
+
+// mode 0: scale[0] = 1 / max (1 if no positive value), argmax[0] (may be null);
+// mode 1: out[0] = max (the raw maximum, for the fallback statistics)
+__global__ void __launch_bounds__(256) k_max_final(int nb, const float* __restrict__ pv, const int* __restrict__ pi,
+                                                   int mode, float* __restrict__ out, int* __restrict__ argmax) {
+  __shared__ float rv[256];
+  __shared__ int ri[256];
+  float v = -3.4e38f;
+  int im = -1;
+  for (int b = threadIdx.x; b < nb; b += 256) better(v, im, pv[b], pi[b]);
+  rv[threadIdx.x] = v;
+  ri[threadIdx.x] = im;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) better(rv[threadIdx.x], ri[threadIdx.x], rv[threadIdx.x + off], ri[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (mode == 0) {
+      const bool pos = rv[0] > 0.f;
+      out[0] = pos ? 1.f / rv[0] : 1.f;
+      if (argmax) argmax[0] = pos ? ri[0] : -1;
+    } else {
+      out[0] = rv[0];
+    }
   }
 }
 
@@ -452,20 +506,35 @@ __global__ void k_net_input_bwd(int P, const __bf16* __restrict__ dX0, const flo
 
 // The normalisation s = 1 / max(dose) depends on the dose at its argmax m:
 // ddose[m] -= s (sum_p dose[p] ddose[p] - sum_p gp[p] pred[p]), with ddose the
-// gradient at fixed s.  One block; FP64 sums in a fixed order.
-__global__ void __launch_bounds__(1024) k_scale_adjoint(int P, const float* __restrict__ dose,
+// gradient at fixed s.  FP64 partial sums per block, then one block adds them in
+// a fixed order and updates ddose[m].
+__global__ void __launch_bounds__(256) k_scale_adj_part(int P, const float* __restrict__ dose,
                                                         const float* __restrict__ gp, const float* __restrict__ pred,
-                                                        const float* __restrict__ scale, const int* __restrict__ argmax,
-                                                        float* __restrict__ ddose) {
-  __shared__ double red[1024];
-  const int m = argmax[0];
-  if (m < 0) return;  // zero dose: s is the constant 1 (uniform across the block)
+                                                        const float* __restrict__ ddose, double* __restrict__ part) {
+  __shared__ double red[256];
   double t = 0.0;
-  for (int p = threadIdx.x; p < P; p += 1024)
+  for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256)
     t += (double)dose[p] * (double)ddose[p] - (double)gp[p] * (double)pred[p];
   red[threadIdx.x] = t;
   __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_scale_adj_final(int nb, const double* __restrict__ part,
+                                                         const float* __restrict__ scale, const int* __restrict__ argmax,
+                                                         float* __restrict__ ddose) {
+  __shared__ double red[256];
+  const int m = argmax[0];
+  if (m < 0) return;  // zero dose: s is the constant 1 (uniform across the block)
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) t += part[b];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
@@ -473,35 +542,7 @@ __global__ void __launch_bounds__(1024) k_scale_adjoint(int P, const float* __re
 }
 
 // Fallback statistics: stats[0] = max pred, stats[1] = max resid over voxels with
-// pred >= frac * max pred.  Two single-block passes (fixed order).
-__global__ void __launch_bounds__(1024) k_fallback_stats(int P, const float* __restrict__ pred,
-                                                         const float* __restrict__ resid, float frac,
-                                                         float* __restrict__ stats) {
-  __shared__ float red[1024];
-  float mx = -3.4e38f;
-  for (int p = threadIdx.x; p < P; p += 1024) mx = fmaxf(mx, pred[p]);
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
-    __syncthreads();
-  }
-  const float pmax = red[0];
-  __syncthreads();
-  float rm = -3.4e38f;
-  for (int p = threadIdx.x; p < P; p += 1024)
-    if (pred[p] >= frac * pmax) rm = fmaxf(rm, resid[p]);
-  red[threadIdx.x] = rm;
-  __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    stats[0] = pmax;
-    stats[1] = red[0];
-  }
-}
+// pred >= frac * max pred; each a two-pass maximum (k_max_part / k_max_final).
 
 // ------------------------------------------------------------------ launchers
 
@@ -607,18 +648,44 @@ hipError_t launch_train_loss(int P, const float* pred, const float* resid, const
 }
 
 hipError_t launch_reduce_splits(int nsplit, size_t n, const float* part, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_splits, dim3(nblk(n)), dim3(256), 0, s, nsplit, n, part, out);
+  if (n < 4096 && nsplit >= 64)
+    hipLaunchKernelGGL(k_reduce_splits_tall, dim3((unsigned)n), dim3(256), 0, s, nsplit, n, part, out);
+  else
+    hipLaunchKernelGGL(k_reduce_splits, dim3(nblk(n)), dim3(256), 0, s, nsplit, n, part, out);
   return hipGetLastError();
 }
 
-hipError_t launch_fallback_stats(int P, const float* pred, const float* resid, float frac, float* stats,
+static int red_blocks(int P) {
+  int nb = (int)nblk((size_t)P, 1024);
+  return nb < 1 ? 1 : (nb > RED_BLOCKS ? RED_BLOCKS : nb);
+}
+
+size_t net_reduce_ws_bytes(int P) {
+  (void)P;
+  return (size_t)RED_BLOCKS * (sizeof(double) + sizeof(int)) + 16;
+}
+
+hipError_t launch_fallback_stats(int P, const float* pred, const float* resid, float frac, float* stats, void* ws,
                                  hipStream_t s) {
-  hipLaunchKernelGGL(k_fallback_stats, dim3(1), dim3(1024), 0, s, P, pred, resid, frac, stats);
+  const int nb = red_blocks(P);
+  float* pv = (float*)ws;
+  int* pi = (int*)((char*)ws + RED_BLOCKS * sizeof(double));
+  hipLaunchKernelGGL(k_max_part, dim3(nb), dim3(256), 0, s, P, pred, -3.4e38f, (const float*)nullptr, 0.f,
+                     (const float*)nullptr, pv, pi);
+  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, nb, pv, pi, 1, stats, (int*)nullptr);
+  hipLaunchKernelGGL(k_max_part, dim3(nb), dim3(256), 0, s, P, resid, -3.4e38f, pred, frac, (const float*)stats, pv,
+                     pi);
+  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, nb, pv, pi, 1, stats + 1, (int*)nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_inv_max(int P, const float* dose, float* scale, int* argmax, hipStream_t s) {
-  hipLaunchKernelGGL(k_inv_max, dim3(1), dim3(1024), 0, s, P, dose, scale, argmax);
+hipError_t launch_inv_max(int P, const float* dose, float* scale, int* argmax, void* ws, hipStream_t s) {
+  const int nb = red_blocks(P);
+  float* pv = (float*)ws;
+  int* pi = (int*)((char*)ws + RED_BLOCKS * sizeof(double));
+  hipLaunchKernelGGL(k_max_part, dim3(nb), dim3(256), 0, s, P, dose, 0.f, (const float*)nullptr, 0.f,
+                     (const float*)nullptr, pv, pi);
+  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, nb, pv, pi, 0, scale, argmax);
   return hipGetLastError();
 }
 
@@ -639,8 +706,11 @@ hipError_t launch_net_input_bwd(int P, const __bf16* dX0, const float* gp, const
 }
 
 hipError_t launch_scale_adjoint(int P, const float* dose, const float* gp, const float* pred, const float* scale,
-                                const int* argmax, float* ddose, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_adjoint, dim3(1), dim3(1024), 0, s, P, dose, gp, pred, scale, argmax, ddose);
+                                const int* argmax, float* ddose, void* ws, hipStream_t s) {
+  const int nb = red_blocks(P);
+  double* part = (double*)ws;
+  hipLaunchKernelGGL(k_scale_adj_part, dim3(nb), dim3(256), 0, s, P, dose, gp, pred, (const float*)ddose, part);
+  hipLaunchKernelGGL(k_scale_adj_final, dim3(1), dim3(256), 0, s, nb, (const double*)part, scale, argmax, ddose);
   return hipGetLastError();
 }
 

@@ -76,20 +76,27 @@ int pdrt_net_input(int32_t n, const float* dose, const float* scale, const float
   return PDRT_OK;
 }
 
+size_t pdrt_net_reduce_ws_bytes(int32_t n) { return n < 1 ? 0 : net_reduce_ws_bytes(n); }
+
 int pdrt_net_input_backward(int32_t n, const void* dx0, const float* gp, const float* scale, const float* dose,
-                            const float* pred, const int32_t* argmax, float* ddose, void* stream) {
+                            const float* pred, const int32_t* argmax, float* ddose, void* ws, size_t ws_bytes,
+                            void* stream) {
   if (n < 1 || !dx0 || !gp || !scale || !ddose) return PDRT_E_INVALID;
   const bool exact = dose || pred || argmax;
   if (exact && !(dose && pred && argmax)) return PDRT_E_INVALID;
+  if (exact && (!ws || ws_bytes < net_reduce_ws_bytes(n))) return PDRT_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   PDRT_TIMED("net_input_bwd", s, launch_net_input_bwd(n, (const __bf16*)dx0, gp, scale, ddose, s));
-  if (exact) PDRT_TIMED("scale_adjoint", s, launch_scale_adjoint(n, dose, gp, pred, scale, argmax, ddose, s));
+  if (exact) PDRT_TIMED("scale_adjoint", s, launch_scale_adjoint(n, dose, gp, pred, scale, argmax, ddose, ws, s));
   return PDRT_OK;
 }
 
-int pdrt_net_scale(int32_t n, const float* dose, float* scale, int32_t* argmax, void* stream) {
+int pdrt_net_scale(int32_t n, const float* dose, float* scale, int32_t* argmax, void* ws, size_t ws_bytes,
+                   void* stream) {
   if (n < 1 || !dose || !scale) return PDRT_E_INVALID;
-  PDRT_TIMED("net_scale", (hipStream_t)stream, launch_inv_max(n, dose, scale, argmax, (hipStream_t)stream));
+  if (!ws || ws_bytes < net_reduce_ws_bytes(n)) return PDRT_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  PDRT_TIMED("net_scale", s, launch_inv_max(n, dose, scale, argmax, ws, s));
   return PDRT_OK;
 }
 
@@ -131,11 +138,12 @@ size_t pdrt_net_head_ws_bytes(int32_t n, int32_t c) {
 
 int pdrt_net_head_backward(int32_t n, int32_t c, const void* x, const float* hw, const float* gp, const float* gr,
                            void* dx, float* ws, size_t ws_bytes, float* dhead, void* stream) {
-  if (n < 1 || c < 1 || !x || !hw || !gp || !dx || !dhead) return PDRT_E_INVALID;
-  if (!ws || ws_bytes < pdrt_net_head_ws_bytes(n, c)) return PDRT_E_WORKSPACE;
+  if (n < 1 || c < 1 || !x || !hw || !gp || !dx) return PDRT_E_INVALID;
+  if (dhead && (!ws || ws_bytes < pdrt_net_head_ws_bytes(n, c))) return PDRT_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  PDRT_TIMED("net_head_bwd", s, launch_head_bwd(n, c, (const __bf16*)x, hw, gp, gr, (__bf16*)dx, ws, s));
-  PDRT_TIMED("reduce_splits", s, launch_reduce_splits((n + 255) / 256, (size_t)(2 * c + 2), ws, dhead, s));
+  PDRT_TIMED("net_head_bwd", s, launch_head_bwd(n, c, (const __bf16*)x, hw, gp, gr, (__bf16*)dx, dhead ? ws : nullptr,
+                                                s));
+  if (dhead) PDRT_TIMED("reduce_splits", s, launch_reduce_splits((n + 255) / 256, (size_t)(2 * c + 2), ws, dhead, s));
   return PDRT_OK;
 }
 
@@ -153,9 +161,12 @@ int pdrt_net_train_loss(int32_t n, const float* pred, const float* resid, const 
   return PDRT_OK;
 }
 
-int pdrt_net_fallback_stats(int32_t n, const float* pred, const float* resid, float frac, float* stats, void* stream) {
+int pdrt_net_fallback_stats(int32_t n, const float* pred, const float* resid, float frac, float* stats, void* ws,
+                            size_t ws_bytes, void* stream) {
   if (n < 1 || !pred || !resid || !stats || !std::isfinite(frac)) return PDRT_E_INVALID;
-  PDRT_TIMED("fallback_stats", (hipStream_t)stream, launch_fallback_stats(n, pred, resid, frac, stats, (hipStream_t)stream));
+  if (!ws || ws_bytes < net_reduce_ws_bytes(n)) return PDRT_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  PDRT_TIMED("fallback_stats", s, launch_fallback_stats(n, pred, resid, frac, stats, ws, s));
   return PDRT_OK;
 }
 

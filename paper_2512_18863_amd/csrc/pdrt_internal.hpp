@@ -42,11 +42,21 @@ struct Geo {
   T kz_max;
   int L;
   T leaf_edges[PDRT_MAX_LEAF_PAIRS + 1];
+  // fluence corrections (off when fcorr == 0); the blur taps travel separately
+  int fcorr;
+  T hs_amp, oar0, oar1;
+};
+
+// Unit-sum taps of one Gaussian blur, radius R <= PDRT_MAX_BLUR_RADIUS.
+template <typename T>
+struct BlurTaps {
+  int R;
+  T g[2 * PDRT_MAX_BLUR_RADIUS + 1];
 };
 
 // Workspace layout (byte offsets) plus sizes, computed on the host.
 struct Layout {
-  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, total;
+  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, fc_tmp, total;
   int batch;
 };
 
@@ -76,6 +86,11 @@ hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, co
 template <typename T>
 hipError_t launch_gather(const Geo<T>& g, int nb, int first, int last, const T* frame, const T* mu,
                          const T* Dfan, T* dose, T* comp, hipStream_t s);
+template <typename T>
+hipError_t launch_blur(const Geo<T>& g, int nb, int axis, const BlurTaps<T>& t, const T* in, T* out, hipStream_t s);
+template <typename T>
+hipError_t launch_fcorr_combine(const Geo<T>& g, int nb, T a, int use_oar, const T* x, const T* y, T* out,
+                                hipStream_t s);
 template <typename T>
 hipError_t launch_backproject_adj(const Geo<T>& g, int nb, const T* frame, const T* g_t, T* Ghat, hipStream_t s);
 template <typename T>
@@ -112,11 +127,12 @@ hipError_t launch_train_loss(int P, const float* pred, const float* resid, const
                              const float* mask, float inv_count, float lam, float* gp, float* gr, float* part,
                              hipStream_t s);
 hipError_t launch_reduce_splits(int nsplit, size_t n, const float* part, float* out, hipStream_t s);
-hipError_t launch_fallback_stats(int P, const float* pred, const float* resid, float frac, float* stats,
+hipError_t launch_fallback_stats(int P, const float* pred, const float* resid, float frac, float* stats, void* ws,
                                  hipStream_t s);
-hipError_t launch_inv_max(int P, const float* dose, float* scale, int* argmax, hipStream_t s);
+size_t net_reduce_ws_bytes(int P);
+hipError_t launch_inv_max(int P, const float* dose, float* scale, int* argmax, void* ws, hipStream_t s);
 hipError_t launch_scale_adjoint(int P, const float* dose, const float* gp, const float* pred, const float* scale,
-                                const int* argmax, float* ddose, hipStream_t s);
+                                const int* argmax, float* ddose, void* ws, hipStream_t s);
 hipError_t launch_scale_by(int P, const float* a, const float* scale, int inv, float* out, hipStream_t s);
 hipError_t launch_add_bf16(size_t n, const __bf16* a, const __bf16* b, __bf16* out, hipStream_t s);
 hipError_t launch_net_input_bwd(int P, const __bf16* dX0, const float* gp, const float* scale, float* ddose,

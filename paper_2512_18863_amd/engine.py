@@ -45,12 +45,22 @@ class Spec(ctypes.Structure):
                 ("transmission", ctypes.c_double), ("calib", ctypes.c_double),
                 ("n_dd", ctypes.c_int32), ("dd_step_mm", ctypes.c_double), ("dd", ctypes.c_void_p),
                 ("kpoly", (ctypes.c_double * 4) * 4), ("kz_max_mm", ctypes.c_double),
-                ("max_cp_batch", ctypes.c_int32)]
+                ("max_cp_batch", ctypes.c_int32),
+                ("fluence_corr", ctypes.c_int32), ("pen_fwhm_mm", ctypes.c_double * 2),
+                ("hs_amp", ctypes.c_double), ("hs_sigma_mm", ctypes.c_double), ("oar", ctypes.c_double * 2)]
+
+
+def set_fluence_corrections(s: "Spec", m) -> None:
+    """Copy a machine's fluence-correction parameters into a Spec."""
+    s.fluence_corr = 1 if m.fcorr else 0
+    s.pen_fwhm_mm[:] = [float(m.pen_fwhm_u), float(m.pen_fwhm_v)]
+    s.hs_amp, s.hs_sigma_mm = float(m.hs_amp), float(m.hs_sigma)
+    s.oar[:] = [float(m.oar[0]), float(m.oar[1])]
 
 
 class WsLayout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_size_t) for n in
-                ("frame", "rho_t", "fluence", "depth", "vol0", "vol1", "adj", "comp", "total")] + \
+                ("frame", "rho_t", "fluence", "depth", "vol0", "vol1", "adj", "comp", "fc_tmp", "total")] + \
                [("batch", ctypes.c_int32)]
 
 
@@ -184,6 +194,7 @@ class DoseEngine:
                 s.kpoly[a][c] = float(m.kpoly[a][c])
         s.kz_max_mm = m.kz_max
         s.max_cp_batch = max_cp_batch
+        set_fluence_corrections(s, m)
         self.spec = s
         dims = (ctypes.c_int32 * 3)()
         d0 = ctypes.c_double()

@@ -53,8 +53,9 @@ def _lib():
             "pdrt_conv3d_backward_weight": (ctypes.c_int, [P(Vol), I32, I32, V, V, I32, V, V, I32, V,
                                                            ctypes.c_size_t, V, V, V]),
             "pdrt_net_input": (ctypes.c_int, [I32, V, V, V, V, V]),
-            "pdrt_net_input_backward": (ctypes.c_int, [I32, V, V, V, V, V, V, V, V]),
-            "pdrt_net_scale": (ctypes.c_int, [I32, V, V, V, V]),
+            "pdrt_net_reduce_ws_bytes": (ctypes.c_size_t, [I32]),
+            "pdrt_net_input_backward": (ctypes.c_int, [I32, V, V, V, V, V, V, V, V, ctypes.c_size_t, V]),
+            "pdrt_net_scale": (ctypes.c_int, [I32, V, V, V, V, ctypes.c_size_t, V]),
             "pdrt_scale_by": (ctypes.c_int, [I32, V, V, I32, V, V]),
             "pdrt_add_bf16": (ctypes.c_int, [ctypes.c_size_t, V, V, V, V]),
             "pdrt_pool2": (ctypes.c_int, [P(Vol), I32, V, V, I32, V]),
@@ -65,7 +66,7 @@ def _lib():
             "pdrt_net_loss_ws_bytes": (ctypes.c_size_t, [I32]),
             "pdrt_net_train_loss": (ctypes.c_int, [I32, V, V, V, V, V, ctypes.c_float, ctypes.c_float, V, V, V,
                                                    ctypes.c_size_t, V, V]),
-            "pdrt_net_fallback_stats": (ctypes.c_int, [I32, V, V, ctypes.c_float, V, V]),
+            "pdrt_net_fallback_stats": (ctypes.c_int, [I32, V, V, ctypes.c_float, V, V, ctypes.c_size_t, V]),
             "pdrt_adam_step": (ctypes.c_int, [ctypes.c_size_t, V, V, V, V, ctypes.c_float, ctypes.c_float,
                                               ctypes.c_float, ctypes.c_float, I32, V]),
         }
@@ -158,7 +159,8 @@ class Net3D:
         self.loss = torch.empty(1, **f32)
         self.nsplit = [max(1, n // 4096) for n in self.npos]
         wsz = max(lib.pdrt_conv3d_wgrad_ws_bytes(cout, c1 + c2, self.nsplit[lvl]) for (_, c1, c2, cout, lvl) in LAYERS)
-        wsz = max(wsz, lib.pdrt_net_head_ws_bytes(n0, HEAD_C), lib.pdrt_net_loss_ws_bytes(n0))
+        wsz = max(wsz, lib.pdrt_net_head_ws_bytes(n0, HEAD_C), lib.pdrt_net_loss_ws_bytes(n0),
+                  lib.pdrt_net_reduce_ws_bytes(n0))
         self.ws = torch.empty(wsz // 4 + 1, **f32)
         self.ws_bytes = self.ws.numel() * 4
 
@@ -200,7 +202,8 @@ class Net3D:
         lib, s = _lib(), self._s()
         n0 = self.npos[0]
         self._dose = dose
-        _ck(lib.pdrt_net_scale(n0, _p(dose), _p(self.scale), _p(self.argmax), s), "net_scale")
+        _ck(lib.pdrt_net_scale(n0, _p(dose), _p(self.scale), _p(self.argmax), _p(self.ws), self.ws_bytes, s),
+            "net_scale")
         _ck(lib.pdrt_net_input(n0, _p(dose), _p(self.scale), _p(rho), _p(self.x0), s), "net_input")
         a = self._conv("e1a", self.x0)
         s1 = self._conv("e1b", a)
@@ -245,7 +248,7 @@ class Net3D:
         lib, s = _lib(), self._s()
         n0 = self.npos[0]
         hw, _ = self.head()
-        dhead = self.grads[self.head_off:self.head_off + 2 * HEAD_C + 2]
+        dhead = self.grads[self.head_off:self.head_off + 2 * HEAD_C + 2] if weights else None
         g = self.gbuf
         _ck(lib.pdrt_net_head_backward(n0, HEAD_C, _p(self.act["d1b"]), _p(hw), _p(gp), _p(gr), _p(g["d1b"]),
                                        _p(self.ws), self.ws_bytes, _p(dhead), s), "head_bwd")
@@ -267,7 +270,8 @@ class Net3D:
         self._back("e1a", g["e1a"], self.x0, None, self.gx0 if dose_grad is not None else None, None, weights)
         if dose_grad is not None:
             _ck(lib.pdrt_net_input_backward(n0, _p(self.gx0), _p(gp), _p(self.scale), _p(self._dose), _p(self.pred),
-                                            _p(self.argmax), _p(dose_grad), s), "input_bwd")
+                                            _p(self.argmax), _p(dose_grad), _p(self.ws), self.ws_bytes, s),
+                "input_bwd")
 
     def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         # (the first layer's padding input channels are zero, so their weight gradients
@@ -375,7 +379,8 @@ class LearnedDose:
         lib, s = _lib(), torch.cuda.current_stream().cuda_stream
         self.small.forward(lv, jw, mu, out=self.dsmall.view(*self.shape))
         pred, resid = self.net.forward(self.dsmall, self.small.rho.reshape(-1))
-        _ck(lib.pdrt_net_fallback_stats(self.n, _p(pred), _p(resid), self.cutoff, _p(self.net.stats), s), "stats")
+        _ck(lib.pdrt_net_fallback_stats(self.n, _p(pred), _p(resid), self.cutoff, _p(self.net.stats), _p(self.net.ws),
+                                        self.net.ws_bytes, s), "stats")
         if self.mode == "auto":
             st = self.net.stats.cpu()
             self.fell_back = bool(st[1] > self.threshold * st[0])

@@ -57,6 +57,7 @@ def _structs(case, n_taps=None, conv=E.CONV_FP32, batch=0):
             s.kpoly[a][c] = float(m.kpoly[a][c])
     s.kz_max_mm = m.kz_max
     s.max_cp_batch = batch
+    E.set_fluence_corrections(s, m)
     return g, b, s, edges
 
 
