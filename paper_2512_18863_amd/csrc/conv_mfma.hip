@@ -247,42 +247,43 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     f32x4 acc[TPW];
 #pragma unroll
     for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    f32x4v an0[TPW], an1[TPW];
-    float bn[4];
+    // Two operand sets, loaded alternately one step ahead of their use: the
+    // loop body covers two steps, so no register copies sit between a load and
+    // the matrix instructions it feeds.
+    int lp = 0, lu = 0;  // next step to load: tap row lp, super-step lu
+    auto load = [&](f32x4v (&a0)[TPW], f32x4v (&a1)[TPW], float (&bb)[4]) {
+      const int op = lp * pitch + 16 * lu, om = 16 * lu - lp * pitch;
+      const float* br = bbase + lp * E + 16 * lu;
 #pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-      an0[q] = *reinterpret_cast<const f32x4v*>(abase[q]);
-      an1[q] = an0[q];
-    }
+      for (int e = 0; e < 4; ++e) bb[e] = br[e];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bn[e] = bbase[e];
-    int p = 0, u = 0;
-    for (int st = 0; st < total; ++st) {
+      for (int q = 0; q < TPW; ++q) {
+        a0[q] = *reinterpret_cast<const f32x4v*>(abase[q] + op);
+        a1[q] = *reinterpret_cast<const f32x4v*>(abase[q] + om);
+      }
+      if (++lu == SS) {
+        lu = 0;
+        ++lp;
+      }
+    };
+    auto compute = [&](const f32x4v (&a0)[TPW], const f32x4v (&a1)[TPW], const float (&bb)[4]) {
       f32x4v ac[TPW];
-      float bc[4];
 #pragma unroll
-      for (int q = 0; q < TPW; ++q) ac[q] = an0[q] + an1[q];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) bc[e] = bn[e];
-      if (++u == SS) {
-        u = 0;
-        ++p;
-      }
-      if (st + 1 < total) {
-        const int op = p * pitch + 16 * u, om = 16 * u - p * pitch;
-        const float* br = bbase + p * E + 16 * u;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) bn[e] = br[e];
-#pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-          an0[q] = *reinterpret_cast<const f32x4v*>(abase[q] + op);
-          an1[q] = *reinterpret_cast<const f32x4v*>(abase[q] + om);
-        }
-      }
+      for (int q = 0; q < TPW; ++q) ac[q] = a0[q] + a1[q];
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int q = 0; q < TPW; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[q][e], bc[e], acc[q], 0, 0, 0);
+        for (int q = 0; q < TPW; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[q][e], bb[e], acc[q], 0, 0, 0);
+    };
+    f32x4v x0[TPW], x1[TPW], y0[TPW], y1[TPW];
+    float bx[4], by[4];
+    load(x0, x1, bx);
+    for (int st = 0; st < total; st += 2) {
+      const bool two = st + 1 < total;
+      if (two) load(y0, y1, by);
+      compute(x0, x1, bx);
+      if (st + 2 < total) load(x0, x1, bx);
+      if (two) compute(y0, y1, by);
     }
     store_tiles<TPW>(g, rs, NW, wave, I0, J0, lane, acc, active, out + (size_t)bk * plane);
     __syncthreads();  // the LDS image and taps are rewritten for the next item
@@ -394,14 +395,21 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
     __syncthreads();
     // Extended tap row x (x = q + h + 31) stored in copy r at position x + sigma_r,
     // sigma_r = (8 - r) % 8, so that a run starting at x with x % 8 == r is aligned.
+    // (written as bf16 pairs: CL is even)
     for (int row = wave; row < (h + 1) * 8; row += NW) {
       const int p = row >> 3, r = row & 7;
-      __bf16* dst = bcopy + (size_t)row * CL;
-      for (int y = lane; y < CL; y += 64) {
-        int x = y - ((8 - r) & 7);
-        int q = x - (h + 31);
-        float v = (x >= 0 && q >= -h && q <= h) ? kq[p * (h + 1) + (q < 0 ? -q : q)] : 0.f;
-        dst[y] = (__bf16)v;
+      unsigned* dst = reinterpret_cast<unsigned*>(bcopy + (size_t)row * CL);
+      for (int y2 = lane; 2 * y2 < CL; y2 += 64) {
+        unsigned packed = 0;
+#pragma unroll
+        for (int hlf = 0; hlf < 2; ++hlf) {
+          const int x = 2 * y2 + hlf - ((8 - r) & 7);
+          const int q = x - (h + 31);
+          const float v = (x >= 0 && q >= -h && q <= h) ? kq[p * (h + 1) + (q < 0 ? -q : q)] : 0.f;
+          const __bf16 bv = (__bf16)v;
+          packed |= (unsigned)(*reinterpret_cast<const unsigned short*>(&bv)) << (16 * hlf);
+        }
+        dst[y2] = packed;
       }
     }
     __syncthreads();
@@ -438,18 +446,25 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
     // add the quarters 1..3 into quarter 0 through LDS (the taps are dead now)
     for (int qd = 1; qd < BQ; ++qd) {
       __syncthreads();
+      // layout [t][r / 4][lane][r % 4]: each lane moves 16-byte runs, lanes contiguous
       if (quarter == qd) {
 #pragma unroll
         for (int t = 0; t < RJ; ++t)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) my_part[t * 1024 + r * 64 + lane] = acc[t][r];
+          for (int r4 = 0; r4 < 4; ++r4)
+            *reinterpret_cast<f32x4*>(my_part + t * 1024 + r4 * 256 + 4 * lane) =
+                f32x4{acc[t][4 * r4], acc[t][4 * r4 + 1], acc[t][4 * r4 + 2], acc[t][4 * r4 + 3]};
       }
       __syncthreads();
       if (quarter == 0) {
 #pragma unroll
         for (int t = 0; t < RJ; ++t)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) acc[t][r] += my_part[t * 1024 + r * 64 + lane];
+          for (int r4 = 0; r4 < 4; ++r4) {
+            const f32x4 v = *reinterpret_cast<const f32x4*>(my_part + t * 1024 + r4 * 256 + 4 * lane);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[t][4 * r4 + e] += v[e];
+          }
       }
     }
     if (quarter == 0) {
