@@ -249,6 +249,11 @@ void make_fc_taps(const pdrt_kernel_spec* spec, FcTaps<T>* t) {
 
 #define LAUNCH(name, x) PDRT_TIMED(name, s, x)
 
+// Smallest kernel taken by the FP32 matrix-core convolution: below it the Toeplitz
+// operand is mostly padding (a 9-tap row fills 9 of 32 columns) and the direct
+// convolution is faster.
+constexpr int kMfmaMinTaps = 13;
+
 template <typename T>
 hipError_t run_conv(const Geo<T>& g, int conv_mode, int nb, const T* z, const T* in, T* out, hipStream_t s);
 
@@ -262,7 +267,7 @@ template <>
 hipError_t run_conv<float>(const Geo<float>& g, int conv_mode, int nb, const float* z, const float* in, float* out,
                            hipStream_t s) {
   if (conv_mode == PDRT_CONV_BF16) return launch_conv_mfma_bf16(g, nb, z, in, out, s);
-  if (g.n_taps >= 13) return launch_conv_mfma_f32(g, nb, z, in, out, s);
+  if (g.n_taps >= kMfmaMinTaps) return launch_conv_mfma_f32(g, nb, z, in, out, s);
   return launch_conv_direct<float>(g, nb, z, in, out, s);
 }
 
@@ -270,7 +275,7 @@ template <typename T>
 const char* conv_name(const Geo<T>& g, int conv_mode) {
   if (sizeof(T) == 8) return "conv_direct_f64";
   if (conv_mode == PDRT_CONV_BF16) return "conv_mfma_bf16";
-  return g.n_taps >= 13 ? "conv_mfma_f32" : "conv_direct_f32";
+  return g.n_taps >= kMfmaMinTaps ? "conv_mfma_f32" : "conv_direct_f32";
 }
 
 template <typename T>

@@ -30,120 +30,173 @@ __device__ __forceinline__ bool neighbour(const Vol& v, int p, int tap, int* q) 
   return true;
 }
 
-__device__ __forceinline__ bool neighbour_back(const Vol& v, int p, int tap, int* q) {
-  int w = p % v.W, t = p / v.W;
-  int h = t % v.H, d = t / v.H;
-  int dd = d - (tap / 9 - 1), hh = h - ((tap / 3) % 3 - 1), ww = w - (tap % 3 - 1);
-  if (dd < 0 || dd >= v.D || hh < 0 || hh >= v.H || ww < 0 || ww >= v.W) return false;
-  *q = (dd * v.H + hh) * v.W + ww;
-  return true;
-}
+// ------------------------------------------------------------------ forward and data gradient
+//
+// Implicit GEMM on v_mfma_f32_16x16x32_bf16 over a tile of 16 (w) x 4 (h) x
+// 2 (d) output positions per workgroup: the input tile with its one-voxel halo
+// is read from global memory once and kept in LDS (every position's 27
+// neighbours are then LDS reads); the weights, shared by every workgroup, are
+// read from global memory (cache resident) one K step ahead of their use.  M = 16 positions along w, N = 16 output channels per tile, K
+// runs over (tap, input channel) in steps of 32, lane group kq holding 8
+// consecutive channels of one tap; each lane tracks its (tap, channel)
+// incrementally.  Each of the 4 wavefronts owns two position rows and all N.
+// The data gradient is the same GEMM with the taps mirrored, K over (tap,
+// output channel), the ReLU mask applied while the tile is staged.
 
-// ------------------------------------------------------------------ forward
-
-// One wavefront: 16 consecutive positions x all NT*16 output channels.
-template <int NT>
-__global__ void __launch_bounds__(256) k_conv3d_fwd(Vol v, int C1, int C2, const __bf16* __restrict__ X1,
-                                                    const __bf16* __restrict__ X2, const __bf16* __restrict__ Wt,
-                                                    int Kp, const float* __restrict__ bias, int relu,
-                                                    __bf16* __restrict__ Y) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int P = v.D * v.H * v.W;
-  const int p0 = (blockIdx.x * 4 + wave) * 16;
-  if (p0 >= P) return;
-  const int Cin = C1 + C2, Cout = NT * 16;
-  const int m = lane & 15, kq = lane >> 4;
-  const int p = p0 + m;
-  const int K = 27 * Cin;
-  nf32x4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = nf32x4{0.f, 0.f, 0.f, 0.f};
-  const nbf16x8 zero8 = {};
-  const int nsteps = Kp / 32;  // the same trip count for every lane
-  for (int st = 0; st < nsteps; ++st) {
-    const int k0 = 32 * st + 8 * kq;
-    nbf16x8 a = zero8;
-    if (k0 < K && p < P) {
-      int tap = k0 / Cin, ci = k0 - tap * Cin, q;
-      if (neighbour(v, p, tap, &q)) {
-        const __bf16* src = ci < C1 ? X1 + (size_t)q * C1 + ci : X2 + (size_t)q * C2 + (ci - C1);
-        a = *reinterpret_cast<const nbf16x8*>(src);
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      nbf16x8 b = *reinterpret_cast<const nbf16x8*>(Wt + (size_t)(16 * t + m) * Kp + k0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = 16 * t + m;
-    const float bb = bias[co];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int pp = p0 + 4 * kq + r;
-      if (pp < P) {
-        float y = acc[t][r] + bb;
-        if (relu) y = y > 0.f ? y : 0.f;
-        Y[(size_t)pp * Cout + co] = (__bf16)y;
+// A lane's position in K: tap (td, th, tw) in {0,1,2}^3 and channel ci < C.
+struct KPos {
+  int ci, tap, td, th, tw;
+  __device__ void next_tap() {
+    ++tap;
+    if (++tw == 3) {
+      tw = 0;
+      if (++th == 3) {
+        th = 0;
+        ++td;
       }
     }
   }
-}
+  __device__ void advance(int add, int C) {  // ci += add (add <= 32, C >= 16: at most two taps)
+    ci += add;
+    if (ci >= C) {
+      ci -= C;
+      next_tap();
+    }
+    if (ci >= C) {
+      ci -= C;
+      next_tap();
+    }
+  }
+};
 
-// ------------------------------------------------------------------ data gradient
+constexpr int CT_W = 16, CT_H = 4, CT_D = 2;                          // output tile
+constexpr int CT_HW = CT_W + 2, CT_HH = CT_H + 2, CT_HD = CT_D + 2;   // with halo
+constexpr int CT_POS = CT_HW * CT_HH * CT_HD;
+
+struct ConvIO {
+  const __bf16* a1;      // input, channels [0, c1)
+  const __bf16* a2;      // input, channels [c1, c1 + c2) (may be null when c2 == 0)
+  int c1, c2;
+  const __bf16* mask;    // optional (c2 == 0): a1 counts only where mask > 0
+  const __bf16* w;       // weights [N][Kp], K = 27 (c1 + c2)
+  int Kp;
+  const float* bias;     // optional
+  int relu;
+  __bf16* o1;            // output channels [0, n1)
+  __bf16* o2;            // output channels [n1, N)
+  int n1;
+  int mirror;            // taps mirrored (data gradient)
+};
+
+__host__ __device__ static inline size_t conv_tile_lds(int cin) { return (size_t)CT_POS * (cin + 8) * 2; }
 
 template <int NT>
-__global__ void __launch_bounds__(256) k_conv3d_dgrad(Vol v, int Cout, const __bf16* __restrict__ dY,
-                                                      const __bf16* __restrict__ Yact, const __bf16* __restrict__ Wd,
-                                                      int Kp, int C1, __bf16* __restrict__ dX1,
-                                                      __bf16* __restrict__ dX2) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int P = v.D * v.H * v.W;
-  const int p0 = (blockIdx.x * 4 + wave) * 16;
-  if (p0 >= P) return;
-  const int Cin = NT * 16, C2 = Cin - C1;
-  const int m = lane & 15, kq = lane >> 4;
-  const int p = p0 + m;
-  const int K = 27 * Cout;
-  nf32x4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = nf32x4{0.f, 0.f, 0.f, 0.f};
-  const nbf16x8 zero8 = {};
-  const int nsteps = Kp / 32;
-  for (int st = 0; st < nsteps; ++st) {
-    const int k0 = 32 * st + 8 * kq;
-    nbf16x8 a = zero8;
-    if (k0 < K && p < P) {
-      int tap = k0 / Cout, co = k0 - tap * Cout, q;
-      if (neighbour_back(v, p, tap, &q)) {
-        a = *reinterpret_cast<const nbf16x8*>(dY + (size_t)q * Cout + co);
-        if (Yact) {
-          nbf16x8 y = *reinterpret_cast<const nbf16x8*>(Yact + (size_t)q * Cout + co);
+__global__ void __launch_bounds__(256) k_conv3d_tiled(Vol v, ConvIO io) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int Cin = io.c1 + io.c2, N = NT * 16, CinP = Cin + 8;
+  __bf16* tin = reinterpret_cast<__bf16*>(smem_raw);                  // [CT_POS][CinP]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_w = (v.W + CT_W - 1) / CT_W, tiles_h = (v.H + CT_H - 1) / CT_H;
+  const int w0 = (blockIdx.x % tiles_w) * CT_W;
+  const int h0 = ((blockIdx.x / tiles_w) % tiles_h) * CT_H;
+  const int d0 = (blockIdx.x / (tiles_w * tiles_h)) * CT_D;
+  // stage the input tile with halo (zero outside the volume), 8 channels per load
+  const int CG = Cin / 8;
+  for (int idx = tid; idx < CT_POS * CG; idx += 256) {
+    const int pos = idx / CG, g = idx - pos * CG;
+    const int pw = pos % CT_HW, ph = (pos / CT_HW) % CT_HH, pd = pos / (CT_HW * CT_HH);
+    const int ww = w0 - 1 + pw, hh = h0 - 1 + ph, dd = d0 - 1 + pd;
+    nbf16x8 val = nbf16x8{};
+    if (ww >= 0 && ww < v.W && hh >= 0 && hh < v.H && dd >= 0 && dd < v.D) {
+      const size_t q = ((size_t)dd * v.H + hh) * v.W + ww;
+      const int c = 8 * g;
+      if (c < io.c1) {
+        val = *reinterpret_cast<const nbf16x8*>(io.a1 + q * io.c1 + c);
+        if (io.mask) {
+          const nbf16x8 mk = *reinterpret_cast<const nbf16x8*>(io.mask + q * io.c1 + c);
 #pragma unroll
           for (int e = 0; e < 8; ++e)
-            if (!((float)y[e] > 0.f)) a[e] = (__bf16)0.f;
+            if (!((float)mk[e] > 0.f)) val[e] = (__bf16)0.f;
         }
+      } else {
+        val = *reinterpret_cast<const nbf16x8*>(io.a2 + q * io.c2 + (c - io.c1));
       }
     }
+    *reinterpret_cast<nbf16x8*>(tin + (size_t)pos * CinP + 8 * g) = val;
+  }
+  const int m = lane & 15, kq = lane >> 4;
+  // this wavefront's two position rows: (h, d) = (mt % CT_H, mt / CT_H), w = w0 + m
+  int base[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int mt = 2 * wave + r;
+    base[r] = ((mt / CT_H + 1) * CT_HH + (mt % CT_H + 1)) * CT_HW + (m + 1);
+  }
+  const int sgn = io.mirror ? -1 : 1;
+  KPos kp{0, 0, 0, 0, 0};
+  kp.advance(8 * kq, Cin);
+  nf32x4 acc[2][NT];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[r][t] = nf32x4{0.f, 0.f, 0.f, 0.f};
+  __syncthreads();  // the tile is staged
+  // K loop: A from the LDS tile, B (weights, shared by every workgroup and so
+  // cache resident) straight from global memory, one step ahead of its use
+  // (two operand sets, alternating)
+  const int nsteps = io.Kp / 32;
+  const __bf16* wrow[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) wrow[t] = io.w + (size_t)(16 * t + m) * io.Kp + 8 * kq;
+  int kb = 0;
+  auto load_b = [&](nbf16x8 (&b)[NT]) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) b[t] = *reinterpret_cast<const nbf16x8*>(wrow[t] + kb);
+    kb += 32;
+  };
+  auto step = [&](const nbf16x8 (&b)[NT]) {
+    const int off = ((sgn * (kp.td - 1)) * CT_HH + sgn * (kp.th - 1)) * CT_HW + sgn * (kp.tw - 1);
+    const bool kin = kp.tap < 27;
+    nbf16x8 a[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+      a[r] = kin ? *reinterpret_cast<const nbf16x8*>(tin + (size_t)(base[r] + off) * CinP + kp.ci) : nbf16x8{};
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[t], acc[r][t], 0, 0, 0);
+    kp.advance(32, Cin);
+  };
+  nbf16x8 bx[NT], by[NT];
+  load_b(bx);
+  for (int st = 0; st < nsteps; st += 2) {
+    const bool two = st + 1 < nsteps;
+    if (two) load_b(by);
+    step(bx);
+    if (st + 2 < nsteps) load_b(bx);
+    if (two) step(by);
+  }
+  // write: row r, lane (m = channel within the tile, kq) holds positions w0 + 4 kq + e
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int mt = 2 * wave + r;
+    const int hh = h0 + mt % CT_H, dd = d0 + mt / CT_H;
+    if (hh >= v.H || dd >= v.D) continue;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      nbf16x8 b = *reinterpret_cast<const nbf16x8*>(Wd + (size_t)(16 * t + m) * Kp + k0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-    }
-  }
+      const int co = 16 * t + m;
+      const float bb = io.bias ? io.bias[co] : 0.f;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int ci = 16 * t + m;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int pp = p0 + 4 * kq + r;
-      if (pp < P) {
-        if (ci < C1)
-          dX1[(size_t)pp * C1 + ci] = (__bf16)acc[t][r];
+      for (int e = 0; e < 4; ++e) {
+        const int ww = w0 + 4 * kq + e;
+        if (ww >= v.W) continue;
+        const size_t q = ((size_t)dd * v.H + hh) * v.W + ww;
+        float y = acc[r][t][e] + bb;
+        if (io.relu) y = y > 0.f ? y : 0.f;
+        if (co < io.n1)
+          io.o1[q * io.n1 + co] = (__bf16)y;
         else
-          dX2[(size_t)pp * C2 + (ci - C1)] = (__bf16)acc[t][r];
+          io.o2[q * (N - io.n1) + (co - io.n1)] = (__bf16)y;
       }
     }
   }
@@ -548,32 +601,43 @@ __global__ void __launch_bounds__(256) k_scale_adj_final(int nb, const double* _
 
 static unsigned nblk(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-hipError_t launch_conv3d_fwd(Vol v, int C1, int C2, const __bf16* X1, const __bf16* X2, int Cout,
-                             const __bf16* Wt, int Kp, const float* bias, int relu, __bf16* Y, hipStream_t s) {
-  size_t P = (size_t)v.D * v.H * v.W;
-  dim3 grid(nblk(P, 64));
-  switch (Cout / 16) {
-    case 1: hipLaunchKernelGGL(k_conv3d_fwd<1>, grid, dim3(256), 0, s, v, C1, C2, X1, X2, Wt, Kp, bias, relu, Y); break;
-    case 2: hipLaunchKernelGGL(k_conv3d_fwd<2>, grid, dim3(256), 0, s, v, C1, C2, X1, X2, Wt, Kp, bias, relu, Y); break;
-    case 4: hipLaunchKernelGGL(k_conv3d_fwd<4>, grid, dim3(256), 0, s, v, C1, C2, X1, X2, Wt, Kp, bias, relu, Y); break;
+template <int NT>
+static hipError_t launch_tiled(Vol v, ConvIO io, hipStream_t s) {
+  const size_t lds = conv_tile_lds(io.c1 + io.c2);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_conv3d_tiled<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const unsigned tiles = (unsigned)(((v.W + CT_W - 1) / CT_W) * ((v.H + CT_H - 1) / CT_H) * ((v.D + CT_D - 1) / CT_D));
+  hipLaunchKernelGGL(k_conv3d_tiled<NT>, dim3(tiles), dim3(256), lds, s, v, io);
+  return hipGetLastError();
+}
+
+static hipError_t launch_tiled_n(Vol v, const ConvIO& io, int n, hipStream_t s) {
+  switch (n / 16) {
+    case 1: return launch_tiled<1>(v, io, s);
+    case 2: return launch_tiled<2>(v, io, s);
+    case 3: return launch_tiled<3>(v, io, s);
+    case 4: return launch_tiled<4>(v, io, s);
+    case 6: return launch_tiled<6>(v, io, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+}
+
+hipError_t launch_conv3d_fwd(Vol v, int C1, int C2, const __bf16* X1, const __bf16* X2, int Cout,
+                             const __bf16* Wt, int Kp, const float* bias, int relu, __bf16* Y, hipStream_t s) {
+  ConvIO io{X1, X2, C1, C2, nullptr, Wt, Kp, bias, relu, Y, nullptr, Cout, 0};
+  return launch_tiled_n(v, io, Cout, s);
 }
 
 hipError_t launch_conv3d_dgrad(Vol v, int Cout, const __bf16* dY, const __bf16* Yact, int Cin, const __bf16* Wd,
                                int Kp, int C1, __bf16* dX1, __bf16* dX2, hipStream_t s) {
-  size_t P = (size_t)v.D * v.H * v.W;
-  dim3 grid(nblk(P, 64));
-  switch (Cin / 16) {
-    case 1: hipLaunchKernelGGL(k_conv3d_dgrad<1>, grid, dim3(256), 0, s, v, Cout, dY, Yact, Wd, Kp, C1, dX1, dX2); break;
-    case 2: hipLaunchKernelGGL(k_conv3d_dgrad<2>, grid, dim3(256), 0, s, v, Cout, dY, Yact, Wd, Kp, C1, dX1, dX2); break;
-    case 3: hipLaunchKernelGGL(k_conv3d_dgrad<3>, grid, dim3(256), 0, s, v, Cout, dY, Yact, Wd, Kp, C1, dX1, dX2); break;
-    case 4: hipLaunchKernelGGL(k_conv3d_dgrad<4>, grid, dim3(256), 0, s, v, Cout, dY, Yact, Wd, Kp, C1, dX1, dX2); break;
-    case 6: hipLaunchKernelGGL(k_conv3d_dgrad<6>, grid, dim3(256), 0, s, v, Cout, dY, Yact, Wd, Kp, C1, dX1, dX2); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  ConvIO io{dY, nullptr, Cout, 0, Yact, Wd, Kp, nullptr, 0, dX1, dX2, C1, 1};
+  return launch_tiled_n(v, io, Cin, s);
 }
 
 hipError_t launch_conv3d_wgrad(Vol v, int C1, int C2, const __bf16* X1, const __bf16* X2, int Cout, const __bf16* dY,
