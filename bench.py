@@ -30,7 +30,7 @@ PEAK_HBM_GBS = 8000.0
 
 # sources that make up each kernel whose counters are recorded in profiles/traffic.json
 KERNEL_SOURCES = {
-    "conv_mfma_f32": ["conv_mfma.hip", "taps.hpp", "device_math.hpp", "pdrt_internal.hpp"],
+    "conv_mfma_f32": ["conv_mfma.hip", "conv_common.hpp", "taps.hpp", "device_math.hpp", "pdrt_internal.hpp"],
 }
 
 

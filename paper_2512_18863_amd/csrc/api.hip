@@ -250,8 +250,8 @@ void make_fc_taps(const pdrt_kernel_spec* spec, FcTaps<T>* t) {
 #define LAUNCH(name, x) PDRT_TIMED(name, s, x)
 
 // Smallest kernel taken by the FP32 matrix-core convolution: below it the Toeplitz
-// operand is mostly padding (a 9-tap row fills 9 of 32 columns) and the direct
-// convolution is faster.
+// operand is mostly padding (a 9-tap row fills 9 of 32 columns) and the vector-ALU
+// convolutions are faster.
 constexpr int kMfmaMinTaps = 13;
 
 template <typename T>
@@ -268,14 +268,23 @@ hipError_t run_conv<float>(const Geo<float>& g, int conv_mode, int nb, const flo
                            hipStream_t s) {
   if (conv_mode == PDRT_CONV_BF16) return launch_conv_mfma_bf16(g, nb, z, in, out, s);
   if (g.n_taps >= kMfmaMinTaps) return launch_conv_mfma_f32(g, nb, z, in, out, s);
+  if (conv_small_supported(g)) return launch_conv_small(g, nb, z, in, out, s);
   return launch_conv_direct<float>(g, nb, z, in, out, s);
 }
 
 template <typename T>
-const char* conv_name(const Geo<T>& g, int conv_mode) {
-  if (sizeof(T) == 8) return "conv_direct_f64";
+const char* conv_name(const Geo<T>& g, int conv_mode);
+
+template <>
+const char* conv_name<double>(const Geo<double>&, int) {
+  return "conv_direct_f64";
+}
+
+template <>
+const char* conv_name<float>(const Geo<float>& g, int conv_mode) {
   if (conv_mode == PDRT_CONV_BF16) return "conv_mfma_bf16";
-  return g.n_taps >= kMfmaMinTaps ? "conv_mfma_f32" : "conv_direct_f32";
+  if (g.n_taps >= kMfmaMinTaps) return "conv_mfma_f32";
+  return conv_small_supported(g) ? "conv_small_f32" : "conv_direct_f32";
 }
 
 template <typename T>

@@ -79,6 +79,10 @@ hipError_t launch_march_adj(const Geo<T>& g, int nb, const T* frame, const T* rh
                             const T* H, T* A, hipStream_t s);
 template <typename T>
 hipError_t launch_conv_direct(const Geo<T>& g, int nb, const T* z, const T* in, T* out, hipStream_t s);
+// Small kernels (odd n <= 11) whose plane band fits the LDS budget.
+bool conv_small_supported(const Geo<float>& g);
+hipError_t launch_conv_small(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
+                             hipStream_t s);
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                 hipStream_t s);
 hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, const float* in, float* out,

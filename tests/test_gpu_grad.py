@@ -46,7 +46,7 @@ def _check(name, got, ref):
     assert err <= TOL_GRAD, name
 
 
-@pytest.mark.parametrize("seed,n_taps", [(31, 3), (32, 5), (33, 15)])
+@pytest.mark.parametrize("seed,n_taps", [(31, 3), (32, 5), (33, 15), (34, 9), (35, 11)])
 def test_tiny_gradient_parity(seed, n_taps):
     _say("tiny gradients seed=%d n=%d" % (seed, n_taps))
     c = inputs.tiny_case(seed=seed, n_cp=3, n_taps=n_taps, shape=(6, 7, 6), spacing=8.0, field=30.0)

@@ -130,6 +130,10 @@ TINY = [
     dict(seed=15, n_taps=13, shape=(1, 5, 4), spacing=8.0, field=20.0),      # a single slice
     # a 115 x 115 beam-frame plane: several convolution regions in both directions
     dict(seed=16, n_taps=15, shape=(10, 12, 11), spacing=3.0, field=150.0, n_leaf=30, leaf_width=10.0),
+    # small kernels on a 107 x 107 plane: the vector-ALU convolution splits it into two row bands
+    dict(seed=17, n_taps=9, shape=(10, 12, 11), spacing=3.0, field=150.0, n_leaf=30, leaf_width=10.0),
+    dict(seed=18, n_taps=11, shape=(7, 6, 8), spacing=6.0, field=40.0),
+    dict(seed=19, n_taps=7, shape=(6, 7, 5), spacing=7.0, field=30.0, n_cp=3),
 ]
 
 
