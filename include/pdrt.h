@@ -56,6 +56,7 @@ extern "C" {
 #define PDRT_MAX_LEAF_PAIRS 160
 #define PDRT_MAX_TAPS 127
 #define PDRT_MAX_BLUR_RADIUS 64
+#define PDRT_MAX_STRUCTS 32
 
 /* CT grid.  Voxel (i, j, k) has its centre at (ox + i sx, oy + j sy, oz + k sz). */
 typedef struct {
@@ -294,6 +295,43 @@ int pdrt_net_fallback_stats(int32_t n, const float* pred, const float* resid, fl
 /* One Adam update of n FP32 parameters (step t >= 1, bias-corrected). */
 int pdrt_adam_step(size_t n, float* w, const float* g, float* m, float* v, float lr, float beta1, float beta2,
                    float eps, int32_t t, void* stream);
+
+/* ---------------------------------------------------------------- plan assessment
+ * The dose objective of the gradient-based optimisation study (§2.5) and the plan
+ * metrics it is judged by (DVH parameters, §3; Dice of the prescription isodose
+ * volume with the PTV, §2.5).  Structures are given as one label per voxel of the
+ * dose grid, device uint32 [n_vox]: bit s set = the voxel belongs to structure s,
+ * 0 <= s < n_struct <= PDRT_MAX_STRUCTS; structures may overlap.  dose is device
+ * float [n_vox], finite and non-negative; n_vox < 2^32.  All calls are
+ * asynchronous on `stream` and deterministic (floating-point partial sums are
+ * added in a fixed order; counts are exact integers).  ws: device scratch of at
+ * least pdrt_eval_ws_bytes(n_struct) bytes, owned by the caller. */
+size_t pdrt_eval_ws_bytes(int32_t n_struct);
+
+/* Weighted L1 objective (§2.5): loss[0] = sum_s weight[s] sum_{v in s} |dose_v - target[s]|
+ * (the PTV term has target = prescribed dose, an organ-at-risk term target 0), in
+ * double precision; grad (device float [n_vox], may be NULL) = dL/d dose, i.e.
+ * sum over the structures s containing v of weight[s] sign(dose_v - target[s]), with
+ * sign(0) = 0.  weight, target: host double [n_struct]; loss: device double [1]. */
+int pdrt_l1_objective(int64_t n_vox, const float* dose, const uint32_t* labels, int32_t n_struct,
+                      const double* weight, const double* target, double* loss, float* grad, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Differential dose-volume histograms: hist (device uint32 [n_struct][n_bins],
+ * overwritten) counts the voxels of each structure in bin floor(dose / bin_width)
+ * (computed in double precision, clamped to [0, n_bins - 1]); stats (device double
+ * [n_struct][3], overwritten) = voxel count, sum of dose and maximum dose (0 for an
+ * empty structure).  1 <= n_bins <= 16384, bin_width > 0. */
+int pdrt_dose_histogram(int64_t n_vox, const float* dose, const uint32_t* labels, int32_t n_struct,
+                        int32_t n_bins, double bin_width, uint32_t* hist, double* stats, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* Voxels at or above a dose level (comparison in double precision): counts (device
+ * uint64 [n_struct + 1], overwritten) = per structure, then over the whole grid.
+ * With threshold = the prescribed dose this gives the Dice coefficient of the
+ * 100 % isodose volume with structure s, 2 counts[s] / (counts[n_struct] + |s|). */
+int pdrt_threshold_counts(int64_t n_vox, const float* dose, const uint32_t* labels, int32_t n_struct,
+                          double threshold, uint64_t* counts, void* stream);
 
 /* Human-readable text of a status code (static storage). */
 const char* pdrt_status_string(int status);
