@@ -135,11 +135,19 @@ def hbm_table(kernels, steps, n_cp, nodes, plane, vox):
     return out
 
 
-def run_gpu(case, conv, steps, warmup, w):
+def run_gpu(case, conv, steps, warmup, w, cache=None):
+    """Forward + backward timed over `steps`; with cache = "fp32" / "bf16" the plan's
+    geometry cache is built first (outside the timed region: once per plan)."""
     import torch
     from paper_2512_18863_amd import engine as E
     eng = E.DoseEngine(case, conv=conv)
     dev = eng.device
+    if cache:
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        eng.cache_bytes = eng.build_cache(cache)
+        torch.cuda.synchronize()
+        eng.cache_build_ms = (time.perf_counter() - tb) * 1e3
     lv = torch.tensor(case.leaves, dtype=torch.float32, device=dev)
     jw = torch.tensor(case.jaws, dtype=torch.float32, device=dev)
     mu = torch.tensor(case.mu, dtype=torch.float32, device=dev)
@@ -171,10 +179,11 @@ def run_gpu(case, conv, steps, warmup, w):
 LEARNED_WEIGHTS = os.path.join(ROOT, "paper_2512_18863_amd", "data", "learned_c4.npz")
 
 
-def run_learned(case, steps, warmup, w, d_ref):
+def run_learned(case, steps, warmup, w, d_ref, cache=None):
     """The learned path (9 x 9 dose + U-Net, falling back to the plain 61 x 61 path
     when its own error estimate is too large), forward + backward, timed like the
-    plain path; its dose is compared with the plain FP32 61 x 61 dose."""
+    plain path; its dose is compared with the plain FP32 61 x 61 dose.  With cache
+    the 9 x 9 engine uses a geometry cache built before the timed region."""
     import numpy as np
     import torch
     from paper_2512_18863_amd import engine as E
@@ -182,6 +191,8 @@ def run_learned(case, steps, warmup, w, d_ref):
     net = learned.Net3D.from_file(LEARNED_WEIGHTS, case.shape)
     ld = learned.LearnedDose(net, case, mode="auto")
     dev = ld.small.device
+    if cache:
+        ld.small.build_cache(cache)
     lv = torch.tensor(case.leaves, dtype=torch.float32, device=dev)
     jw = torch.tensor(case.jaws, dtype=torch.float32, device=dev)
     mu = torch.tensor(case.mu, dtype=torch.float32, device=dev)
@@ -268,6 +279,7 @@ def main():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-fluence-corr", action="store_true")
+    ap.add_argument("--no-cache", action="store_true", help="skip the geometry-cache variants")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from the two counter runs' CSV files and exit")
     ap.add_argument("--counter-run", action="store_true",
@@ -361,10 +373,32 @@ def main():
             "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(kc.items())}}
         del engc
         torch.cuda.empty_cache()
+    if not args.no_cache:
+        for name, conv, kind in (("fp32_geometry_cache", "fp32", "fp32"), ("bf16_geometry_cache", "bf16", "bf16")):
+            print("[bench] %s" % name, file=sys.stderr, flush=True)
+            msg, kg, dg, engg = run_gpu(case, conv, args.steps, args.warmup, w, cache=kind)
+            v = {"value": round(n_cp / (msg / 1e3), 3), "ms_per_step": round(msg, 4),
+                 "cache": "%s factor, %.2f GB, built once per plan in %.2f ms (not in the step)"
+                          % (kind.upper(), engg.cache_bytes / 1e9, engg.cache_build_ms),
+                 "kernels_ms_per_step": {k: round(x[1] / args.steps, 4) for k, x in sorted(kg.items())}}
+            if kind == "fp32":
+                v["identical_to_uncached_fp32"] = bool(np.array_equal(dg, d32))
+            else:
+                v["max_abs_err_vs_fp32_over_max"] = float(np.abs(dg.astype(np.float64) - d32).max()
+                                                          / np.abs(d32).max())
+                v["gamma_1pct_1mm_vs_fp32"] = round(gamma.pass_rate(d32, dg, case.spacing, 1.0, 1.0), 6)
+            out.setdefault("variants", {})[name] = v
+            del engg
+            torch.cuda.empty_cache()
     if not args.no_learned and os.path.exists(LEARNED_WEIGHTS):
         print("[bench] learned variant", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out.setdefault("variants", {})["learned"] = run_learned(case, args.steps, args.warmup, w, d32)
+        if not args.no_cache:
+            print("[bench] learned variant with geometry cache", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+            out["variants"]["learned_geometry_cache"] = run_learned(case, args.steps, args.warmup, w, d32,
+                                                                    cache="fp32")
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, w)

@@ -53,6 +53,9 @@ extern "C" {
 #define PDRT_CONV_FP32 0 /* lateral convolution in FP32 */
 #define PDRT_CONV_BF16 1 /* lateral convolution with BF16 operands, FP32 accumulation */
 
+#define PDRT_CACHE_F32 0  /* geometry cache holds G in FP32: results identical to the uncached path */
+#define PDRT_CACHE_BF16 1 /* geometry cache holds G in BF16 (half the bytes, G rounded to 8 bits) */
+
 #define PDRT_MAX_LEAF_PAIRS 160
 #define PDRT_MAX_TAPS 127
 #define PDRT_MAX_BLUR_RADIUS 64
@@ -171,6 +174,44 @@ int pdrt_dose_backward(const pdrt_grid* grid, const float* rho, const pdrt_beam*
 int pdrt_dose_forward_f64(const pdrt_grid* grid, const double* rho, const pdrt_beam* beam,
                           const double* leaves, const double* jaws, const double* mu,
                           const pdrt_kernel_spec* spec, double* dose, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- geometry cache
+ * In plan optimisation (§2.5) only leaves, jaws and MU change between calls.  The
+ * primary of Eq. 6 factorises as P_k(u, v) = F(u, v) G_k(u, v) with the
+ * aperture-free factor G_k = (SAD/d_k)^2 DD(W_k(u, v)) of Eqs. 6-7; G and the
+ * central-axis depths z_k that set the kernel taps (§2.2.5) depend only on the
+ * density, the gantry angles and the beam-frame grid.  The cache holds both for
+ * every control point, so the cached forward / backward skip the ray march:
+ *   layout (device, caller-owned, cache_bytes >= pdrt_geometry_cache_bytes):
+ *   z float [n_cp][Nk] at byte 0, then G [n_cp][Nk][Nu][Nv] (float for
+ *   PDRT_CACHE_F32, bf16 for PDRT_CACHE_BF16) at the next 256-byte boundary.
+ * A cache is valid for the grid, density, beam (gantry angles, isocentre, SAD,
+ * field limit) and the spec fields n_taps, wepl_mode, lateral/depth steps and the
+ * depth-dose table it was built with; the caller keeps those fixed (they are not
+ * checked).  The spec's conv_mode, calib, transmission, kernel polynomials and
+ * fluence corrections may change between builds and uses.  With PDRT_CACHE_F32
+ * the cached calls return exactly what pdrt_dose_forward / _backward return.
+ * Returns 0 for an invalid problem or cache type. */
+size_t pdrt_geometry_cache_bytes(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spec* spec,
+                                 int32_t cache_type);
+
+/* Fill a cache (one ray march over all control points).  ws as for
+ * pdrt_dose_forward (pdrt_workspace_bytes(..., 0, 4)). */
+int pdrt_geometry_cache_build(const pdrt_grid* grid, const float* rho, const pdrt_beam* beam,
+                              const pdrt_kernel_spec* spec, int32_t cache_type, void* cache, size_t cache_bytes,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* pdrt_dose_forward / pdrt_dose_backward with the march replaced by the cache
+ * (rho is not needed).  Workspace requirements are those of the uncached calls. */
+int pdrt_dose_forward_cached(const pdrt_grid* grid, const pdrt_beam* beam, const float* leaves,
+                             const float* jaws, const float* mu, const pdrt_kernel_spec* spec,
+                             int32_t cache_type, const void* cache, size_t cache_bytes, float* dose, void* ws,
+                             size_t ws_bytes, void* stream);
+int pdrt_dose_backward_cached(const pdrt_grid* grid, const pdrt_beam* beam, const float* leaves,
+                              const float* jaws, const float* mu, const pdrt_kernel_spec* spec,
+                              int32_t cache_type, const void* cache, size_t cache_bytes,
+                              const float* grad_dose, float* grad_leaves, float* grad_jaws, float* grad_mu,
+                              void* ws, size_t ws_bytes, void* stream);
 
 /* Hardware-constrained projection (§2.2.1, Eqs. 1-3): every opposing pair
  * (leaf pair, x jaws, y jaws) goes to centre-width form, the width is raised to

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdrt.so")
-SOURCES = ["api.hip", "dose_fwd.hip", "dose_bwd.hip", "conv_mfma.hip", "conv_small.hip", "fluence_corr.hip", "plan_eval.hip", "net.hip", "net_api.hip"]
+SOURCES = ["api.hip", "dose_fwd.hip", "dose_bwd.hip", "conv_mfma.hip", "conv_small.hip", "geometry_cache.hip", "fluence_corr.hip", "plan_eval.hip", "net.hip", "net_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -3,6 +3,7 @@
 // never allocates, frees or synchronises.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "pdrt_internal.hpp"
@@ -287,13 +288,58 @@ const char* conv_name<float>(const Geo<float>& g, int conv_mode) {
   return conv_small_supported(g) ? "conv_small_f32" : "conv_direct_f32";
 }
 
+// Plan-level geometry cache: z [n_cp][Nk] float at offset 0, then G [n_cp][Nk][Nu][Nv]
+// as float or bf16 at a 256-byte aligned offset.
+struct GeoCache {
+  int type;
+  const float* z;
+  const void* G;
+};
+
+bool cache_offsets(const Problem& P, int n_cp, int type, size_t* g_off, size_t* total) {
+  if (type != PDRT_CACHE_F32 && type != PDRT_CACHE_BF16) return false;
+  const size_t e = type == PDRT_CACHE_F32 ? sizeof(float) : sizeof(__bf16);
+  *g_off = align256((size_t)n_cp * P.Nk * sizeof(float));
+  *total = *g_off + (size_t)n_cp * P.Nk * P.Nu * P.Nv * e;
+  return true;
+}
+
+// The cache as seen by the forward / backward, after checking its size.
+int cache_view(const Problem& P, const pdrt_beam* beam, int type, const void* cache, size_t cache_bytes,
+               GeoCache* gc) {
+  size_t g_off = 0, total = 0;
+  if (!cache || !cache_offsets(P, beam->n_cp, type, &g_off, &total)) return PDRT_E_INVALID;
+  if (cache_bytes < total) return PDRT_E_WORKSPACE;
+  gc->type = type;
+  gc->z = (const float*)cache;
+  gc->G = (const char*)cache + g_off;
+  return PDRT_OK;
+}
+
+template <typename E>
+hipError_t apply_geometry(const Geo<float>& g, int nb, int cp0, const GeoCache& gc, const float* F, float* P,
+                          hipStream_t s) {
+  const E* G = (const E*)gc.G + (size_t)cp0 * g.Nk * g.Nu * g.Nv;
+  return launch_apply_geometry<E>(g, nb, F, G, P, s);
+}
+
+template <typename E>
+hipError_t geometry_adjoint(const Geo<float>& g, int nb, int cp0, const GeoCache& gc, const float* H, float* A,
+                            hipStream_t s) {
+  const E* G = (const E*)gc.G + (size_t)cp0 * g.Nk * g.Nu * g.Nv;
+  return launch_geometry_adjoint<E>(g, nb, H, G, A, s);
+}
+
+// With gc == nullptr the march computes the geometry from rho; with a cache (FP32
+// only) rho is not read and the march is replaced by the cached factor.
 template <typename T>
 int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, const T* leaves, const T* jaws,
-                 const T* mu, const pdrt_kernel_spec* spec, T* dose, void* ws, size_t ws_bytes, void* stream) {
+                 const T* mu, const pdrt_kernel_spec* spec, T* dose, void* ws, size_t ws_bytes, void* stream,
+                 const GeoCache* gc = nullptr) {
   Problem P;
   int st = size_problem(grid, beam, spec, 0, (int)sizeof(T), &P);
   if (st != PDRT_OK) return st;
-  if (!rho || !leaves || !jaws || !mu || !dose) return PDRT_E_INVALID;
+  if ((!rho && !gc) || !leaves || !jaws || !mu || !dose) return PDRT_E_INVALID;
   if (!ws || ws_bytes < P.lay.total) return PDRT_E_WORKSPACE;
   if (sizeof(T) == 8 && spec->conv_mode != PDRT_CONV_FP32) return PDRT_E_UNSUPPORTED;
   Geo<T> g;
@@ -314,7 +360,7 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
   const T* dd = (const T*)spec->dd;
   const int L = beam->n_leaf_pairs, n_cp = beam->n_cp;
   LAUNCH("frame", launch_frame<T>(g, (const T*)beam->gantry_deg, n_cp, frame, s));
-  LAUNCH("transpose_rho", launch_transpose_rho<T>(g, rho, rho_t, s));
+  if (!gc) LAUNCH("transpose_rho", launch_transpose_rho<T>(g, rho, rho_t, s));
   for (int cp0 = 0; cp0 < n_cp; cp0 += P.batch) {
     int nb = n_cp - cp0 < P.batch ? n_cp - cp0 : P.batch;
     const T* fr = frame + 2 * cp0;
@@ -327,9 +373,19 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
       LAUNCH("fluence_corr", launch_blur<T>(g, nb, 1, fct.hs, t0, F, s));
       LAUNCH("fluence_corr", launch_fcorr_combine<T>(g, nb, g.hs_amp, 1, t1, F, F, s));
     }
-    LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
-    LAUNCH("march", launch_march<T>(g, nb, fr, rho_t, F, z, dd, vol0, s));
-    LAUNCH(conv_name<T>(g, spec->conv_mode), run_conv<T>(g, spec->conv_mode, nb, z, vol0, vol1, s));
+    const T* zb = z;
+    if constexpr (std::is_same<T, float>::value) {
+      if (gc) {
+        zb = gc->z + (size_t)cp0 * g.Nk;
+        LAUNCH("apply_geometry", gc->type == PDRT_CACHE_F32 ? apply_geometry<float>(g, nb, cp0, *gc, F, vol0, s)
+                                                            : apply_geometry<__bf16>(g, nb, cp0, *gc, F, vol0, s));
+      }
+    }
+    if (!gc) {
+      LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
+      LAUNCH("march", launch_march<T>(g, nb, fr, rho_t, F, z, dd, vol0, s));
+    }
+    LAUNCH(conv_name<T>(g, spec->conv_mode), run_conv<T>(g, spec->conv_mode, nb, zb, vol0, vol1, s));
     LAUNCH("gather", launch_gather<T>(g, nb, cp0 == 0, cp0 + nb == n_cp, fr, mu + cp0, vol1, dose, comp, s));
   }
   return PDRT_OK;
@@ -338,11 +394,11 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
 template <typename T>
 int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, const T* leaves, const T* jaws,
                   const T* mu, const pdrt_kernel_spec* spec, const T* grad, T* gleaves, T* gjaws, T* gmu, void* ws,
-                  size_t ws_bytes, void* stream) {
+                  size_t ws_bytes, void* stream, const GeoCache* gc = nullptr) {
   Problem P;
   int st = size_problem(grid, beam, spec, 1, (int)sizeof(T), &P);
   if (st != PDRT_OK) return st;
-  if (!rho || !leaves || !jaws || !mu || !grad || !gleaves || !gjaws || !gmu) return PDRT_E_INVALID;
+  if ((!rho && !gc) || !leaves || !jaws || !mu || !grad || !gleaves || !gjaws || !gmu) return PDRT_E_INVALID;
   if (!ws || ws_bytes < P.lay.total) return PDRT_E_WORKSPACE;
   Geo<T> g;
   make_geo<T>(grid, beam, spec, P, &g);
@@ -362,15 +418,25 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
   const T* dd = (const T*)spec->dd;
   const int L = beam->n_leaf_pairs, n_cp = beam->n_cp;
   LAUNCH("frame", launch_frame<T>(g, (const T*)beam->gantry_deg, n_cp, frame, s));
-  LAUNCH("transpose_rho", launch_transpose_rho<T>(g, rho, rho_t, s));
+  if (!gc) LAUNCH("transpose_rho", launch_transpose_rho<T>(g, rho, rho_t, s));
   LAUNCH("transpose_grad", launch_transpose_rho<T>(g, grad, g_t, s));
   for (int cp0 = 0; cp0 < n_cp; cp0 += P.batch) {
     int nb = n_cp - cp0 < P.batch ? n_cp - cp0 : P.batch;
     const T* fr = frame + 2 * cp0;
-    LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
+    const T* zb = z;
+    if constexpr (std::is_same<T, float>::value) {
+      if (gc) zb = gc->z + (size_t)cp0 * g.Nk;
+    }
+    if (!gc) LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
     LAUNCH("backproject_adj", launch_backproject_adj<T>(g, nb, fr, g_t, vol0, s));
-    LAUNCH(conv_name<T>(g, spec->conv_mode), run_conv<T>(g, spec->conv_mode, nb, z, vol0, vol1, s));
-    LAUNCH("march_adj", launch_march_adj<T>(g, nb, fr, rho_t, z, dd, vol1, A, s));
+    LAUNCH(conv_name<T>(g, spec->conv_mode), run_conv<T>(g, spec->conv_mode, nb, zb, vol0, vol1, s));
+    if constexpr (std::is_same<T, float>::value) {
+      if (gc)
+        LAUNCH("geometry_adjoint", gc->type == PDRT_CACHE_F32
+                                       ? geometry_adjoint<float>(g, nb, cp0, *gc, vol1, A, s)
+                                       : geometry_adjoint<__bf16>(g, nb, cp0, *gc, vol1, A, s));
+    }
+    if (!gc) LAUNCH("march_adj", launch_march_adj<T>(g, nb, fr, rho_t, z, dd, vol1, A, s));
     if (g.fcorr) {
       // A <- G_u G_v (X + a G_hu G_hv X), X = O A: the corrections' adjoint, so that
       // the parameter gradients see dL/d(aperture fluence)
@@ -472,6 +538,79 @@ int pdrt_dose_forward_f64(const pdrt_grid* grid, const double* rho, const pdrt_b
                           const double* jaws, const double* mu, const pdrt_kernel_spec* spec, double* dose, void* ws,
                           size_t ws_bytes, void* stream) {
   return forward_impl<double>(grid, rho, beam, leaves, jaws, mu, spec, dose, ws, ws_bytes, stream);
+}
+
+size_t pdrt_geometry_cache_bytes(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spec* spec,
+                                 int32_t cache_type) {
+  Problem P;
+  if (size_problem(grid, beam, spec, 0, 4, &P) != PDRT_OK) return 0;
+  size_t g_off = 0, total = 0;
+  if (!cache_offsets(P, beam->n_cp, cache_type, &g_off, &total)) return 0;
+  return total;
+}
+
+int pdrt_geometry_cache_build(const pdrt_grid* grid, const float* rho, const pdrt_beam* beam,
+                              const pdrt_kernel_spec* spec, int32_t cache_type, void* cache, size_t cache_bytes,
+                              void* ws, size_t ws_bytes, void* stream) {
+  Problem P;
+  int st = size_problem(grid, beam, spec, 0, 4, &P);
+  if (st != PDRT_OK) return st;
+  if (!rho) return PDRT_E_INVALID;
+  GeoCache gc;
+  st = cache_view(P, beam, cache_type, cache, cache_bytes, &gc);
+  if (st != PDRT_OK) return st;
+  if (!ws || ws_bytes < P.lay.total) return PDRT_E_WORKSPACE;
+  Geo<float> g;
+  make_geo<float>(grid, beam, spec, P, &g);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  float* frame = (float*)(w + P.lay.frame);
+  float* rho_t = (float*)(w + P.lay.rho_t);
+  float* z = (float*)cache;
+  const float* dd = (const float*)spec->dd;
+  const int n_cp = beam->n_cp;
+  const size_t node = (size_t)g.Nk * g.Nu * g.Nv;
+  LAUNCH("frame", launch_frame<float>(g, (const float*)beam->gantry_deg, n_cp, frame, s));
+  LAUNCH("transpose_rho", launch_transpose_rho<float>(g, rho, rho_t, s));
+  LAUNCH("ca_depth", launch_ca_depth<float>(g, n_cp, frame, rho_t, z, s));
+  for (int cp0 = 0; cp0 < n_cp; cp0 += P.batch) {
+    const int nb = n_cp - cp0 < P.batch ? n_cp - cp0 : P.batch;
+    const float* fr = frame + 2 * cp0;
+    const float* zb = z + (size_t)cp0 * g.Nk;
+    if (cache_type == PDRT_CACHE_F32)
+      LAUNCH("march_geometry", launch_march_geometry<float>(g, nb, fr, rho_t, zb, dd,
+                                                            (float*)gc.G + (size_t)cp0 * node, s));
+    else
+      LAUNCH("march_geometry", launch_march_geometry<__bf16>(g, nb, fr, rho_t, zb, dd,
+                                                             (__bf16*)gc.G + (size_t)cp0 * node, s));
+  }
+  return PDRT_OK;
+}
+
+int pdrt_dose_forward_cached(const pdrt_grid* grid, const pdrt_beam* beam, const float* leaves, const float* jaws,
+                             const float* mu, const pdrt_kernel_spec* spec, int32_t cache_type, const void* cache,
+                             size_t cache_bytes, float* dose, void* ws, size_t ws_bytes, void* stream) {
+  Problem P;
+  int st = size_problem(grid, beam, spec, 0, 4, &P);
+  if (st != PDRT_OK) return st;
+  GeoCache gc;
+  st = cache_view(P, beam, cache_type, cache, cache_bytes, &gc);
+  if (st != PDRT_OK) return st;
+  return forward_impl<float>(grid, nullptr, beam, leaves, jaws, mu, spec, dose, ws, ws_bytes, stream, &gc);
+}
+
+int pdrt_dose_backward_cached(const pdrt_grid* grid, const pdrt_beam* beam, const float* leaves, const float* jaws,
+                              const float* mu, const pdrt_kernel_spec* spec, int32_t cache_type, const void* cache,
+                              size_t cache_bytes, const float* grad_dose, float* grad_leaves, float* grad_jaws,
+                              float* grad_mu, void* ws, size_t ws_bytes, void* stream) {
+  Problem P;
+  int st = size_problem(grid, beam, spec, 1, 4, &P);
+  if (st != PDRT_OK) return st;
+  GeoCache gc;
+  st = cache_view(P, beam, cache_type, cache, cache_bytes, &gc);
+  if (st != PDRT_OK) return st;
+  return backward_impl<float>(grid, nullptr, beam, leaves, jaws, mu, spec, grad_dose, grad_leaves, grad_jaws,
+                              grad_mu, ws, ws_bytes, stream, &gc);
 }
 
 int pdrt_project_params(int32_t n_cp, int32_t n_leaf_pairs, const float* leaves_in, const float* jaws_in,

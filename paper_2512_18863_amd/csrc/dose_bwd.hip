@@ -4,7 +4,7 @@
 //   k_backproject_adj  Ghat_b = (trilinear back-projection)^T g   (adjoint of §2.2.7)
 //   conv          H = K_k (*) Ghat_k (the taps are point symmetric, so the
 //                 transposed convolution is the convolution itself; §2.2.6)
-//   k_march<ADJ>  A = sum_k H_k (SAD/d_k)^2 DD(W_k), W recomputed    (§2.2.3-2.2.4)
+//   k_march (adjoint mode)  A = sum_k H_k (SAD/d_k)^2 DD(W_k), W recomputed (§2.2.3-2.2.4)
 //   k_param_grad  dL/dMU = calib <A, F>, dL/dF = calib MU A, then the chain rule
 //                 through the fluence map (§2.2.2) to leaves and jaws.
 // Depth and kernels are outside the gradient graph (§2.1), so nothing flows to

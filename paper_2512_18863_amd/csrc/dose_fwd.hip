@@ -174,13 +174,17 @@ hipError_t launch_ca_depth(const Geo<T>& g, int nb, const T* frame, const T* rho
 // the density is sampled trilinearly there and integrated with a compensated
 // running sum (step Dd sqrt(1 + (u^2 + v^2)/SAD^2)), giving W_k; the primary is
 // P_k = F (SAD / d_k)^2 DD(W_k).  Lanes run along v, i.e. along patient z, so the
-// z-fastest density copy is read almost contiguously.  With ADJ the same march
-// instead accumulates A = sum_k H_k (SAD / d_k)^2 DD(W_k) (the adjoint of the
-// primary w.r.t. F).
-template <typename T, bool ADJ>
+// z-fastest density copy is read almost contiguously.  MARCH_ADJOINT instead
+// accumulates A = sum_k H_k (SAD / d_k)^2 DD(W_k) (the adjoint of the primary
+// w.r.t. F); MARCH_GEOMETRY stores the aperture-independent factor
+// G_k = (SAD / d_k)^2 DD(W_k) itself (rounded to E), so that P = F G later.
+enum { MARCH_PRIMARY = 0, MARCH_ADJOINT = 1, MARCH_GEOMETRY = 2 };
+
+template <typename T, int MODE, typename E>
 __global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ frame, const T* __restrict__ rho_t,
                                                const T* __restrict__ F, const T* __restrict__ zca,
-                                               const T* __restrict__ dd, T* __restrict__ vol, T* __restrict__ A) {
+                                               const T* __restrict__ dd, E* __restrict__ vol, T* __restrict__ A) {
+  constexpr bool ADJ = MODE == MARCH_ADJOINT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tab = reinterpret_cast<T*>(smem_raw);
   for (int q = threadIdx.x; q < g.n_dd; q += 256) tab[q] = dd[q];
@@ -190,12 +194,12 @@ __global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ f
   int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= plane) return;
   int i = r / g.Nv, j = r - i * g.Nv;
-  T* vb = vol + (size_t)b * g.Nk * plane + r;
+  E* vb = vol + (size_t)b * g.Nk * plane + r;
   T Fv = T(1);
-  if (!ADJ) {
+  if (MODE == MARCH_PRIMARY) {
     Fv = F[(size_t)b * plane + r];
     if (Fv == T(0)) {
-      for (int k = 0; k < g.Nk; ++k) vb[(size_t)k * plane] = T(0);
+      for (int k = 0; k < g.Nk; ++k) vb[(size_t)k * plane] = E(0);
       return;
     }
   }
@@ -211,10 +215,12 @@ __global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ f
     const T e = g.e0 + T(k) * g.dstep;
     const T gk = T(1) + e * g.inv_sad;
     const T geo = dd_lookup(tab, g.n_dd, g.inv_dd_step, Wk) / (gk * gk);
-    if (ADJ)
-      acc += vb[(size_t)k * plane] * geo;
-    else
+    if (MODE == MARCH_ADJOINT)
+      acc = fma(T(vb[(size_t)k * plane]), geo, acc);
+    else if (MODE == MARCH_PRIMARY)
       vb[(size_t)k * plane] = Fv * geo;
+    else
+      vb[(size_t)k * plane] = E(geo);
   };
   if (g.wepl_mode == PDRT_WEPL_PER_RAY) {
 #pragma unroll 4
@@ -241,16 +247,30 @@ template <typename T>
 hipError_t launch_march(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* F, const T* z, const T* dd,
                         T* P, hipStream_t s) {
   dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
-  hipLaunchKernelGGL((k_march<T, false>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t, F, z, dd, P,
-                     (T*)nullptr);
+  hipLaunchKernelGGL((k_march<T, MARCH_PRIMARY, T>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t, F, z,
+                     dd, P, (T*)nullptr);
   return hipGetLastError();
 }
+
+template <typename E>
+hipError_t launch_march_geometry(const Geo<float>& g, int nb, const float* frame, const float* rho_t, const float* z,
+                                 const float* dd, E* G, hipStream_t s) {
+  dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
+  hipLaunchKernelGGL((k_march<float, MARCH_GEOMETRY, E>), grid, dim3(256), g.n_dd * sizeof(float), s, g, frame,
+                     rho_t, (const float*)nullptr, z, dd, G, (float*)nullptr);
+  return hipGetLastError();
+}
+template hipError_t launch_march_geometry<float>(const Geo<float>&, int, const float*, const float*, const float*,
+                                                 const float*, float*, hipStream_t);
+template hipError_t launch_march_geometry<__bf16>(const Geo<float>&, int, const float*, const float*, const float*,
+                                                  const float*, __bf16*, hipStream_t);
 
 template <typename T>
 hipError_t launch_march_adj(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* z, const T* dd,
                             const T* H, T* A, hipStream_t s) {
   dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
-  hipLaunchKernelGGL((k_march<T, true>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t, (const T*)nullptr,
+  hipLaunchKernelGGL((k_march<T, MARCH_ADJOINT, T>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t,
+                     (const T*)nullptr,
                      z, dd, const_cast<T*>(H), A);
   return hipGetLastError();
 }

@@ -77,6 +77,16 @@ hipError_t launch_march(const Geo<T>& g, int nb, const T* frame, const T* rho_t,
 template <typename T>
 hipError_t launch_march_adj(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* z, const T* dd,
                             const T* H, T* A, hipStream_t s);
+// Plan-level geometry cache: G = (SAD/d)^2 DD(W) per beam-frame node (E = float or
+// __bf16), P = F G, and A = sum_k H_k G_k.
+template <typename E>
+hipError_t launch_march_geometry(const Geo<float>& g, int nb, const float* frame, const float* rho_t, const float* z,
+                                 const float* dd, E* G, hipStream_t s);
+template <typename E>
+hipError_t launch_apply_geometry(const Geo<float>& g, int nb, const float* F, const E* G, float* P, hipStream_t s);
+template <typename E>
+hipError_t launch_geometry_adjoint(const Geo<float>& g, int nb, const float* H, const E* G, float* A,
+                                   hipStream_t s);
 template <typename T>
 hipError_t launch_conv_direct(const Geo<T>& g, int nb, const T* z, const T* in, T* out, hipStream_t s);
 // Small kernels (odd n <= 11) whose plane band fits the LDS budget.

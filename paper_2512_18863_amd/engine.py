@@ -24,6 +24,8 @@ CONV_FP32 = 0
 CONV_BF16 = 1
 WEPL_PER_RAY = 0
 WEPL_CENTRAL_AXIS = 1
+CACHE_F32 = 0
+CACHE_BF16 = 1
 
 
 class Grid(ctypes.Structure):
@@ -91,6 +93,17 @@ _SIGS = {
                                           ctypes.POINTER(Spec), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "pdrt_dose_forward_f64": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, ctypes.POINTER(Beam), _VP, _VP, _VP,
                                              ctypes.POINTER(Spec), _VP, _VP, ctypes.c_size_t, _VP]),
+    "pdrt_geometry_cache_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), ctypes.POINTER(Beam),
+                                                    ctypes.POINTER(Spec), ctypes.c_int32]),
+    "pdrt_geometry_cache_build": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, ctypes.POINTER(Beam),
+                                                 ctypes.POINTER(Spec), ctypes.c_int32, _VP, ctypes.c_size_t, _VP,
+                                                 ctypes.c_size_t, _VP]),
+    "pdrt_dose_forward_cached": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Beam), _VP, _VP, _VP,
+                                                ctypes.POINTER(Spec), ctypes.c_int32, _VP, ctypes.c_size_t, _VP, _VP,
+                                                ctypes.c_size_t, _VP]),
+    "pdrt_dose_backward_cached": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Beam), _VP, _VP, _VP,
+                                                 ctypes.POINTER(Spec), ctypes.c_int32, _VP, ctypes.c_size_t, _VP,
+                                                 _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "pdrt_project_params": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, ctypes.POINTER(Limits),
                                            _VP, _VP, _VP, _VP]),
     "pdrt_project_params_backward": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP,
@@ -218,6 +231,8 @@ class DoseEngine:
         self._f64 = None
         if with_f64:
             self._init_f64()
+        self.cache = None
+        self.cache_type = None
 
     # ------------------------------------------------------------------ helpers
     def _ptrs(self, leaves, jaws, mu, dtype=torch.float32):
@@ -242,12 +257,40 @@ class DoseEngine:
         ws = self.ws if elem == 4 else self._f64["ws"]
         return ws[off:off + count * elem].view(dtype).view(*shape)
 
+    # ------------------------------------------------------------------ geometry cache
+    def build_cache(self, kind: str = "fp32") -> int:
+        """Compute the plan-level geometry cache (central-axis depths and
+        (SAD/d)^2 DD(W) of every beam-frame node, all control points); later
+        forward / backward calls use it instead of the ray march.  Returns bytes."""
+        ctype = {"fp32": CACHE_F32, "bf16": CACHE_BF16}[kind]
+        nbytes = lib().pdrt_geometry_cache_bytes(ctypes.byref(self.grid), ctypes.byref(self.beam),
+                                                 ctypes.byref(self.spec), ctype)
+        if nbytes == 0:
+            raise PdrtError("invalid problem for a geometry cache")
+        self.cache = None
+        cache = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _check(lib().pdrt_geometry_cache_build(ctypes.byref(self.grid), self.rho.data_ptr(), ctypes.byref(self.beam),
+                                               ctypes.byref(self.spec), ctype, cache.data_ptr(), nbytes,
+                                               self.ws.data_ptr(), self.ws.numel(), _stream_ptr(self.device)),
+               "pdrt_geometry_cache_build")
+        self.cache, self.cache_type = cache, ctype
+        return nbytes
+
+    def drop_cache(self):
+        self.cache, self.cache_type = None, None
+
     # ------------------------------------------------------------------ calls
     def forward(self, leaves, jaws, mu, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         lp, jp, mp = self._ptrs(leaves, jaws, mu)
         if out is None:
             out = torch.empty(self.vol_shape, dtype=torch.float32, device=self.device)
         op = _dptr(out, torch.float32, self.device, self.vol_shape, "out")
+        if self.cache is not None:
+            _check(lib().pdrt_dose_forward_cached(ctypes.byref(self.grid), ctypes.byref(self.beam), lp, jp, mp,
+                                                  ctypes.byref(self.spec), self.cache_type, self.cache.data_ptr(),
+                                                  self.cache.numel(), op, self.ws.data_ptr(), self.ws.numel(),
+                                                  _stream_ptr(self.device)), "pdrt_dose_forward_cached")
+            return out
         _check(lib().pdrt_dose_forward(ctypes.byref(self.grid), self.rho.data_ptr(), ctypes.byref(self.beam), lp, jp,
                                        mp, ctypes.byref(self.spec), op, self.ws.data_ptr(), self.ws.numel(),
                                        _stream_ptr(self.device)), "pdrt_dose_forward")
@@ -259,6 +302,13 @@ class DoseEngine:
         gl = torch.empty((self.n_cp, 2, self.n_leaf), dtype=torch.float32, device=self.device)
         gj = torch.empty((self.n_cp, 4), dtype=torch.float32, device=self.device)
         gm = torch.empty((self.n_cp,), dtype=torch.float32, device=self.device)
+        if self.cache is not None:
+            _check(lib().pdrt_dose_backward_cached(ctypes.byref(self.grid), ctypes.byref(self.beam), lp, jp, mp,
+                                                   ctypes.byref(self.spec), self.cache_type, self.cache.data_ptr(),
+                                                   self.cache.numel(), gp, gl.data_ptr(), gj.data_ptr(),
+                                                   gm.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
+                                                   _stream_ptr(self.device)), "pdrt_dose_backward_cached")
+            return gl, gj, gm
         _check(lib().pdrt_dose_backward(ctypes.byref(self.grid), self.rho.data_ptr(), ctypes.byref(self.beam), lp, jp,
                                         mp, ctypes.byref(self.spec), gp, gl.data_ptr(), gj.data_ptr(), gm.data_ptr(),
                                         self.ws.data_ptr(), self.ws.numel(), _stream_ptr(self.device)),
