@@ -245,6 +245,151 @@ __global__ void __launch_bounds__(256) k_backproject_adj(Geo<T> g, int tiles_i, 
   }
 }
 
+// Register-tiled variant (used whenever Nv <= 256): one wavefront owns a
+// BR_TK x BR_TI block of beam-frame columns (k, i) of one control point and keeps
+// their Nv sums in registers (lanes along j).  Its members are the voxel columns
+// with floor(kappa) in [k0-1, k0+TK) and floor(iota) in [i0-1, i0+TI), found by
+// testing the voxel columns of the block's rotated bounding box 64 at a time with
+// the forward's index arithmetic; each member's z sum T_c[j] is formed once and
+// added with weight w_k w_i to the (at most four) columns of the block it touches.
+// Members are taken in scan order and z in increasing order, so every sum has a
+// fixed order; no LDS, no barriers, no atomics.
+constexpr int BR_TK = 4, BR_TI = 4;
+
+__device__ __forceinline__ float bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ int bcast(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+
+template <typename T, int JS>
+__global__ void __launch_bounds__(256) k_backproject_reg(Geo<T> g, int nb, int tiles_k, int tiles_i, int per_xcd,
+                                                         const T* __restrict__ frame, const T* __restrict__ g_t,
+                                                         T* __restrict__ Ghat) {
+  const int lane = threadIdx.x & 63;
+  // workgroups reach the eight XCDs round robin; renumber so that each XCD walks a
+  // contiguous range of blocks (neighbouring columns of the same control point)
+  const int logical = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const long wid = (long)logical * 4 + (threadIdx.x >> 6);
+  const long n_waves = (long)nb * tiles_k * tiles_i;
+  if (wid >= n_waves) return;
+  const int it = (int)(wid % tiles_i);
+  const long rest = wid / tiles_i;
+  const int kt = (int)(rest % tiles_k), b = (int)(rest / tiles_k);
+  const int k0 = kt * BR_TK, i0 = it * BR_TI;
+  const T sn = frame[2 * b], cs = frame[2 * b + 1];
+  // rotated bounding box of the beam-frame points with kappa in [k0-1, k0+TK), iota in [i0-1, i0+TI)
+  const T e_lo = g.e0 + T(k0 - 1) * g.dstep, e_hi = g.e0 + T(k0 + BR_TK) * g.dstep;
+  const T u_lo = (T(i0 - 1) - g.cu) * g.lat, u_hi = (T(i0 + BR_TI) - g.cu) * g.lat;
+  const T s_lo = T(1) + e_lo * g.inv_sad, s_hi = T(1) + e_hi * g.inv_sad;
+  const T l_lo = fmin(u_lo * s_lo, u_lo * s_hi), l_hi = fmax(u_hi * s_lo, u_hi * s_hi);
+  T xmin = T(1e30), xmax = T(-1e30), ymin = T(1e30), ymax = T(-1e30);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const T e = (c & 1) ? e_hi : e_lo, l = (c & 2) ? l_hi : l_lo;
+    const T X = (-sn * e + cs * l - g.rel_ox) * g.inv_sx;
+    const T Y = (cs * e + sn * l - g.rel_oy) * g.inv_sy;
+    xmin = fmin(xmin, X);
+    xmax = fmax(xmax, X);
+    ymin = fmin(ymin, Y);
+    ymax = fmax(ymax, Y);
+  }
+  const T eps = T(1e-3);  // rounding margin (index units); membership uses the forward's arithmetic
+  const int x0 = max(0, (int)dfloor(xmin - eps) + 1), x1 = min(g.nx - 1, (int)dfloor(xmax + eps));
+  const int y0 = max(0, (int)dfloor(ymin - eps) + 1), y1 = min(g.ny - 1, (int)dfloor(ymax + eps));
+  const int bw = x1 - x0 + 1, nbox = (x1 >= x0 && y1 >= y0) ? bw * (y1 - y0 + 1) : 0;
+
+  T acc[BR_TK][BR_TI][JS];
+#pragma unroll
+  for (int a = 0; a < BR_TK; ++a)
+#pragma unroll
+    for (int c = 0; c < BR_TI; ++c)
+#pragma unroll
+      for (int s = 0; s < JS; ++s) acc[a][c][s] = T(0);
+
+  for (int base = 0; base < nbox; base += 64) {
+    const int idx = base + lane;
+    bool member = false;
+    int col = 0, kf = 0, ifl = 0;
+    T wk = T(0), wi = T(0), q = T(1), dq = T(1);
+    if (idx < nbox) {
+      const int y = y0 + idx / bw, x = x0 + idx % bw;
+      const T tx = g.rel_ox + T(x) * g.sx, ty = g.rel_oy + T(y) * g.sy;
+      FanIdx<T> f = voxel_to_fan(g, sn, cs, tx, ty, T(0));
+      const T fk = dfloor(f.k), fi = dfloor(f.i);
+      kf = (int)fk;
+      ifl = (int)fi;
+      member = kf >= k0 - 1 && kf < k0 + BR_TK && ifl >= i0 - 1 && ifl < i0 + BR_TI;
+      wk = f.k - fk;
+      wi = f.i - fi;
+      const T e = -sn * tx + cs * ty;
+      dq = T(1) + e * g.inv_sad;  // d / SAD
+      q = T(1) / dq;              // SAD / d, as in voxel_to_fan
+      col = y * g.nx + x;
+    }
+    unsigned long long mask = __ballot(member);
+    while (mask) {
+      const int src = __builtin_ctzll(mask);
+      mask &= mask - 1ull;
+      const int ck = bcast(kf, src), ci = bcast(ifl, src), cc = bcast(col, src);
+      const T cwk = bcast(wk, src), cwi = bcast(wi, src), cq = bcast(q, src), cdq = bcast(dq, src);
+      const T* gcol = g_t + (size_t)cc * g.nz;
+      T part[JS];
+#pragma unroll
+      for (int s = 0; s < JS; ++s) {
+        const int j = 64 * s + lane;
+        part[s] = j < g.Nv ? z_sum(g, j, cq, cdq, [&](int z) { return gcol[z]; }) : T(0);
+      }
+      T wK[BR_TK], wI[BR_TI];
+#pragma unroll
+      for (int a = 0; a < BR_TK; ++a) wK[a] = k0 + a == ck ? T(1) - cwk : (k0 + a == ck + 1 ? cwk : T(0));
+#pragma unroll
+      for (int c = 0; c < BR_TI; ++c) wI[c] = i0 + c == ci ? T(1) - cwi : (i0 + c == ci + 1 ? cwi : T(0));
+#pragma unroll
+      for (int a = 0; a < BR_TK; ++a)
+#pragma unroll
+        for (int c = 0; c < BR_TI; ++c) {
+          const T w2 = wK[a] * wI[c];
+#pragma unroll
+          for (int s = 0; s < JS; ++s) acc[a][c][s] += w2 * part[s];
+        }
+    }
+  }
+  const size_t plane = (size_t)g.Nu * g.Nv;
+  T* out_b = Ghat + (size_t)b * g.Nk * plane;
+#pragma unroll
+  for (int a = 0; a < BR_TK; ++a) {
+    if (k0 + a >= g.Nk) break;
+#pragma unroll
+    for (int c = 0; c < BR_TI; ++c) {
+      if (i0 + c >= g.Nu) break;
+      T* o = out_b + (size_t)(k0 + a) * plane + (size_t)(i0 + c) * g.Nv;
+#pragma unroll
+      for (int s = 0; s < JS; ++s) {
+        const int j = 64 * s + lane;
+        if (j < g.Nv) o[j] = acc[a][c][s];
+      }
+    }
+  }
+}
+
+template <typename T, int JS>
+static hipError_t launch_bp_reg(const Geo<T>& g, int nb, const T* frame, const T* g_t, T* Ghat, hipStream_t s) {
+  const int tiles_k = (g.Nk + BR_TK - 1) / BR_TK, tiles_i = (g.Nu + BR_TI - 1) / BR_TI;
+  const long n_waves = (long)nb * tiles_k * tiles_i;
+  const long blocks = (n_waves + 3) / 4;
+  const long per_xcd = (blocks + 7) / 8;
+  if (per_xcd * 8 > 0x7fffffffL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_backproject_reg<T, JS>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, s, g, nb, tiles_k,
+                     tiles_i, (int)per_xcd, frame, g_t, Ghat);
+  return hipGetLastError();
+}
+
 template <typename T, int JS, int ZS>
 static hipError_t launch_bp(const Geo<T>& g, int nb, const T* frame, const T* g_t, T* Ghat, hipStream_t s) {
   const size_t lds = sizeof(BpLds<T, JS>);
@@ -271,8 +416,12 @@ static hipError_t launch_bp_z(const Geo<T>& g, int nb, const T* frame, const T* 
 
 template <typename T>
 hipError_t launch_backproject_adj(const Geo<T>& g, int nb, const T* frame, const T* g_t, T* Ghat, hipStream_t s) {
-  // j chunks of 64 or 128 (FP64: 64, to keep the LDS image small)
-  if (sizeof(T) == 8 || g.Nv <= 64) return launch_bp_z<T, 1>(g, nb, frame, g_t, Ghat, s);
+  if (g.Nv <= 64) return launch_bp_reg<T, 1>(g, nb, frame, g_t, Ghat, s);
+  if (g.Nv <= 128) return launch_bp_reg<T, 2>(g, nb, frame, g_t, Ghat, s);
+  if (g.Nv <= 192) return launch_bp_reg<T, 3>(g, nb, frame, g_t, Ghat, s);
+  if (g.Nv <= 256) return launch_bp_reg<T, 4>(g, nb, frame, g_t, Ghat, s);
+  // wider planes: the LDS-tiled kernel, j in chunks of 64 or 128 (FP64: 64)
+  if (sizeof(T) == 8) return launch_bp_z<T, 1>(g, nb, frame, g_t, Ghat, s);
   return launch_bp_z<T, 2>(g, nb, frame, g_t, Ghat, s);
 }
 
