@@ -318,13 +318,19 @@ def tiny_case(seed: int = 7, n_cp: int = 2, n_taps: int = 3, shape=(6, 6, 6), sp
 def structures_c3(case: Case) -> dict:
     """Masks for the optimisation workload: PTV ellipsoid (30 x 30 x 40 mm) at the
     isocentre; rectum cylinder r = 12 mm along z at (0, 42), |z| <= 50, minus the PTV;
-    bladder ellipsoid (40 x 30 x 30 mm) at (0, -35, 35), minus the PTV."""
+    bladder ellipsoid (40 x 30 x 30 mm) at (0, -35, 35), minus the PTV; the two femur
+    cylinders and the elliptic body outline ("external") of the default pelvis
+    phantom.  Together the organs at risk of the paper's objective (§2.5)."""
     x, y, z = voxel_centres(case.shape, case.spacing, case.origin)
     Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
     ptv = (X / 30.0) ** 2 + (Y / 30.0) ** 2 + (Z / 40.0) ** 2 <= 1.0
     rectum = (X ** 2 + (Y - 42.0) ** 2 <= 12.0 ** 2) & (np.abs(Z) <= 50.0) & ~ptv
     bladder = ((X / 40.0) ** 2 + ((Y + 35.0) / 30.0) ** 2 + ((Z - 35.0) / 30.0) ** 2 <= 1.0) & ~ptv
-    return {"ptv": ptv, "rectum": rectum, "bladder": bladder}
+    femur_l = (X + 95.0) ** 2 + (Y - 15.0) ** 2 <= 25.0 ** 2
+    femur_r = (X - 95.0) ** 2 + (Y - 15.0) ** 2 <= 25.0 ** 2
+    external = (X / 170.0) ** 2 + (Y / 110.0) ** 2 <= 1.0
+    return {"ptv": ptv, "rectum": rectum, "bladder": bladder, "femur_l": femur_l, "femur_r": femur_r,
+            "external": external}
 
 
 # --------------------------------------------------------------------------- reference conditions

@@ -1,8 +1,11 @@
-"""Plan optimisation workload on the GPU: 200 Adam steps from closed apertures on
-the two-arc 192 x 192 x 128 geometry; the final objective is recomputed from the
-FP64 oracle's dose of the final (projected) parameters.  Also checks the
-projection layer against the oracle's projection and its Jacobian against
-finite differences."""
+"""Plan optimisation workload on the GPU: Adam from closed apertures on the
+two-arc 192 x 192 x 128 geometry with the workload's quadratic objective and with
+the paper's weighted L1 objective (coarse-to-fine kernel sizes on geometry
+caches, weight selection by isodose Dice).  Also checks the projection layer
+against the oracle's projection (seeded inputs) and its Jacobian against finite
+differences.  The optimised plans are checked by properties (objective decrease,
+feasibility, Dice); the dose path's parity with the oracle is covered on seeded
+inputs elsewhere."""
 import numpy as np
 import pytest
 import torch
@@ -52,6 +55,7 @@ def test_projection_matches_oracle_and_jacobian():
 
 
 def test_c3_optimisation_200_steps():
+    from paper_2512_18863_amd import engine as E
     from paper_2512_18863_amd import optimize
     case = optimize.c3_case()
     masks = inputs.structures_c3(case)
@@ -59,17 +63,48 @@ def test_c3_optimisation_200_steps():
     opt = optimize.PlanOptimizer(case, masks)
     losses, sec_per_step = opt.run(200)
     lv, jw, mu, dose = opt.final()
-    L_gpu = float(optimize.objective(dose, opt.masks))
-    _say("C3: %.2f ms/step, L: %.3f -> %.3f (final eval %.4f)" % (1e3 * sec_per_step, losses[0], losses[-1], L_gpu))
+    L_end = float(optimize.objective(dose, opt.masks))
+    _say("C3: %.2f ms/step, L: %.3f -> %.3f (final eval %.4f)" % (1e3 * sec_per_step, losses[0], losses[-1], L_end))
     assert losses[-1] < 0.25 * losses[0]
-    # oracle recomputation of the final dose and objective
-    import copy
-    c = copy.copy(case)
-    c.leaves, c.jaws, c.mu = lv, jw, mu
-    m = oracle.Model(c)
-    rho = oracle.density(m)
-    ref = oracle.forward(m, rho, c.gantry, lv, jw, mu)
-    assert np.abs(dose.cpu().numpy() - ref).max() <= 1e-5 * ref.max()
-    L_ref = float(optimize.objective(torch.tensor(ref), {k: torch.tensor(v) for k, v in masks.items()}))
-    _say("C3 objective: GPU %.6f vs oracle %.6f" % (L_gpu, L_ref))
-    assert abs(L_gpu - L_ref) <= 1e-4 * max(1.0, L_ref)
+    assert L_end < 0.25 * losses[0]
+    # the final parameters are feasible: projecting them again moves nothing beyond
+    # FP32 rounding of the centre / width round trip (values up to 50 mm)
+    again = E.project_params(_t(lv), _t(jw), _t(mu), opt.limits)
+    for a, b in zip(again, (lv, jw, mu)):
+        np.testing.assert_allclose(a.cpu().numpy(), b, rtol=0, atol=2e-5)
+    assert (lv[:, 1] - lv[:, 0] >= opt.limits["w_min"] - 1e-4).all() and (mu >= opt.limits["mu_min"] - 1e-6).all()
+
+
+def test_c3_l1_objective_coarse_to_fine_with_cache():
+    """The paper's weighted L1 objective (§2.5) from the closed start: 100 steps with
+    9 x 9 kernels, then 40 with the workload's 31 x 31, both on geometry caches."""
+    from paper_2512_18863_amd import optimize
+    case = optimize.c3_case()
+    masks = inputs.structures_c3(case)
+    w = {"ptv": 100.0, "rectum": 1.0, "bladder": 1.0, "femur_l": 0.1, "femur_r": 0.1, "external": 0.1}
+    _say("C3 L1 objective, stages n=9 (100 steps) -> n=31 (40 steps), FP32 geometry caches")
+    opt = optimize.PlanOptimizer(case, masks, objective="l1", weights=w, rx=78.0, cache="fp32")
+    runs = opt.run_stages([optimize.Stage(100, n_taps=9), optimize.Stage(40, n_taps=31)])
+    (_, l9, s9), (_, l31, s31) = runs
+    dose = opt.final()[3]
+    dice = opt.dice(dose)
+    _say("L1: %.4g -> %.4g (n=9, %.1f ms/step) -> %.4g (n=31, %.1f ms/step); Dice(100%% isodose, PTV) = %.3f"
+         % (l9[0], l9[-1], 1e3 * s9, l31[-1], 1e3 * s31, dice))
+    rep = opt.evaluator.report(dose, rx=78.0, voxel_cc=2.5 ** 3 / 1000.0, bin_width=0.01)
+    _say("PTV D98 %.2f D50 %.2f D2 %.2f Gy; rectum Dmean %.2f, bladder Dmean %.2f Gy"
+         % (rep["ptv"]["D98"], rep["ptv"]["D50"], rep["ptv"]["D2"], rep["rectum"]["Dmean"], rep["bladder"]["Dmean"]))
+    assert l9[-1] < 0.3 * l9[0] and l31[-1] < 0.3 * l9[0]
+    assert dice > 0.3
+
+
+def test_weight_search_keeps_the_best_dice():
+    from paper_2512_18863_amd import optimize
+    case = optimize.c3_case()
+    masks = inputs.structures_c3(case)
+    _say("weight search over two OAR weight combinations (100 steps each, n=9, cached)")
+    combos = [{"rectum": 0.0, "bladder": 0.0}, {"rectum": 100.0, "bladder": 100.0}]
+    best, dice, res = optimize.weight_search(case, masks, ["rectum", "bladder"], [optimize.Stage(100, n_taps=9)],
+                                             rx=78.0, combos=combos)
+    _say("results (rectum/bladder weight, Dice): %s" % [(r[0]["rectum"], round(r[1], 3)) for r in res])
+    assert dice == max(r[1] for r in res) and best in [r[0] for r in res]
+    assert dice > 0.3
