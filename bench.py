@@ -113,6 +113,18 @@ def traffic_from_counters(fetch_csv, write_csv, workload="c4bench_fp32"):
     print("wrote", path)
 
 
+def aperture_pixels(jaws, lat, Nu, Nv):
+    """Per control point, the fan pixels that overlap the jaw opening: the fluence
+    (hence the primary P = F G) is zero elsewhere, and the parameter gradients read
+    the adjoint only there.  These are the nodes the lateral convolution has to
+    process, in either direction: 2 n^2 flops per aperture node and plane."""
+    import numpy as np
+    def count(a, b, N):
+        c = (np.arange(N) - (N - 1) / 2.0) * lat
+        return int(((c + lat / 2 > a) & (c - lat / 2 < b)).sum())
+    return np.array([count(j[0], j[1], Nu) * count(j[2], j[3], Nv) for j in np.asarray(jaws)])
+
+
 def hbm_table(kernels, steps, n_cp, nodes, plane, vox):
     """Achieved bandwidth of the memory-bound kernels from their algorithmic bytes
     (each byte the kernel must move once): nodes = beam-frame nodes of the plan,
@@ -312,7 +324,9 @@ def main():
     conv_name = "conv_mfma_f32"
     launches, total_ms = kernels.get(conv_name, (0, 0.0))
     avg_s = total_ms / max(launches, 1) / 1e3
-    flops = 2.0 * n * n * nodes
+    ap_nodes = int(aperture_pixels(case.jaws, case.lat_step, eng.Nu, eng.Nv).sum()) * eng.Nk
+    flops = 2.0 * n * n * ap_nodes           # the convolution's work on the aperture nodes
+    dense_flops = 2.0 * n * n * nodes        # every beam-frame node (what a dense convolution does)
     achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
     traffic = measured_traffic(conv_name, "c4bench_fp32")
     out = {
@@ -337,7 +351,10 @@ def main():
                      "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
                      "traffic": traffic,
                      "flops_per_launch": flops, "avg_launch_ms": round(avg_s * 1e3, 4),
-                     "launches": launches},
+                     "launches": launches,
+                     "work": "2 n^2 flops per aperture node (fan pixels overlapping the jaw opening x planes): "
+                             "%d of %d nodes" % (ap_nodes, nodes),
+                     "dense_equivalent_TFLOPs": round(dense_flops / avg_s / 1e12, 3) if avg_s > 0 else 0.0},
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(kernels.items())},
         "hbm_kernels": hbm_table(kernels, args.steps, n_cp, nodes, eng.Nu * eng.Nv, int(np.prod(case.shape))),
         "paper_context": {"value": 35.3, "unit": "control points/s (fwd+bwd)", "hardware": "NVIDIA A40",

@@ -125,11 +125,13 @@ size_t pdrt_workspace_bytes(const pdrt_grid* grid, const pdrt_beam* beam, const 
 
 /* Byte offsets of the intermediates inside the workspace after a forward call
  * (debugging and tests): frame, rho_t ([ny][nx][nz]), F ([B][Nu][Nv]), z ([B][Nk]),
- * P and Dfan ([B][Nk][Nu][Nv]), A ([B][Nu][Nv]), comp, and the two fluence-correction
- * scratch maps fc_tmp (2 x [B][Nu][Nv], present only with fluence corrections); B =
- * control points per batch; the arrays hold the last batch. */
+ * P and Dfan ([B][Nk][Nu][Nv]), A ([B][Nu][Nv]), comp, the two fluence-correction
+ * scratch maps fc_tmp (2 x [B][Nu][Nv], present only with fluence corrections) and
+ * box (int32 [B][4]: each control point's aperture rectangle u0, u1, v0, v1 of fan
+ * pixels outside which the fluence and its derivatives vanish); B = control points
+ * per batch; the arrays hold the last batch. */
 typedef struct {
-  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, fc_tmp, total;
+  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, fc_tmp, box, total;
   int32_t batch;
 } pdrt_ws_layout;
 int pdrt_workspace_layout(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spec* spec,

@@ -176,6 +176,8 @@ int size_problem(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel
   off += align256(nvox * elem);
   L.fc_tmp = off;
   if (spec->fluence_corr) off += align256((size_t)2 * B * plane * elem);
+  L.box = off;
+  off += align256((size_t)4 * B * sizeof(int));
   L.total = off;
   return PDRT_OK;
 }
@@ -255,20 +257,24 @@ void make_fc_taps(const pdrt_kernel_spec* spec, FcTaps<T>* t) {
 // convolutions are faster.
 constexpr int kMfmaMinTaps = 13;
 
+// box / support: the aperture rectangles of the batch and how the convolution may
+// use them (CONV_IN_BOX forward, CONV_OUT_BOX adjoint); kernels without support
+// handling compute the dense convolution, which is a superset.
 template <typename T>
-hipError_t run_conv(const Geo<T>& g, int conv_mode, int nb, const T* z, const T* in, T* out, hipStream_t s);
+hipError_t run_conv(const Geo<T>& g, int conv_mode, int nb, const T* z, const T* in, T* out, hipStream_t s,
+                    const int* box, int support);
 
 template <>
 hipError_t run_conv<double>(const Geo<double>& g, int, int nb, const double* z, const double* in, double* out,
-                            hipStream_t s) {
+                            hipStream_t s, const int*, int) {
   return launch_conv_direct<double>(g, nb, z, in, out, s);
 }
 
 template <>
 hipError_t run_conv<float>(const Geo<float>& g, int conv_mode, int nb, const float* z, const float* in, float* out,
-                           hipStream_t s) {
+                           hipStream_t s, const int* box, int support) {
   if (conv_mode == PDRT_CONV_BF16) return launch_conv_mfma_bf16(g, nb, z, in, out, s);
-  if (g.n_taps >= kMfmaMinTaps) return launch_conv_mfma_f32(g, nb, z, in, out, s);
+  if (g.n_taps >= kMfmaMinTaps) return launch_conv_mfma_f32(g, nb, z, in, out, s, box, support);
   if (conv_small_supported(g)) return launch_conv_small(g, nb, z, in, out, s);
   return launch_conv_direct<float>(g, nb, z, in, out, s);
 }
@@ -357,6 +363,9 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
   T* t1 = t0 + (size_t)P.batch * P.Nu * P.Nv;
   FcTaps<T> fct;
   if (g.fcorr) make_fc_taps<T>(spec, &fct);
+  int* box = (int*)(w + P.lay.box);
+  // the corrections spread the aperture's fluence by their blur radii
+  const int box_du = g.fcorr ? fct.pu.R + fct.hs.R : 0, box_dv = g.fcorr ? fct.pv.R + fct.hs.R : 0;
   const T* dd = (const T*)spec->dd;
   const int L = beam->n_leaf_pairs, n_cp = beam->n_cp;
   LAUNCH("frame", launch_frame<T>(g, (const T*)beam->gantry_deg, n_cp, frame, s));
@@ -365,6 +374,7 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
     int nb = n_cp - cp0 < P.batch ? n_cp - cp0 : P.batch;
     const T* fr = frame + 2 * cp0;
     LAUNCH("raster", launch_raster<T>(g, nb, leaves + (size_t)2 * L * cp0, jaws + (size_t)4 * cp0, F, s));
+    LAUNCH("aperture_box", launch_aperture_box<T>(g, nb, jaws + (size_t)4 * cp0, box_du, box_dv, box, s));
     if (g.fcorr) {
       // F1 = G_v G_u F; F <- O (F1 + a G_hv G_hu F1)
       LAUNCH("fluence_corr", launch_blur<T>(g, nb, 0, fct.pu, F, t0, s));
@@ -385,7 +395,8 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
       LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
       LAUNCH("march", launch_march<T>(g, nb, fr, rho_t, F, z, dd, vol0, s));
     }
-    LAUNCH(conv_name<T>(g, spec->conv_mode), run_conv<T>(g, spec->conv_mode, nb, zb, vol0, vol1, s));
+    LAUNCH(conv_name<T>(g, spec->conv_mode),
+           run_conv<T>(g, spec->conv_mode, nb, zb, vol0, vol1, s, box, CONV_IN_BOX));
     LAUNCH("gather", launch_gather<T>(g, nb, cp0 == 0, cp0 + nb == n_cp, fr, mu + cp0, vol1, dose, comp, s));
   }
   return PDRT_OK;
@@ -415,6 +426,10 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
   T* t1 = t0 + (size_t)P.batch * P.Nu * P.Nv;
   FcTaps<T> fct;
   if (g.fcorr) make_fc_taps<T>(spec, &fct);
+  int* box = (int*)(w + P.lay.box);
+  // the parameter gradients read A inside the aperture rectangle; the corrections'
+  // adjoint gathers it from as far as their blur radii
+  const int box_du = g.fcorr ? fct.pu.R + fct.hs.R : 0, box_dv = g.fcorr ? fct.pv.R + fct.hs.R : 0;
   const T* dd = (const T*)spec->dd;
   const int L = beam->n_leaf_pairs, n_cp = beam->n_cp;
   LAUNCH("frame", launch_frame<T>(g, (const T*)beam->gantry_deg, n_cp, frame, s));
@@ -428,8 +443,10 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
       if (gc) zb = gc->z + (size_t)cp0 * g.Nk;
     }
     if (!gc) LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
+    LAUNCH("aperture_box", launch_aperture_box<T>(g, nb, jaws + (size_t)4 * cp0, box_du, box_dv, box, s));
     LAUNCH("backproject_adj", launch_backproject_adj<T>(g, nb, fr, g_t, vol0, s));
-    LAUNCH(conv_name<T>(g, spec->conv_mode), run_conv<T>(g, spec->conv_mode, nb, zb, vol0, vol1, s));
+    LAUNCH(conv_name<T>(g, spec->conv_mode),
+           run_conv<T>(g, spec->conv_mode, nb, zb, vol0, vol1, s, box, CONV_OUT_BOX));
     if constexpr (std::is_same<T, float>::value) {
       if (gc)
         LAUNCH("geometry_adjoint", gc->type == PDRT_CACHE_F32
@@ -498,6 +515,7 @@ int pdrt_workspace_layout(const pdrt_grid* grid, const pdrt_beam* beam, const pd
   out->adj = P.lay.adj;
   out->comp = P.lay.comp;
   out->fc_tmp = P.lay.fc_tmp;
+  out->box = P.lay.box;
   out->total = P.lay.total;
   out->batch = P.batch;
   return PDRT_OK;

@@ -50,22 +50,15 @@ static RegionShape region_shape(int Nu, int Nv, int rmax) {
   return r;
 }
 
-template <int TPW>
-__device__ __forceinline__ void store_tiles(const Geo<float>& g, const RegionShape& rs, int NW, int wave, int I0,
-                                            int J0, int lane, const f32x4 (&acc)[TPW], const bool (&active)[TPW],
-                                            float* dst) {
+// One 16 x 16 output tile at plane position (i0, j0), clipped to the plane.
+__device__ __forceinline__ void store_tile_at(const Geo<float>& g, int i0, int j0, int lane, const f32x4& acc,
+                                              float* dst) {
   const int m = lane & 15, r4 = lane >> 4;
+  const int j = j0 + m;
 #pragma unroll
-  for (int q = 0; q < TPW; ++q) {
-    if (!active[q]) continue;
-    int t = wave + NW * q;
-    int ti = t / rs.TJ, tj = t - ti * rs.TJ;
-    int j = J0 + MT * tj + m;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int i = I0 + MT * ti + 4 * r4 + r;
-      if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[q][r];
-    }
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + 4 * r4 + r;
+    if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[r];
   }
 }
 
@@ -103,11 +96,97 @@ static size_t f32_lds(int h, const F32Shape& fs) {
 
 constexpr int PF = 12;  // prefetched elements per thread
 
+// The matrix loop over tap rows p in [pa, pb] and super-steps u in [ua, ub] for
+// NA tiles that share the Toeplitz operand.  Two operand sets are loaded
+// alternately one step ahead of their use: the loop body covers two steps, so no
+// register copies sit between a load and the matrix instructions it feeds.
+// B[k][n] of instruction s in super-step u = K[p][16 u + 4 k + s - h - n]
+//                                           = kx[p][16 u + 4 k + s + 15 - n].
+template <int NA>
+__device__ __forceinline__ void f32_steps(const float* const* abase, const float* bbase, int pitch, int E, int pa,
+                                          int pb, int ua, int ub, f32x4* acc) {
+  const int nu = ub - ua + 1;
+  const int total = (pb >= pa && nu > 0) ? (pb - pa + 1) * nu : 0;
+  const float* ab[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) ab[q] = abase[q];
+  f32x4 ac_[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) ac_[q] = acc[q];
+  int lp = pa, lu = ua;  // next step to load: tap row lp, super-step lu
+  auto load = [&](f32x4v (&a0)[NA], f32x4v (&a1)[NA], float (&bb)[4]) {
+    const int op = lp * pitch + 16 * lu, om = 16 * lu - lp * pitch;
+    const float* br = bbase + lp * E + 16 * lu;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bb[e] = br[e];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      a0[q] = *reinterpret_cast<const f32x4v*>(ab[q] + op);
+      a1[q] = *reinterpret_cast<const f32x4v*>(ab[q] + om);
+    }
+    if (++lu > ub) {
+      lu = ua;
+      ++lp;
+    }
+  };
+  auto compute = [&](const f32x4v (&a0)[NA], const f32x4v (&a1)[NA], const float (&bb)[4]) {
+    f32x4v ac[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) ac[q] = a0[q] + a1[q];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int q = 0; q < NA; ++q) ac_[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[q][e], bb[e], ac_[q], 0, 0, 0);
+  };
+  if (total > 0) {
+    f32x4v x0[NA], x1[NA], y0[NA], y1[NA];
+    float bx[4], by[4];
+    load(x0, x1, bx);
+    for (int st = 0; st < total; st += 2) {
+      const bool two = st + 1 < total;
+      if (two) load(y0, y1, by);
+      compute(x0, x1, bx);
+      if (st + 2 < total) load(x0, x1, bx);
+      if (two) compute(y0, y1, by);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NA; ++q) acc[q] = ac_[q];
+}
+
+// The part of a plane's data rectangle that lies inside the box [u0, u1) x [v0, v1).
+__device__ __forceinline__ DataRect clip_rect(const DataRect& d, int4 bx) {
+  DataRect c;
+  const int r0 = max(d.r0, bx.x), r1 = min(d.r0 + d.nr, bx.y);
+  const int c0 = max(d.c0, bx.z), c1 = min(d.c0 + d.nc, bx.w);
+  c.r0 = r0;
+  c.c0 = c0;
+  c.nr = r1 > r0 && c1 > c0 ? r1 - r0 : 0;
+  c.nc = r1 > r0 && c1 > c0 ? c1 - c0 : 1;
+  c.lr0 = d.lr0 + (r0 - d.r0);
+  c.lc0 = d.lc0 + (c0 - d.c0);
+  return c;
+}
+
+__device__ __forceinline__ int floor_div16(int a) { return a >= 0 ? a / 16 : -((15 - a) / 16); }
+
+// Support of the convolution (box: per control point [u0, u1) x [v0, v1), the
+// aperture's rectangle outside which the fluence and its derivatives vanish):
+//   CONV_DENSE    every input and output;
+//   CONV_IN_BOX   the input is zero outside the box (forward: P = F G): only the
+//                 box is staged, and each wavefront skips the tap rows and column
+//                 super-steps whose inputs all lie outside it (exact zeros);
+//   CONV_OUT_BOX  only outputs in the box are needed (adjoint: the parameter
+//                 gradients read A only there): the region's tiles that meet the
+//                 box are spread over the wavefronts, every other output is 0.
+// The matrix arithmetic of every computed output is that of the dense kernel.
+
 // Items it = blockIdx.x, blockIdx.x + gridDim.x, ... with region = it % regions
 // and (control point, plane) = it / regions; gridDim.x is a multiple of the
 // region count, so a workgroup keeps one region.
-template <int NW, int TPW>
+template <int NW, int TPW, int SUP>
 __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionShape rs, F32Shape fs, int n_items,
+                                                           const int4* __restrict__ box,
                                                            const float* __restrict__ zca,
                                                            const float* __restrict__ in, float* __restrict__ out) {
   extern __shared__ __align__(16) float lds[];
@@ -127,31 +206,48 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int m = lane & 15, kk = lane >> 4;
-  const float* abase[TPW];
+  // this wavefront's fixed tiles t = wave + NW q (all of them stored every item)
+  int tI[TPW], tJ[TPW];
   bool active[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
     int t = wave + NW * q;
     bool valid = t < rs.TI * rs.TJ;
-    int ti = valid ? t / rs.TJ : 0, tj = valid ? t - (t / rs.TJ) * rs.TJ : 0;
-    active[q] = valid && I0 + MT * ti < g.Nu && J0 + MT * tj < g.Nv;
-    abase[q] = tile + (MT * ti + m + h) * pitch + MT * tj + 4 * kk;
+    tI[q] = valid ? t / rs.TJ : 0;
+    tJ[q] = valid ? t - (t / rs.TJ) * rs.TJ : 0;
+    active[q] = valid && I0 + MT * tI[q] < g.Nu && J0 + MT * tJ[q] < g.Nv;
   }
-  // B[k][n] of instruction s in super-step u = K[p][16 u + 4 k + s - h - n] = kx[p][16 u + 4 k + s + 15 - n]
   const float* bbase = kx + 4 * kk + 15 - m;
-  const int total = (h + 1) * SS;
   const int off = h + 15;
+  auto a_of = [&](int ti, int tj) { return tile + (MT * ti + m + h) * pitch + MT * tj + 4 * kk; };
+  auto rect_of = [&](int item) {
+    if (SUP == CONV_IN_BOX) return clip_rect(dr, box[(item / nreg) / g.Nk]);
+    return dr;
+  };
 
   zero_lds(tile, rows * pitch, tid, NT);
   float buf[PF];
   int it = blockIdx.x;
-  if (it < n_items) fetch_rect<PF>(in + (size_t)(it / nreg) * plane, g.Nv, dr, tid, NT, buf);
+  DataRect cur = rect_of(it < n_items ? it : 0);
+  DataRect prev = cur;
+  prev.nr = 0;
+  prev.nc = 1;
+  if (it < n_items) fetch_rect<PF>(in + (size_t)(it / nreg) * plane, g.Nv, cur, tid, NT, buf);
   __syncthreads();
   for (; it < n_items; it += gridDim.x) {
     const int bk = it / nreg;  // b * Nk + k
     const int k = bk % g.Nk;
     const float* src = in + (size_t)bk * plane;
-    put_rect<PF>(src, g.Nv, dr, pitch, tid, NT, buf, tile);
+    put_rect<PF>(src, g.Nv, cur, pitch, tid, NT, buf, tile);
+    if (SUP == CONV_IN_BOX) {
+      // clear what the previous item wrote outside this item's rectangle
+      for (int idx = tid; idx < prev.nr * prev.nc; idx += NT) {
+        const int r = idx / prev.nc, c = idx - r * prev.nc;
+        const int lr = prev.lr0 + r, lc = prev.lc0 + c;
+        const bool in_cur = lr >= cur.lr0 && lr < cur.lr0 + cur.nr && lc >= cur.lc0 && lc < cur.lc0 + cur.nc;
+        if (!in_cur) tile[lr * pitch + lc] = 0.f;
+      }
+    }
     unique_taps(g, k, zca[bk], kq, tid, NT);
     __syncthreads();
     for (int idx = tid; idx < (h + 1) * E; idx += NT) {
@@ -164,50 +260,99 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     __syncthreads();
     // next item's input, in flight while this item's matrix work runs
     const int nx = it + gridDim.x;
-    if (nx < n_items) fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, dr, tid, NT, buf);
+    DataRect nxt = cur;
+    if (nx < n_items) {
+      nxt = rect_of(nx);
+      fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, nxt, tid, NT, buf);
+    }
+    float* dst = out + (size_t)bk * plane;
 
-    f32x4 acc[TPW];
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // Two operand sets, loaded alternately one step ahead of their use: the
-    // loop body covers two steps, so no register copies sit between a load and
-    // the matrix instructions it feeds.
-    int lp = 0, lu = 0;  // next step to load: tap row lp, super-step lu
-    auto load = [&](f32x4v (&a0)[TPW], f32x4v (&a1)[TPW], float (&bb)[4]) {
-      const int op = lp * pitch + 16 * lu, om = 16 * lu - lp * pitch;
-      const float* br = bbase + lp * E + 16 * lu;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) bb[e] = br[e];
+    if (SUP == CONV_OUT_BOX) {
+      // tiles of the region that meet the box: ti in [ta, tb], tj in [sa, sb]
+      const int4 bx = box[bk / g.Nk];
+      const int ta = max(0, floor_div16(bx.x - I0)), tb = min(rs.TI - 1, floor_div16(bx.y - 1 - I0));
+      const int sa = max(0, floor_div16(bx.z - J0)), sb = min(rs.TJ - 1, floor_div16(bx.w - 1 - J0));
+      const int nI = bx.y > bx.x && tb >= ta ? tb - ta + 1 : 0;
+      const int nJ = bx.w > bx.z && sb >= sa ? sb - sa + 1 : 0;
+      const int nneed = nI * nJ;
+      // outputs of the wavefront's fixed tiles that lie outside the box rectangle are 0
+      const f32x4 zero4 = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int q = 0; q < TPW; ++q) {
-        a0[q] = *reinterpret_cast<const f32x4v*>(abase[q] + op);
-        a1[q] = *reinterpret_cast<const f32x4v*>(abase[q] + om);
+        const bool needed = tI[q] >= ta && tI[q] < ta + nI && tJ[q] >= sa && tJ[q] < sa + nJ;
+        if (active[q] && !needed) store_tile_at(g, I0 + MT * tI[q], J0 + MT * tJ[q], lane, zero4, dst);
       }
-      if (++lu == SS) {
-        lu = 0;
-        ++lp;
+      // the needed tiles, n = wave, wave + NW, ...
+      int nact = 0;
+      const float* ab[TPW];
+      int oI[TPW], oJ[TPW];
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        const int n = wave + NW * q;
+        const bool use = n < nneed;
+        const int ti = use ? ta + n / nJ : 0, tj = use ? sa + n % max(nJ, 1) : 0;
+        ab[q] = a_of(ti, tj);
+        oI[q] = I0 + MT * ti;
+        oJ[q] = J0 + MT * tj;
+        nact += use ? 1 : 0;
       }
-    };
-    auto compute = [&](const f32x4v (&a0)[TPW], const f32x4v (&a1)[TPW], const float (&bb)[4]) {
-      f32x4v ac[TPW];
+      f32x4 acc[TPW];
 #pragma unroll
-      for (int q = 0; q < TPW; ++q) ac[q] = a0[q] + a1[q];
+      for (int q = 0; q < TPW; ++q) acc[q] = zero4;
+      if (nact == 1) f32_steps<1>(ab, bbase, pitch, E, 0, h, 0, SS - 1, acc);
+      if (TPW >= 2 && nact == 2) f32_steps<TPW >= 2 ? 2 : 1>(ab, bbase, pitch, E, 0, h, 0, SS - 1, acc);
+      if (TPW >= 3 && nact == 3) f32_steps<TPW >= 3 ? 3 : 1>(ab, bbase, pitch, E, 0, h, 0, SS - 1, acc);
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int q = 0; q < TPW; ++q)
+        if (q < nact && oI[q] < g.Nu && oJ[q] < g.Nv) store_tile_at(g, oI[q], oJ[q], lane, acc[q], dst);
+    } else {
+      int pa = 0, pb = h, ua = 0, ub = SS - 1;
+      if (SUP == CONV_IN_BOX) {
+        // hull over the wavefront's tiles of the tap rows and super-steps that reach the input rectangle
+        pa = h + 1;
+        pb = -1;
+        ua = SS;
+        ub = -1;
+        const int r0 = cur.r0, r1 = cur.r0 + cur.nr, c0 = cur.c0, c1 = cur.c0 + cur.nc;
+        if (cur.nr > 0) {
 #pragma unroll
-        for (int q = 0; q < TPW; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[q][e], bb[e], acc[q], 0, 0, 0);
-    };
-    f32x4v x0[TPW], x1[TPW], y0[TPW], y1[TPW];
-    float bx[4], by[4];
-    load(x0, x1, bx);
-    for (int st = 0; st < total; st += 2) {
-      const bool two = st + 1 < total;
-      if (two) load(y0, y1, by);
-      compute(x0, x1, bx);
-      if (st + 2 < total) load(x0, x1, bx);
-      if (two) compute(y0, y1, by);
+          for (int q = 0; q < TPW; ++q) {
+            if (!active[q]) continue;
+            const int I = I0 + MT * tI[q], cb = J0 + MT * tJ[q] - h;
+            const int u_lo = max(0, floor_div16(c0 - cb)), u_hi = min(SS - 1, floor_div16(c1 - 1 - cb));
+            // rows I + p .. I + p + 15 or I - p .. I - p + 15 meet [r0, r1)
+            int p_lo = h + 1, p_hi = -1;
+            const int a1 = max(0, r0 - I - 15), b1 = min(h, r1 - I - 1);
+            if (a1 <= b1) {
+              p_lo = min(p_lo, a1);
+              p_hi = max(p_hi, b1);
+            }
+            const int a2 = max(0, I - r1 + 1), b2 = min(h, I + 15 - r0);
+            if (a2 <= b2) {
+              p_lo = min(p_lo, a2);
+              p_hi = max(p_hi, b2);
+            }
+            if (u_lo > u_hi || p_lo > p_hi) continue;
+            pa = min(pa, p_lo);
+            pb = max(pb, p_hi);
+            ua = min(ua, u_lo);
+            ub = max(ub, u_hi);
+          }
+        }
+      }
+      const float* ab[TPW];
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) ab[q] = a_of(tI[q], tJ[q]);
+      f32x4 acc[TPW];
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+      f32_steps<TPW>(ab, bbase, pitch, E, pa, pb, ua, ub, acc);
+#pragma unroll
+      for (int q = 0; q < TPW; ++q)
+        if (active[q]) store_tile_at(g, I0 + MT * tI[q], J0 + MT * tJ[q], lane, acc[q], dst);
     }
-    store_tiles<TPW>(g, rs, NW, wave, I0, J0, lane, acc, active, out + (size_t)bk * plane);
+    prev = cur;
+    cur = nxt;
     __syncthreads();  // the LDS image and taps are rewritten for the next item
   }
 }
@@ -409,12 +554,13 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
 
 // Persistent grid: as many workgroups as fit on the device at once (a multiple of
 // the region count), never more than there are items.
-template <int NW, int TPW, typename Shape, typename Kern>
-static hipError_t launch_cfg(Kern kern, const Geo<float>& g, const RegionShape& rs, const Shape& sh, size_t lds,
-                             int nb, const float* z, const float* in, float* out, hipStream_t s) {
+template <int NW, int TPW, int SUP>
+static hipError_t launch_f32_cfg(const Geo<float>& g, const RegionShape& rs, const F32Shape& fs, size_t lds, int nb,
+                                 const int4* box, const float* z, const float* in, float* out, hipStream_t s) {
+  const void* kern = (const void*)k_conv_mfma_f32<NW, TPW, SUP>;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
     if (e != hipSuccess) return e;
     attr = true;
   }
@@ -422,21 +568,25 @@ static hipError_t launch_cfg(Kern kern, const Geo<float>& g, const RegionShape& 
   const int nreg = rs.regions_i * rs.regions_j;
   const long n_items = (long)nreg * g.Nk * nb;
   if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;
-  const int grid = persistent_grid((const void*)kern, 64 * NW, lds, nreg, n_items);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, s, g, rs, sh, (int)n_items, z, in, out);
+  const int grid = persistent_grid(kern, 64 * NW, lds, nreg, n_items);
+  hipLaunchKernelGGL((k_conv_mfma_f32<NW, TPW, SUP>), dim3(grid), dim3(64 * NW), lds, s, g, rs, fs, (int)n_items,
+                     box, z, in, out);
   return hipGetLastError();
 }
 
-#define PDRT_CONV_DISPATCH(KERN, SHAPE)                                                          \
-  int tiles = rs.TI * rs.TJ;                                                                     \
-  if (tiles <= 4) return launch_cfg<4, 1>(KERN<4, 1>, g, rs, SHAPE, lds, nb, z, in, out, s);     \
-  if (tiles <= 8) return launch_cfg<8, 1>(KERN<8, 1>, g, rs, SHAPE, lds, nb, z, in, out, s);     \
-  if (tiles <= 16) return launch_cfg<8, 2>(KERN<8, 2>, g, rs, SHAPE, lds, nb, z, in, out, s);    \
-  if (tiles <= 24) return launch_cfg<8, 3>(KERN<8, 3>, g, rs, SHAPE, lds, nb, z, in, out, s);    \
-  return launch_cfg<12, 3>(KERN<12, 3>, g, rs, SHAPE, lds, nb, z, in, out, s);
+template <int SUP>
+static hipError_t launch_f32_sup(const Geo<float>& g, const RegionShape& rs, const F32Shape& fs, size_t lds, int nb,
+                                 const int4* box, const float* z, const float* in, float* out, hipStream_t s) {
+  const int tiles = rs.TI * rs.TJ;
+  if (tiles <= 4) return launch_f32_cfg<4, 1, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
+  if (tiles <= 8) return launch_f32_cfg<8, 1, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
+  if (tiles <= 16) return launch_f32_cfg<8, 2, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
+  if (tiles <= 24) return launch_f32_cfg<8, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
+  return launch_f32_cfg<12, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
+}
 
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
-                                hipStream_t s) {
+                                hipStream_t s, const int* box, int support) {
   RegionShape rs;
   F32Shape fs;
   size_t lds = 0;
@@ -446,7 +596,10 @@ hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, con
     lds = f32_lds(g.h, fs);
     if (lds <= LDS_MAX) break;
   }
-  PDRT_CONV_DISPATCH(k_conv_mfma_f32, fs)
+  const int4* bx = reinterpret_cast<const int4*>(box);
+  if (!bx || support == CONV_DENSE) return launch_f32_sup<CONV_DENSE>(g, rs, fs, lds, nb, bx, z, in, out, s);
+  if (support == CONV_IN_BOX) return launch_f32_sup<CONV_IN_BOX>(g, rs, fs, lds, nb, bx, z, in, out, s);
+  return launch_f32_sup<CONV_OUT_BOX>(g, rs, fs, lds, nb, bx, z, in, out, s);
 }
 
 template <int RJ, int SMAX>

@@ -130,6 +130,46 @@ hipError_t launch_raster(const Geo<T>& g, int nb, const T* leaves, const T* jaws
   return hipGetLastError();
 }
 
+// Rectangle of fluence pixels [u0, u1) x [v0, v1) of each control point outside
+// which F and all its derivatives are exactly zero: a pixel carries fluence only
+// if it overlaps the jaw opening (the factor f(u; x1, x2) f(v; y1, y2) of Eq. 4),
+// widened by one pixel for rounding and by (du, dv) pixels for the reach of the
+// fluence corrections.  A non-finite jaw gives the whole plane.
+template <typename T>
+__device__ __forceinline__ void pixel_range(T a, T b, T c, int N, int d, T inv_lat, int* lo, int* hi) {
+  const T fa = a * inv_lat + c - T(0.5), fb = b * inv_lat + c + T(0.5);
+  if (!(fa == fa) || !(fb == fb) || !(fabs(fa) < T(1e8)) || !(fabs(fb) < T(1e8))) {
+    *lo = 0;
+    *hi = N;
+    return;
+  }
+  int l = (int)floor(fa) - 1 - d, u = (int)ceil(fb) + 1 + d;
+  l = max(l, 0);
+  u = min(u, N);
+  *lo = l;
+  *hi = u > l ? u : l;
+}
+
+template <typename T>
+__global__ void k_aperture_box(Geo<T> g, int nb, const T* __restrict__ jaws, int du, int dv, int* __restrict__ box) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const T* jw = jaws + 4 * b;
+  int u0, u1, v0, v1;
+  pixel_range(jw[0], jw[1], g.cu, g.Nu, du, g.inv_lat, &u0, &u1);
+  pixel_range(jw[2], jw[3], g.cv, g.Nv, dv, g.inv_lat, &v0, &v1);
+  box[4 * b] = u0;
+  box[4 * b + 1] = u1;
+  box[4 * b + 2] = v0;
+  box[4 * b + 3] = v1;
+}
+
+template <typename T>
+hipError_t launch_aperture_box(const Geo<T>& g, int nb, const T* jaws, int du, int dv, int* box, hipStream_t s) {
+  hipLaunchKernelGGL(k_aperture_box<T>, dim3((nb + 63) / 64), dim3(64), 0, s, g, nb, jaws, du, dv, box);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ depth
 
 // Central-axis depth (§2.2.4, Eq. 7): one wavefront per control point samples
@@ -478,6 +518,7 @@ hipError_t launch_gather(const Geo<T>& g, int nb, int first, int last, const T* 
   template hipError_t launch_frame<T>(const Geo<T>&, const T*, int, T*, hipStream_t);                        \
   template hipError_t launch_transpose_rho<T>(const Geo<T>&, const T*, T*, hipStream_t);                     \
   template hipError_t launch_raster<T>(const Geo<T>&, int, const T*, const T*, T*, hipStream_t);             \
+  template hipError_t launch_aperture_box<T>(const Geo<T>&, int, const T*, int, int, int*, hipStream_t);     \
   template hipError_t launch_ca_depth<T>(const Geo<T>&, int, const T*, const T*, T*, hipStream_t);           \
   template hipError_t launch_march<T>(const Geo<T>&, int, const T*, const T*, const T*, const T*, const T*, T*, \
                                       hipStream_t);                                                          \

@@ -56,7 +56,7 @@ struct BlurTaps {
 
 // Workspace layout (byte offsets) plus sizes, computed on the host.
 struct Layout {
-  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, fc_tmp, total;
+  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, fc_tmp, box, total;
   int batch;
 };
 
@@ -77,6 +77,13 @@ hipError_t launch_march(const Geo<T>& g, int nb, const T* frame, const T* rho_t,
 template <typename T>
 hipError_t launch_march_adj(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* z, const T* dd,
                             const T* H, T* A, hipStream_t s);
+// Support of a lateral convolution: box[b] = {u0, u1, v0, v1} (int4 per control
+// point) bounds the aperture; CONV_IN_BOX: inputs outside it are zero; CONV_OUT_BOX:
+// only outputs inside it are needed (the rest are written as 0).
+enum { CONV_DENSE = 0, CONV_IN_BOX = 1, CONV_OUT_BOX = 2 };
+template <typename T>
+hipError_t launch_aperture_box(const Geo<T>& g, int nb, const T* jaws, int du, int dv, int* box, hipStream_t s);
+
 // Plan-level geometry cache: G = (SAD/d)^2 DD(W) per beam-frame node (E = float or
 // __bf16), P = F G, and A = sum_k H_k G_k.
 template <typename E>
@@ -94,7 +101,7 @@ bool conv_small_supported(const Geo<float>& g);
 hipError_t launch_conv_small(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                              hipStream_t s);
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
-                                hipStream_t s);
+                                hipStream_t s, const int* box = nullptr, int support = 0);
 hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                  hipStream_t s);
 template <typename T>

@@ -62,7 +62,8 @@ def set_fluence_corrections(s: "Spec", m) -> None:
 
 class WsLayout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_size_t) for n in
-                ("frame", "rho_t", "fluence", "depth", "vol0", "vol1", "adj", "comp", "fc_tmp", "total")] + \
+                ("frame", "rho_t", "fluence", "depth", "vol0", "vol1", "adj", "comp", "fc_tmp", "box",
+                 "total")] + \
                [("batch", ctypes.c_int32)]
 
 

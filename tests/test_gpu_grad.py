@@ -58,6 +58,47 @@ def test_tiny_gradient_parity(seed, n_taps):
     _check("mu", gm, rm)
 
 
+def _aperture_case(fcorr=False, large=False):
+    """Off-centre, asymmetric, closed and out-of-field jaws: the convolutions restrict
+    themselves to each control point's jaw rectangle, so its edges must be exact.
+    large: a 115 x 115 beam-frame plane (several convolution regions)."""
+    if large:
+        c = inputs.tiny_case(seed=37, n_cp=5, n_taps=15, shape=(10, 12, 11), spacing=3.0, field=150.0, n_leaf=30,
+                             leaf_width=10.0)
+        f = 150.0 / 40.0
+    else:
+        c = inputs.tiny_case(seed=36, n_cp=5, n_taps=15, shape=(9, 8, 10), spacing=6.0, field=40.0)
+        f = 1.0
+    c.jaws = f * np.array([[-30.0, 10.0, 5.0, 35.0],
+                           [-40.0, 40.0, -40.0, 40.0],
+                           [3.0, 3.0, -10.0, 10.0],        # closed in x
+                           [20.0, 38.5, -38.0, -21.5],
+                           [-55.0, -12.0, -60.0, 52.0]])   # beyond the field limit
+    if fcorr:
+        c.machine = inputs.with_fluence_corrections(c.machine)
+    return c
+
+
+@pytest.mark.parametrize("fcorr,large", [(False, False), (True, False), (False, True)],
+                         ids=["plain", "fluence-corrections", "large-plane"])
+def test_aperture_rectangles_forward_and_gradient(fcorr, large):
+    from tests.test_gpu_parity import gpu_dose, oracle_dose, _rel_err
+    _say("asymmetric / closed / out-of-field jaws, n=15%s%s"
+         % (" with fluence corrections" if fcorr else "", ", 115 x 115 plane" if large else ""))
+    c = _aperture_case(fcorr, large)
+    ref, _, _ = oracle_dose(c)
+    got, _ = gpu_dose(c)
+    err = _rel_err(got, ref)
+    _say("forward max|dD|/maxD = %.3e" % err)
+    assert err <= 1e-5
+    w = np.random.default_rng(36).uniform(size=c.shape)
+    gl, gj, gm, _ = _grads_gpu(c, w)
+    rl, rj, rm = _grads_oracle(c, w)
+    _check("leaves", gl, rl)
+    _check("jaws", gj, rj)
+    _check("mu", gm, rm)
+
+
 def test_c1_gradient_parity():
     _say("C1 gradients, 90 CPs, L = sum w D")
     c = inputs.config_c1()
