@@ -273,7 +273,7 @@ hipError_t run_conv<double>(const Geo<double>& g, int, int nb, const double* z, 
 template <>
 hipError_t run_conv<float>(const Geo<float>& g, int conv_mode, int nb, const float* z, const float* in, float* out,
                            hipStream_t s, const int* box, int support) {
-  if (conv_mode == PDRT_CONV_BF16) return launch_conv_mfma_bf16(g, nb, z, in, out, s);
+  if (conv_mode == PDRT_CONV_BF16) return launch_conv_mfma_bf16(g, nb, z, in, out, s, box, support);
   if (g.n_taps >= kMfmaMinTaps) return launch_conv_mfma_f32(g, nb, z, in, out, s, box, support);
   if (conv_small_supported(g)) return launch_conv_small(g, nb, z, in, out, s);
   return launch_conv_direct<float>(g, nb, z, in, out, s);

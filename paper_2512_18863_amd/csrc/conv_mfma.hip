@@ -267,45 +267,7 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     }
     float* dst = out + (size_t)bk * plane;
 
-    if (SUP == CONV_OUT_BOX) {
-      // tiles of the region that meet the box: ti in [ta, tb], tj in [sa, sb]
-      const int4 bx = box[bk / g.Nk];
-      const int ta = max(0, floor_div16(bx.x - I0)), tb = min(rs.TI - 1, floor_div16(bx.y - 1 - I0));
-      const int sa = max(0, floor_div16(bx.z - J0)), sb = min(rs.TJ - 1, floor_div16(bx.w - 1 - J0));
-      const int nI = bx.y > bx.x && tb >= ta ? tb - ta + 1 : 0;
-      const int nJ = bx.w > bx.z && sb >= sa ? sb - sa + 1 : 0;
-      const int nneed = nI * nJ;
-      // outputs of the wavefront's fixed tiles that lie outside the box rectangle are 0
-      const f32x4 zero4 = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        const bool needed = tI[q] >= ta && tI[q] < ta + nI && tJ[q] >= sa && tJ[q] < sa + nJ;
-        if (active[q] && !needed) store_tile_at(g, I0 + MT * tI[q], J0 + MT * tJ[q], lane, zero4, dst);
-      }
-      // the needed tiles, n = wave, wave + NW, ...
-      int nact = 0;
-      const float* ab[TPW];
-      int oI[TPW], oJ[TPW];
-#pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        const int n = wave + NW * q;
-        const bool use = n < nneed;
-        const int ti = use ? ta + n / nJ : 0, tj = use ? sa + n % max(nJ, 1) : 0;
-        ab[q] = a_of(ti, tj);
-        oI[q] = I0 + MT * ti;
-        oJ[q] = J0 + MT * tj;
-        nact += use ? 1 : 0;
-      }
-      f32x4 acc[TPW];
-#pragma unroll
-      for (int q = 0; q < TPW; ++q) acc[q] = zero4;
-      if (nact == 1) f32_steps<1>(ab, bbase, pitch, E, 0, h, 0, SS - 1, acc);
-      if (TPW >= 2 && nact == 2) f32_steps<TPW >= 2 ? 2 : 1>(ab, bbase, pitch, E, 0, h, 0, SS - 1, acc);
-      if (TPW >= 3 && nact == 3) f32_steps<TPW >= 3 ? 3 : 1>(ab, bbase, pitch, E, 0, h, 0, SS - 1, acc);
-#pragma unroll
-      for (int q = 0; q < TPW; ++q)
-        if (q < nact && oI[q] < g.Nu && oJ[q] < g.Nv) store_tile_at(g, oI[q], oJ[q], lane, acc[q], dst);
-    } else {
+    {
       int pa = 0, pb = h, ua = 0, ub = SS - 1;
       if (SUP == CONV_IN_BOX) {
         // hull over the wavefront's tiles of the tap rows and super-steps that reach the input rectangle
@@ -354,6 +316,126 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     prev = cur;
     cur = nxt;
     __syncthreads();  // the LDS image and taps are rewritten for the next item
+  }
+}
+
+// The adjoint direction (CONV_OUT_BOX): only the outputs inside the box are
+// needed.  Per item the box (clipped to the region) is covered by nI x nJ output
+// tiles placed at the box corner (columns rounded down to a multiple of 4, so the
+// 16-byte LDS reads stay aligned) instead of on the region's tile grid, and the
+// work is split over the wavefronts by tile and by a range of tap rows: with nT
+// tiles each tile's rows p = 0..h are cut into C = NW / nT chunks, whose partial
+// sums are added in LDS in chunk order.  Every output of the region outside the
+// covered rectangle is written as 0.
+template <int NW, int TPW>
+__global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32_adj(Geo<float> g, RegionShape rs, F32Shape fs,
+                                                               int n_items, const int4* __restrict__ box,
+                                                               const float* __restrict__ zca,
+                                                               const float* __restrict__ in,
+                                                               float* __restrict__ out) {
+  extern __shared__ __align__(16) float lds[];
+  constexpr int NT = 64 * NW;
+  const int h = g.h;
+  const int rows = fs.rows, pitch = fs.pitch, E = fs.E, SS = fs.SS;
+  float* tile = lds;
+  float* kx = lds + rows * pitch;
+  float* kq = kx + (h + 1) * E;
+  float* part = kq + (h + 1) * (h + 1);  // (NW - 1) x 256 partial sums, 16-byte aligned (see f32_adj_lds)
+  part = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(part) + 15) & ~(uintptr_t)15);
+  const int nreg = rs.regions_i * rs.regions_j;
+  const int region = blockIdx.x % nreg;
+  const int I0 = (region / rs.regions_j) * rs.TI * MT;
+  const int J0 = (region % rs.regions_j) * rs.TJ * MT;
+  const int Ie = min(g.Nu, I0 + MT * rs.TI), Je = min(g.Nv, J0 + MT * rs.TJ);  // region's outputs in the plane
+  const size_t plane = (size_t)g.Nu * g.Nv;
+  const int tid = threadIdx.x;
+  const DataRect dr = data_rect(g, I0, J0, MT * rs.TI, MT * rs.TJ);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int m = lane & 15, kk = lane >> 4;
+  const float* bbase = kx + 4 * kk + 15 - m;
+  const int off = h + 15;
+
+  zero_lds(tile, rows * pitch, tid, NT);
+  float buf[PF];
+  int it = blockIdx.x;
+  if (it < n_items) fetch_rect<PF>(in + (size_t)(it / nreg) * plane, g.Nv, dr, tid, NT, buf);
+  __syncthreads();
+  for (; it < n_items; it += gridDim.x) {
+    const int bk = it / nreg;
+    const int k = bk % g.Nk;
+    const float* src = in + (size_t)bk * plane;
+    put_rect<PF>(src, g.Nv, dr, pitch, tid, NT, buf, tile);
+    unique_taps(g, k, zca[bk], kq, tid, NT);
+    __syncthreads();
+    for (int idx = tid; idx < (h + 1) * E; idx += NT) {
+      int p = idx / E, c = idx - p * E;
+      int q = c - off;
+      float v = 0.f;
+      if (q >= -h && q <= h) v = kq[p * (h + 1) + (q < 0 ? -q : q)] * (p == 0 ? 0.5f : 1.f);
+      kx[idx] = v;
+    }
+    __syncthreads();
+    const int nx = it + gridDim.x;
+    if (nx < n_items) fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, dr, tid, NT, buf);
+    float* dst = out + (size_t)bk * plane;
+
+    // the covered rectangle [Iw, Iw + 16 nI) x [Jw, Jw + 16 nJ)
+    const int4 bx = box[bk / g.Nk];
+    const int u0 = max(bx.x, I0), u1 = min(bx.y, Ie), v0 = max(bx.z, J0), v1 = min(bx.w, Je);
+    int nI = 0, nJ = 0, Iw = I0, Jw = J0;
+    if (u1 > u0 && v1 > v0) {
+      nI = (u1 - u0 + MT - 1) / MT;
+      Iw = min(u0, I0 + MT * rs.TI - MT * nI);
+      const int ja = v0 - ((v0 - J0) & 3);
+      nJ = (v1 - ja + MT - 1) / MT;
+      Jw = min(ja, J0 + MT * rs.TJ - MT * nJ);
+    }
+    const int nT = nI * nJ;
+    const int C = nT > 0 && nT < NW ? NW / nT : 1;  // tap-row chunks per tile
+    const int chunk = wave % C, slot = wave / C, slots = NW / C;
+    const int h1 = h + 1, pa = (h1 * chunk) / C, pb = (h1 * (chunk + 1)) / C - 1;
+    int nact = 0;
+    const float* ab[TPW];
+    int oI[TPW], oJ[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = slot + slots * q;
+      const bool use = t < nT;
+      const int ti = use ? t / nJ : 0, tj = use ? t - (t / nJ) * nJ : 0;
+      oI[q] = Iw + MT * ti;
+      oJ[q] = Jw + MT * tj;
+      ab[q] = tile + (oI[q] - I0 + m + h) * pitch + (oJ[q] - J0) + 4 * kk;
+      nact += use ? 1 : 0;
+    }
+    f32x4 acc[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (nact == 1) f32_steps<1>(ab, bbase, pitch, E, pa, pb, 0, SS - 1, acc);
+    if (TPW >= 2 && nact == 2) f32_steps<TPW >= 2 ? 2 : 1>(ab, bbase, pitch, E, pa, pb, 0, SS - 1, acc);
+    if (TPW >= 3 && nact == 3) f32_steps<TPW >= 3 ? 3 : 1>(ab, bbase, pitch, E, pa, pb, 0, SS - 1, acc);
+    if (C > 1) {
+      // (C > 1 only with one tile per wavefront) chunks 1 .. C-1 park their sums, chunk 0 adds them in order
+      __syncthreads();
+      if (chunk > 0 && nact > 0)
+        *reinterpret_cast<f32x4*>(part + ((slot * (C - 1) + chunk - 1) * 64 + lane) * 4) = acc[0];
+      __syncthreads();
+      if (chunk == 0 && nact > 0) {
+        for (int c = 1; c < C; ++c) acc[0] += *reinterpret_cast<const f32x4*>(part + ((slot * (C - 1) + c - 1) * 64 + lane) * 4);
+        store_tile_at(g, oI[0], oJ[0], lane, acc[0], dst);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < TPW; ++q)
+        if (q < nact) store_tile_at(g, oI[q], oJ[q], lane, acc[q], dst);
+    }
+    // every other output of the region is 0
+    const int rw = Je - J0, cnt = (Ie - I0) * rw;
+    const int cI1 = Iw + MT * nI, cJ1 = Jw + MT * nJ;
+    for (int idx = tid; idx < cnt; idx += NT) {
+      const int r = I0 + idx / rw, c = J0 + idx % rw;
+      if (!(r >= Iw && r < cI1 && c >= Jw && c < cJ1)) dst[(size_t)r * g.Nv + c] = 0.f;
+    }
+    __syncthreads();
   }
 }
 
@@ -413,8 +495,13 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // Items as in the FP32 kernel.  LDS: the region's BF16 input image (zero halo
 // written once), then the tap copies, which the quarters' partial sums reuse
 // after the matrix loop (one quarter at a time, added in a fixed order).
-template <int RJ, int SMAX>
+// With a support box (see the FP32 kernel): CONV_IN_BOX stages only the box and
+// each strip splits just the tap rows that reach it over its four wavefronts,
+// skipping the A fragments outside the box's columns; CONV_OUT_BOX skips the
+// strips and tiles that do not meet the box (their outputs are stored as 0).
+template <int RJ, int SMAX, int SUP>
 __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Shape bs, int n_items,
+                                                            const int4* __restrict__ box,
                                                             const float* __restrict__ zca,
                                                             const float* __restrict__ in, float* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -442,22 +529,57 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
   // entries x0 + e, x0 = 16 s + 8 hi + 31 - m, residue r = (31 - m) % 8.
   const int rr = (31 - m) & 7;
   const __bf16* bbase = bcopy + rr * CL + 8 * hi + 31 - m + ((8 - rr) & 7);
-  const int n_p = 2 * h + 1, per = (n_p + BQ - 1) / BQ;
-  const int p_begin = -h + quarter * per, p_end = min(h + 1, p_begin + per);
   constexpr int NA = 2 * RJ + SMAX - 2;
   const int na = 2 * RJ + S - 2;
   float* my_part = part + (size_t)strip * RJ * 1024;
+  const int I = I0 + 32 * strip;  // first output row of this wavefront's strip
+  auto rect_of = [&](int item) {
+    if (SUP == CONV_IN_BOX) return clip_rect(dr, box[(item / nreg) / g.Nk]);
+    return dr;
+  };
 
   zero_lds(tile, rows * pitch, tid, NT);
   float buf[PF];
   int it = blockIdx.x;
-  if (it < n_items) fetch_rect<PF>(in + (size_t)(it / nreg) * plane, g.Nv, dr, tid, NT, buf);
+  DataRect cur = rect_of(it < n_items ? it : 0);
+  DataRect prev = cur;
+  prev.nr = 0;
+  prev.nc = 1;
+  if (it < n_items) fetch_rect<PF>(in + (size_t)(it / nreg) * plane, g.Nv, cur, tid, NT, buf);
   __syncthreads();
   for (; it < n_items; it += gridDim.x) {
     const int bk = it / nreg;
     const int k = bk % g.Nk;
     const float* src = in + (size_t)bk * plane;
-    put_rect<PF>(src, g.Nv, dr, pitch, tid, NT, buf, tile);
+    put_rect<PF>(src, g.Nv, cur, pitch, tid, NT, buf, tile);
+    if (SUP == CONV_IN_BOX) {
+      for (int idx = tid; idx < prev.nr * prev.nc; idx += NT) {
+        const int r = idx / prev.nc, c = idx - r * prev.nc;
+        const int lr = prev.lr0 + r, lc = prev.lc0 + c;
+        const bool in_cur = lr >= cur.lr0 && lr < cur.lr0 + cur.nr && lc >= cur.lc0 && lc < cur.lc0 + cur.nc;
+        if (!in_cur) tile[lr * pitch + lc] = (__bf16)0.f;
+      }
+    }
+    // this wavefront's tap rows [p_begin, p_end), A fragments [a_lo, a_hi], tiles [t_lo, t_hi]
+    int p_lo = -h, p_hi = h, a_lo = 0, a_hi = na - 1, t_lo = 0, t_hi = RJ - 1;
+    if (SUP == CONV_IN_BOX) {
+      const int r0 = cur.r0, r1 = cur.r0 + cur.nr;
+      p_lo = max(-h, r0 - I - 31);
+      p_hi = min(h, r1 - I - 1);
+      if (cur.nr == 0) p_hi = p_lo - 1;
+      a_lo = max(0, floor_div16(cur.c0 - (J0 - h)));
+      a_hi = min(na - 1, floor_div16(cur.c0 + cur.nc - 1 - (J0 - h)));
+    } else if (SUP == CONV_OUT_BOX) {
+      const int4 bx = box[bk / g.Nk];
+      if (bx.y <= I || bx.x >= I + 32 || bx.y <= bx.x || bx.w <= bx.z) p_hi = p_lo - 1;  // strip not needed
+      t_lo = max(0, (bx.z - J0) >= 0 ? (bx.z - J0) / 32 : -((31 - (bx.z - J0)) / 32));
+      t_hi = min(RJ - 1, (bx.w - 1 - J0) >= 0 ? (bx.w - 1 - J0) / 32 : -1);
+      if (t_hi < t_lo) p_hi = p_lo - 1;
+      a_lo = 2 * t_lo;
+      a_hi = min(na - 1, 2 * t_hi + S - 1);
+    }
+    const int n_need = p_hi >= p_lo ? p_hi - p_lo + 1 : 0, per = (n_need + BQ - 1) / BQ;
+    const int p_begin = p_lo + quarter * per, p_end = min(p_lo + n_need, p_begin + per);
     unique_taps(g, k, zca[bk], kq, tid, NT);
     __syncthreads();
     // Extended tap row x (x = q + h + 31) stored in copy r at position x + sigma_r,
@@ -481,7 +603,11 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
     }
     __syncthreads();
     const int nx = it + gridDim.x;
-    if (nx < n_items) fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, dr, tid, NT, buf);
+    DataRect nxt = cur;
+    if (nx < n_items) {
+      nxt = rect_of(nx);
+      fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, nxt, tid, NT, buf);
+    }
 
     f32x16 acc[RJ];
 #pragma unroll
@@ -499,12 +625,12 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
       // walk the A fragments: fragment a feeds tile t at K-step a - 2 t
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
-        if (a < na) {
+        if (a < na && a >= a_lo && a <= a_hi) {
           const bf16x8 Af = *reinterpret_cast<const bf16x8*>(arow + 16 * a);
 #pragma unroll
           for (int t = 0; t < RJ; ++t) {
             const int s2 = a - 2 * t;
-            if (s2 >= 0 && s2 < SMAX && s2 < S)
+            if (s2 >= 0 && s2 < SMAX && s2 < S && t >= t_lo && t <= t_hi)
               acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Af, Bf[s2], acc[t], 0, 0, 0);
           }
         }
@@ -546,6 +672,8 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
         }
       }
     }
+    prev = cur;
+    cur = nxt;
     __syncthreads();  // the partial sums alias the next item's taps
   }
 }
@@ -585,27 +713,63 @@ static hipError_t launch_f32_sup(const Geo<float>& g, const RegionShape& rs, con
   return launch_f32_cfg<12, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
 }
 
+// LDS of the adjoint kernel: the FP32 image and taps plus NW x 256 partial sums
+// (16-byte aligned).
+static size_t f32_adj_lds(int h, const F32Shape& fs, int nw) { return f32_lds(h, fs) + 16 + sizeof(float) * 256 * nw; }
+
+template <int NW, int TPW>
+static hipError_t launch_f32_adj_cfg(const Geo<float>& g, const RegionShape& rs, const F32Shape& fs, int nb,
+                                     const int4* box, const float* z, const float* in, float* out, hipStream_t s) {
+  const void* kern = (const void*)k_conv_mfma_f32_adj<NW, TPW>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const size_t lds = f32_adj_lds(g.h, fs, NW);
+  if (lds > LDS_MAX) return hipErrorInvalidConfiguration;
+  const int nreg = rs.regions_i * rs.regions_j;
+  const long n_items = (long)nreg * g.Nk * nb;
+  if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;
+  const int grid = persistent_grid(kern, 64 * NW, lds, nreg, n_items);
+  hipLaunchKernelGGL((k_conv_mfma_f32_adj<NW, TPW>), dim3(grid), dim3(64 * NW), lds, s, g, rs, fs, (int)n_items,
+                     box, z, in, out);
+  return hipGetLastError();
+}
+
+static hipError_t launch_f32_adj(const Geo<float>& g, const RegionShape& rs, const F32Shape& fs, int nb,
+                                 const int4* box, const float* z, const float* in, float* out, hipStream_t s) {
+  const int tiles = rs.TI * rs.TJ;
+  if (tiles <= 4) return launch_f32_adj_cfg<4, 1>(g, rs, fs, nb, box, z, in, out, s);
+  if (tiles <= 8) return launch_f32_adj_cfg<8, 1>(g, rs, fs, nb, box, z, in, out, s);
+  if (tiles <= 16) return launch_f32_adj_cfg<8, 2>(g, rs, fs, nb, box, z, in, out, s);
+  if (tiles <= 24) return launch_f32_adj_cfg<8, 3>(g, rs, fs, nb, box, z, in, out, s);
+  return launch_f32_adj_cfg<12, 3>(g, rs, fs, nb, box, z, in, out, s);
+}
+
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                 hipStream_t s, const int* box, int support) {
+  const int4* bx = reinterpret_cast<const int4*>(box);
+  const bool adj = bx && support == CONV_OUT_BOX;
   RegionShape rs;
   F32Shape fs;
   size_t lds = 0;
   for (int rmax = RMAX; rmax >= 1; --rmax) {  // the largest region whose LDS image fits
     rs = region_shape(g.Nu, g.Nv, rmax);
     fs = f32_shape(g.h, rs);
-    lds = f32_lds(g.h, fs);
+    lds = adj ? f32_adj_lds(g.h, fs, 12) : f32_lds(g.h, fs);
     if (lds <= LDS_MAX) break;
   }
-  const int4* bx = reinterpret_cast<const int4*>(box);
+  if (adj) return launch_f32_adj(g, rs, fs, nb, bx, z, in, out, s);
   if (!bx || support == CONV_DENSE) return launch_f32_sup<CONV_DENSE>(g, rs, fs, lds, nb, bx, z, in, out, s);
-  if (support == CONV_IN_BOX) return launch_f32_sup<CONV_IN_BOX>(g, rs, fs, lds, nb, bx, z, in, out, s);
-  return launch_f32_sup<CONV_OUT_BOX>(g, rs, fs, lds, nb, bx, z, in, out, s);
+  return launch_f32_sup<CONV_IN_BOX>(g, rs, fs, lds, nb, bx, z, in, out, s);
 }
 
-template <int RJ, int SMAX>
-static hipError_t launch_bf16_cfg(const Geo<float>& g, const BF16Shape& bs, size_t lds, int nb, const float* z,
-                                  const float* in, float* out, hipStream_t s) {
-  const void* kern = (const void*)k_conv_mfma_bf16<RJ, SMAX>;
+template <int RJ, int SMAX, int SUP>
+static hipError_t launch_bf16_cfg(const Geo<float>& g, const BF16Shape& bs, size_t lds, int nb, const int4* box,
+                                  const float* z, const float* in, float* out, hipStream_t s) {
+  const void* kern = (const void*)k_conv_mfma_bf16<RJ, SMAX, SUP>;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
@@ -618,22 +782,30 @@ static hipError_t launch_bf16_cfg(const Geo<float>& g, const BF16Shape& bs, size
   if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;
   const int threads = 64 * BQ * bs.RI;
   const int grid = persistent_grid(kern, threads, lds, nreg, n_items);
-  hipLaunchKernelGGL((k_conv_mfma_bf16<RJ, SMAX>), dim3(grid), dim3(threads), lds, s, g, bs, (int)n_items, z, in,
-                     out);
+  hipLaunchKernelGGL((k_conv_mfma_bf16<RJ, SMAX, SUP>), dim3(grid), dim3(threads), lds, s, g, bs, (int)n_items, box,
+                     z, in, out);
   return hipGetLastError();
 }
 
-template <int RJ>
-static hipError_t launch_bf16_rj(const Geo<float>& g, const BF16Shape& bs, size_t lds, int nb, const float* z,
-                                 const float* in, float* out, hipStream_t s) {
-  if (bs.S <= 4) return launch_bf16_cfg<RJ, 4>(g, bs, lds, nb, z, in, out, s);
-  if (bs.S <= 6) return launch_bf16_cfg<RJ, 6>(g, bs, lds, nb, z, in, out, s);
-  if (bs.S <= 8) return launch_bf16_cfg<RJ, 8>(g, bs, lds, nb, z, in, out, s);
-  return launch_bf16_cfg<RJ, 10>(g, bs, lds, nb, z, in, out, s);
+template <int RJ, int SUP>
+static hipError_t launch_bf16_rj(const Geo<float>& g, const BF16Shape& bs, size_t lds, int nb, const int4* box,
+                                 const float* z, const float* in, float* out, hipStream_t s) {
+  if (bs.S <= 4) return launch_bf16_cfg<RJ, 4, SUP>(g, bs, lds, nb, box, z, in, out, s);
+  if (bs.S <= 6) return launch_bf16_cfg<RJ, 6, SUP>(g, bs, lds, nb, box, z, in, out, s);
+  if (bs.S <= 8) return launch_bf16_cfg<RJ, 8, SUP>(g, bs, lds, nb, box, z, in, out, s);
+  return launch_bf16_cfg<RJ, 10, SUP>(g, bs, lds, nb, box, z, in, out, s);
+}
+
+template <int SUP>
+static hipError_t launch_bf16_sup(const Geo<float>& g, const BF16Shape& bs, size_t lds, int nb, const int4* box,
+                                  const float* z, const float* in, float* out, hipStream_t s) {
+  if (bs.RJ == 1) return launch_bf16_rj<1, SUP>(g, bs, lds, nb, box, z, in, out, s);
+  if (bs.RJ == 2) return launch_bf16_rj<2, SUP>(g, bs, lds, nb, box, z, in, out, s);
+  return launch_bf16_cfg<3, 6, SUP>(g, bs, lds, nb, box, z, in, out, s);
 }
 
 hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
-                                 hipStream_t s) {
+                                 hipStream_t s, const int* box, int support) {
   BF16Shape bs;
   size_t lds = 0;
   for (int rmax = 3; rmax >= 1; --rmax) {  // strips per region, while the LDS image fits
@@ -642,9 +814,10 @@ hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, co
     if (lds <= LDS_MAX) break;
   }
   if (bs.S > 10) return hipErrorInvalidConfiguration;
-  if (bs.RJ == 1) return launch_bf16_rj<1>(g, bs, lds, nb, z, in, out, s);
-  if (bs.RJ == 2) return launch_bf16_rj<2>(g, bs, lds, nb, z, in, out, s);
-  return launch_bf16_cfg<3, 6>(g, bs, lds, nb, z, in, out, s);
+  const int4* bx = reinterpret_cast<const int4*>(box);
+  if (!bx || support == CONV_DENSE) return launch_bf16_sup<CONV_DENSE>(g, bs, lds, nb, bx, z, in, out, s);
+  if (support == CONV_IN_BOX) return launch_bf16_sup<CONV_IN_BOX>(g, bs, lds, nb, bx, z, in, out, s);
+  return launch_bf16_sup<CONV_OUT_BOX>(g, bs, lds, nb, bx, z, in, out, s);
 }
 
 }  // namespace pdrt

@@ -103,7 +103,7 @@ hipError_t launch_conv_small(const Geo<float>& g, int nb, const float* z, const 
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                 hipStream_t s, const int* box = nullptr, int support = 0);
 hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
-                                 hipStream_t s);
+                                 hipStream_t s, const int* box = nullptr, int support = 0);
 template <typename T>
 hipError_t launch_gather(const Geo<T>& g, int nb, int first, int last, const T* frame, const T* mu,
                          const T* Dfan, T* dose, T* comp, hipStream_t s);

@@ -55,3 +55,29 @@ def test_bf16_gradients_close_to_fp32():
         e = np.abs(a - b).max() / np.abs(a).max()
         _say("%s: bf16 vs fp32 max|dg|/max|g| = %.3e" % (name, e))
         assert e <= 2.0 ** -7
+
+
+@pytest.mark.parametrize("large", [False, True], ids=["small-plane", "large-plane"])
+def test_bf16_aperture_rectangles(large):
+    """Asymmetric, closed and out-of-field jaws: the BF16 convolution restricted to
+    each control point's jaw rectangle, forward against the oracle and gradients
+    against the (oracle-checked) FP32 adjoint."""
+    from paper_2512_18863_amd.engine import DoseEngine
+    from tests.test_gpu_grad import _aperture_case
+    from tests.test_gpu_parity import _t
+    _say("bf16 with asymmetric / closed / out-of-field jaws%s" % (", 115 x 115 plane" if large else ""))
+    c = _aperture_case(False, large)
+    ref, _, _ = oracle_dose(c)
+    got, _ = gpu_dose(c, conv="bf16")
+    err = float(np.abs(got - ref).max() / ref.max())
+    _say("forward max|dD|/maxD = %.3e" % err)
+    assert err <= 2.0 ** -8
+    w = _t(np.random.default_rng(36).uniform(size=c.shape))
+    out = {}
+    for conv in ("fp32", "bf16"):
+        eng = DoseEngine(c, conv=conv)
+        out[conv] = [t.cpu().numpy() for t in eng.backward(_t(c.leaves), _t(c.jaws), _t(c.mu), w)]
+    for name, a, b in zip(("leaves", "jaws", "mu"), out["fp32"], out["bf16"]):
+        e = np.abs(a - b).max() / np.abs(a).max()
+        _say("%s: bf16 vs fp32 max|dg|/max|g| = %.3e" % (name, e))
+        assert e <= 2.0 ** -7
