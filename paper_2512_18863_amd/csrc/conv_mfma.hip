@@ -91,7 +91,8 @@ static F32Shape f32_shape(int h, const RegionShape& r) {
 }
 
 static size_t f32_lds(int h, const F32Shape& fs) {
-  return sizeof(float) * ((size_t)fs.rows * fs.pitch + (size_t)(h + 1) * fs.E + (size_t)(h + 1) * (h + 1));
+  // image, extended taps, unique taps, and one counter
+  return sizeof(float) * ((size_t)fs.rows * fs.pitch + (size_t)(h + 1) * fs.E + (size_t)(h + 1) * (h + 1)) + 16;
 }
 
 constexpr int PF = 12;  // prefetched elements per thread
@@ -196,6 +197,7 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
   float* tile = lds;
   float* kx = lds + rows * pitch;  // (h + 1) x E, zero outside |q| <= h, row 0 halved
   float* kq = kx + (h + 1) * E;    // (h + 1) x (h + 1) unique taps
+  int* grab = reinterpret_cast<int*>(kq + (h + 1) * (h + 1));  // next tile to take (CONV_IN_BOX)
   const int nreg = rs.regions_i * rs.regions_j;
   const int region = blockIdx.x % nreg;
   const int I0 = (region / rs.regions_j) * rs.TI * MT;
@@ -240,6 +242,7 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     const float* src = in + (size_t)bk * plane;
     put_rect<PF>(src, g.Nv, cur, pitch, tid, NT, buf, tile);
     if (SUP == CONV_IN_BOX) {
+      if (tid == 0) *grab = 0;
       // clear what the previous item wrote outside this item's rectangle
       for (int idx = tid; idx < prev.nr * prev.nc; idx += NT) {
         const int r = idx / prev.nc, c = idx - r * prev.nc;
@@ -267,48 +270,49 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     }
     float* dst = out + (size_t)bk * plane;
 
-    {
-      int pa = 0, pb = h, ua = 0, ub = SS - 1;
-      if (SUP == CONV_IN_BOX) {
-        // hull over the wavefront's tiles of the tap rows and super-steps that reach the input rectangle
-        pa = h + 1;
-        pb = -1;
-        ua = SS;
-        ub = -1;
-        const int r0 = cur.r0, r1 = cur.r0 + cur.nr, c0 = cur.c0, c1 = cur.c0 + cur.nc;
-        if (cur.nr > 0) {
-#pragma unroll
-          for (int q = 0; q < TPW; ++q) {
-            if (!active[q]) continue;
-            const int I = I0 + MT * tI[q], cb = J0 + MT * tJ[q] - h;
-            const int u_lo = max(0, floor_div16(c0 - cb)), u_hi = min(SS - 1, floor_div16(c1 - 1 - cb));
-            // rows I + p .. I + p + 15 or I - p .. I - p + 15 meet [r0, r1)
-            int p_lo = h + 1, p_hi = -1;
-            const int a1 = max(0, r0 - I - 15), b1 = min(h, r1 - I - 1);
-            if (a1 <= b1) {
-              p_lo = min(p_lo, a1);
-              p_hi = max(p_hi, b1);
-            }
-            const int a2 = max(0, I - r1 + 1), b2 = min(h, I + 15 - r0);
-            if (a2 <= b2) {
-              p_lo = min(p_lo, a2);
-              p_hi = max(p_hi, b2);
-            }
-            if (u_lo > u_hi || p_lo > p_hi) continue;
-            pa = min(pa, p_lo);
-            pb = max(pb, p_hi);
-            ua = min(ua, u_lo);
-            ub = max(ub, u_hi);
-          }
+    if (SUP == CONV_IN_BOX) {
+      // Tiles are taken one at a time from a shared counter (row-major order), each
+      // with only the tap rows and super-steps that reach the input rectangle, so
+      // wavefronts whose tiles need little work take more tiles.  Every tile is
+      // computed by one wavefront in a fixed step order.
+      const int r0 = cur.r0, r1 = cur.r0 + cur.nr, c0 = cur.c0, c1 = cur.c0 + cur.nc;
+      const int n_tiles = rs.TI * rs.TJ;
+      while (true) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(grab, 1);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= n_tiles) break;
+        const int ti = t / rs.TJ, tj = t - (t / rs.TJ) * rs.TJ;
+        const int I = I0 + MT * ti, J = J0 + MT * tj;
+        if (I >= g.Nu || J >= g.Nv) continue;
+        const int cb = J - h;
+        const int ua = max(0, floor_div16(c0 - cb)), ub = min(SS - 1, floor_div16(c1 - 1 - cb));
+        // rows I + p .. I + p + 15 or I - p .. I - p + 15 meet [r0, r1)
+        int pa = h + 1, pb = -1;
+        const int a1 = max(0, r0 - I - 15), b1 = min(h, r1 - I - 1);
+        if (a1 <= b1) {
+          pa = min(pa, a1);
+          pb = max(pb, b1);
         }
+        const int a2 = max(0, I - r1 + 1), b2 = min(h, I + 15 - r0);
+        if (a2 <= b2) {
+          pa = min(pa, a2);
+          pb = max(pb, b2);
+        }
+        if (cur.nr == 0) pb = pa - 1;
+        const float* ab[1] = {a_of(ti, tj)};
+        f32x4 acc[1] = {f32x4{0.f, 0.f, 0.f, 0.f}};
+        f32_steps<1>(ab, bbase, pitch, E, pa, pb, ua, ub, acc);
+        store_tile_at(g, I, J, lane, acc[0], dst);
       }
+    } else {
       const float* ab[TPW];
 #pragma unroll
       for (int q = 0; q < TPW; ++q) ab[q] = a_of(tI[q], tJ[q]);
       f32x4 acc[TPW];
 #pragma unroll
       for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-      f32_steps<TPW>(ab, bbase, pitch, E, pa, pb, ua, ub, acc);
+      f32_steps<TPW>(ab, bbase, pitch, E, 0, h, 0, SS - 1, acc);
 #pragma unroll
       for (int q = 0; q < TPW; ++q)
         if (active[q]) store_tile_at(g, I0 + MT * tI[q], J0 + MT * tJ[q], lane, acc[q], dst);
