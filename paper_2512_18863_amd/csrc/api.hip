@@ -287,6 +287,13 @@ const char* conv_name<double>(const Geo<double>&, int) {
   return "conv_direct_f64";
 }
 
+// The matrix-core convolutions honour the aperture box (inputs read, outputs
+// written only inside it); the vector-ALU ones are dense.
+template <typename T>
+bool conv_uses_box(const Geo<T>& g, int conv_mode) {
+  return sizeof(T) == 4 && (conv_mode == PDRT_CONV_BF16 || g.n_taps >= kMfmaMinTaps);
+}
+
 template <>
 const char* conv_name<float>(const Geo<float>& g, int conv_mode) {
   if (conv_mode == PDRT_CONV_BF16) return "conv_mfma_bf16";
@@ -324,16 +331,16 @@ int cache_view(const Problem& P, const pdrt_beam* beam, int type, const void* ca
 
 template <typename E>
 hipError_t apply_geometry(const Geo<float>& g, int nb, int cp0, const GeoCache& gc, const float* F, float* P,
-                          hipStream_t s) {
+                          hipStream_t s, const int* box) {
   const E* G = (const E*)gc.G + (size_t)cp0 * g.Nk * g.Nu * g.Nv;
-  return launch_apply_geometry<E>(g, nb, F, G, P, s);
+  return launch_apply_geometry<E>(g, nb, F, G, P, s, box);
 }
 
 template <typename E>
 hipError_t geometry_adjoint(const Geo<float>& g, int nb, int cp0, const GeoCache& gc, const float* H, float* A,
-                            hipStream_t s) {
+                            hipStream_t s, const int* box) {
   const E* G = (const E*)gc.G + (size_t)cp0 * g.Nk * g.Nu * g.Nv;
-  return launch_geometry_adjoint<E>(g, nb, H, G, A, s);
+  return launch_geometry_adjoint<E>(g, nb, H, G, A, s, box);
 }
 
 // With gc == nullptr the march computes the geometry from rho; with a cache (FP32
@@ -366,6 +373,8 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
   int* box = (int*)(w + P.lay.box);
   // the corrections spread the aperture's fluence by their blur radii
   const int box_du = g.fcorr ? fct.pu.R + fct.hs.R : 0, box_dv = g.fcorr ? fct.pv.R + fct.hs.R : 0;
+  // rays outside the box are skipped only when the convolution reads just the box
+  const int* ray_box = conv_uses_box<T>(g, spec->conv_mode) ? box : nullptr;
   const T* dd = (const T*)spec->dd;
   const int L = beam->n_leaf_pairs, n_cp = beam->n_cp;
   LAUNCH("frame", launch_frame<T>(g, (const T*)beam->gantry_deg, n_cp, frame, s));
@@ -387,13 +396,14 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
     if constexpr (std::is_same<T, float>::value) {
       if (gc) {
         zb = gc->z + (size_t)cp0 * g.Nk;
-        LAUNCH("apply_geometry", gc->type == PDRT_CACHE_F32 ? apply_geometry<float>(g, nb, cp0, *gc, F, vol0, s)
-                                                            : apply_geometry<__bf16>(g, nb, cp0, *gc, F, vol0, s));
+        LAUNCH("apply_geometry", gc->type == PDRT_CACHE_F32
+                                     ? apply_geometry<float>(g, nb, cp0, *gc, F, vol0, s, ray_box)
+                                     : apply_geometry<__bf16>(g, nb, cp0, *gc, F, vol0, s, ray_box));
       }
     }
     if (!gc) {
       LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
-      LAUNCH("march", launch_march<T>(g, nb, fr, rho_t, F, z, dd, vol0, s));
+      LAUNCH("march", launch_march<T>(g, nb, fr, rho_t, F, z, dd, vol0, s, ray_box));
     }
     LAUNCH(conv_name<T>(g, spec->conv_mode),
            run_conv<T>(g, spec->conv_mode, nb, zb, vol0, vol1, s, box, CONV_IN_BOX));
@@ -430,6 +440,8 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
   // the parameter gradients read A inside the aperture rectangle; the corrections'
   // adjoint gathers it from as far as their blur radii
   const int box_du = g.fcorr ? fct.pu.R + fct.hs.R : 0, box_dv = g.fcorr ? fct.pv.R + fct.hs.R : 0;
+  // with a box-restricted convolution H is valid only inside the box
+  const int* ray_box = conv_uses_box<T>(g, spec->conv_mode) ? box : nullptr;
   const T* dd = (const T*)spec->dd;
   const int L = beam->n_leaf_pairs, n_cp = beam->n_cp;
   LAUNCH("frame", launch_frame<T>(g, (const T*)beam->gantry_deg, n_cp, frame, s));
@@ -450,10 +462,10 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
     if constexpr (std::is_same<T, float>::value) {
       if (gc)
         LAUNCH("geometry_adjoint", gc->type == PDRT_CACHE_F32
-                                       ? geometry_adjoint<float>(g, nb, cp0, *gc, vol1, A, s)
-                                       : geometry_adjoint<__bf16>(g, nb, cp0, *gc, vol1, A, s));
+                                       ? geometry_adjoint<float>(g, nb, cp0, *gc, vol1, A, s, ray_box)
+                                       : geometry_adjoint<__bf16>(g, nb, cp0, *gc, vol1, A, s, ray_box));
     }
-    if (!gc) LAUNCH("march_adj", launch_march_adj<T>(g, nb, fr, rho_t, z, dd, vol1, A, s));
+    if (!gc) LAUNCH("march_adj", launch_march_adj<T>(g, nb, fr, rho_t, z, dd, vol1, A, s, ray_box));
     if (g.fcorr) {
       // A <- G_u G_v (X + a G_hu G_hv X), X = O A: the corrections' adjoint, so that
       // the parameter gradients see dL/d(aperture fluence)

@@ -329,8 +329,8 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
 // 16-byte LDS reads stay aligned) instead of on the region's tile grid, and the
 // work is split over the wavefronts by tile and by a range of tap rows: with nT
 // tiles each tile's rows p = 0..h are cut into C = NW / nT chunks, whose partial
-// sums are added in LDS in chunk order.  Every output of the region outside the
-// covered rectangle is written as 0.
+// sums are added in LDS in chunk order.  Outputs outside the covered rectangle are
+// not written: the adjoint ray march reads this volume only inside the box.
 template <int NW, int TPW>
 __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32_adj(Geo<float> g, RegionShape rs, F32Shape fs,
                                                                int n_items, const int4* __restrict__ box,
@@ -431,13 +431,6 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32_adj(Geo<float> g, Reg
 #pragma unroll
       for (int q = 0; q < TPW; ++q)
         if (q < nact) store_tile_at(g, oI[q], oJ[q], lane, acc[q], dst);
-    }
-    // every other output of the region is 0
-    const int rw = Je - J0, cnt = (Ie - I0) * rw;
-    const int cI1 = Iw + MT * nI, cJ1 = Jw + MT * nJ;
-    for (int idx = tid; idx < cnt; idx += NT) {
-      const int r = I0 + idx / rw, c = J0 + idx % rw;
-      if (!(r >= Iw && r < cI1 && c >= Jw && c < cJ1)) dst[(size_t)r * g.Nv + c] = 0.f;
     }
     __syncthreads();
   }

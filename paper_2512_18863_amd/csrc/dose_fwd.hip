@@ -220,10 +220,16 @@ hipError_t launch_ca_depth(const Geo<T>& g, int nb, const T* frame, const T* rho
 // G_k = (SAD / d_k)^2 DD(W_k) itself (rounded to E), so that P = F G later.
 enum { MARCH_PRIMARY = 0, MARCH_ADJOINT = 1, MARCH_GEOMETRY = 2 };
 
+//
+// With a box (the aperture rectangle of each control point, given when the
+// convolution honours it) rays outside it are skipped: the convolution never
+// reads P there, and the adjoint's A there is written as 0 (the parameter
+// gradients only read it inside).
 template <typename T, int MODE, typename E>
 __global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ frame, const T* __restrict__ rho_t,
                                                const T* __restrict__ F, const T* __restrict__ zca,
-                                               const T* __restrict__ dd, E* __restrict__ vol, T* __restrict__ A) {
+                                               const T* __restrict__ dd, E* __restrict__ vol, T* __restrict__ A,
+                                               const int* __restrict__ box) {
   constexpr bool ADJ = MODE == MARCH_ADJOINT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tab = reinterpret_cast<T*>(smem_raw);
@@ -234,6 +240,13 @@ __global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ f
   int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= plane) return;
   int i = r / g.Nv, j = r - i * g.Nv;
+  if (box) {
+    const int* bx = box + 4 * b;
+    if (!(i >= bx[0] && i < bx[1] && j >= bx[2] && j < bx[3])) {
+      if (MODE == MARCH_ADJOINT) A[(size_t)b * plane + r] = T(0);
+      return;
+    }
+  }
   E* vb = vol + (size_t)b * g.Nk * plane + r;
   T Fv = T(1);
   if (MODE == MARCH_PRIMARY) {
@@ -285,10 +298,10 @@ __global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ f
 
 template <typename T>
 hipError_t launch_march(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* F, const T* z, const T* dd,
-                        T* P, hipStream_t s) {
+                        T* P, hipStream_t s, const int* box) {
   dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
   hipLaunchKernelGGL((k_march<T, MARCH_PRIMARY, T>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t, F, z,
-                     dd, P, (T*)nullptr);
+                     dd, P, (T*)nullptr, box);
   return hipGetLastError();
 }
 
@@ -297,7 +310,7 @@ hipError_t launch_march_geometry(const Geo<float>& g, int nb, const float* frame
                                  const float* dd, E* G, hipStream_t s) {
   dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
   hipLaunchKernelGGL((k_march<float, MARCH_GEOMETRY, E>), grid, dim3(256), g.n_dd * sizeof(float), s, g, frame,
-                     rho_t, (const float*)nullptr, z, dd, G, (float*)nullptr);
+                     rho_t, (const float*)nullptr, z, dd, G, (float*)nullptr, (const int*)nullptr);
   return hipGetLastError();
 }
 template hipError_t launch_march_geometry<float>(const Geo<float>&, int, const float*, const float*, const float*,
@@ -307,11 +320,10 @@ template hipError_t launch_march_geometry<__bf16>(const Geo<float>&, int, const 
 
 template <typename T>
 hipError_t launch_march_adj(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* z, const T* dd,
-                            const T* H, T* A, hipStream_t s) {
+                            const T* H, T* A, hipStream_t s, const int* box) {
   dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
   hipLaunchKernelGGL((k_march<T, MARCH_ADJOINT, T>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t,
-                     (const T*)nullptr,
-                     z, dd, const_cast<T*>(H), A);
+                     (const T*)nullptr, z, dd, const_cast<T*>(H), A, box);
   return hipGetLastError();
 }
 
@@ -521,9 +533,9 @@ hipError_t launch_gather(const Geo<T>& g, int nb, int first, int last, const T* 
   template hipError_t launch_aperture_box<T>(const Geo<T>&, int, const T*, int, int, int*, hipStream_t);     \
   template hipError_t launch_ca_depth<T>(const Geo<T>&, int, const T*, const T*, T*, hipStream_t);           \
   template hipError_t launch_march<T>(const Geo<T>&, int, const T*, const T*, const T*, const T*, const T*, T*, \
-                                      hipStream_t);                                                          \
+                                      hipStream_t, const int*);                                              \
   template hipError_t launch_march_adj<T>(const Geo<T>&, int, const T*, const T*, const T*, const T*, const T*, \
-                                          T*, hipStream_t);                                                  \
+                                          T*, hipStream_t, const int*);                                      \
   template hipError_t launch_conv_direct<T>(const Geo<T>&, int, const T*, const T*, T*, hipStream_t);        \
   template hipError_t launch_gather<T>(const Geo<T>&, int, int, int, const T*, const T*, const T*, T*, T*,    \
                                        hipStream_t);

@@ -20,12 +20,22 @@ namespace pdrt {
 
 namespace {
 
+// Rays outside the control point's aperture rectangle (box, when given) are
+// skipped as in the ray march: P is not read there, and A there is 0.
+__device__ __forceinline__ bool outside_box(const int* box, int b, int r, int Nv) {
+  if (!box) return false;
+  const int i = r / Nv, j = r - i * Nv;
+  const int* bx = box + 4 * b;
+  return !(i >= bx[0] && i < bx[1] && j >= bx[2] && j < bx[3]);
+}
+
 template <typename E>
-__global__ void __launch_bounds__(256) k_apply_geometry(int Nk, int plane, const float* __restrict__ F,
-                                                        const E* __restrict__ G, float* __restrict__ P) {
+__global__ void __launch_bounds__(256) k_apply_geometry(int Nk, int Nv, int plane, const float* __restrict__ F,
+                                                        const E* __restrict__ G, float* __restrict__ P,
+                                                        const int* __restrict__ box) {
   const int b = blockIdx.y;
   const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= plane) return;
+  if (r >= plane || outside_box(box, b, r, Nv)) return;
   const float Fv = F[(size_t)b * plane + r];
   const E* gb = G + (size_t)b * Nk * plane + r;
   float* pb = P + (size_t)b * Nk * plane + r;
@@ -38,11 +48,16 @@ __global__ void __launch_bounds__(256) k_apply_geometry(int Nk, int plane, const
 }
 
 template <typename E>
-__global__ void __launch_bounds__(256) k_geometry_adjoint(int Nk, int plane, const float* __restrict__ H,
-                                                          const E* __restrict__ G, float* __restrict__ A) {
+__global__ void __launch_bounds__(256) k_geometry_adjoint(int Nk, int Nv, int plane, const float* __restrict__ H,
+                                                          const E* __restrict__ G, float* __restrict__ A,
+                                                          const int* __restrict__ box) {
   const int b = blockIdx.y;
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= plane) return;
+  if (outside_box(box, b, r, Nv)) {
+    A[(size_t)b * plane + r] = 0.f;
+    return;
+  }
   const E* gb = G + (size_t)b * Nk * plane + r;
   const float* hb = H + (size_t)b * Nk * plane + r;
   float acc = 0.f;
@@ -54,27 +69,30 @@ __global__ void __launch_bounds__(256) k_geometry_adjoint(int Nk, int plane, con
 }  // namespace
 
 template <typename E>
-hipError_t launch_apply_geometry(const Geo<float>& g, int nb, const float* F, const E* G, float* P, hipStream_t s) {
+hipError_t launch_apply_geometry(const Geo<float>& g, int nb, const float* F, const E* G, float* P, hipStream_t s,
+                                 const int* box) {
   const int plane = g.Nu * g.Nv;
-  hipLaunchKernelGGL(k_apply_geometry<E>, dim3((plane + 255) / 256, nb), dim3(256), 0, s, g.Nk, plane, F, G, P);
+  hipLaunchKernelGGL(k_apply_geometry<E>, dim3((plane + 255) / 256, nb), dim3(256), 0, s, g.Nk, g.Nv, plane, F, G, P,
+                     box);
   return hipGetLastError();
 }
 
 template <typename E>
-hipError_t launch_geometry_adjoint(const Geo<float>& g, int nb, const float* H, const E* G, float* A,
-                                   hipStream_t s) {
+hipError_t launch_geometry_adjoint(const Geo<float>& g, int nb, const float* H, const E* G, float* A, hipStream_t s,
+                                   const int* box) {
   const int plane = g.Nu * g.Nv;
-  hipLaunchKernelGGL(k_geometry_adjoint<E>, dim3((plane + 255) / 256, nb), dim3(256), 0, s, g.Nk, plane, H, G, A);
+  hipLaunchKernelGGL(k_geometry_adjoint<E>, dim3((plane + 255) / 256, nb), dim3(256), 0, s, g.Nk, g.Nv, plane, H, G,
+                     A, box);
   return hipGetLastError();
 }
 
 template hipError_t launch_apply_geometry<float>(const Geo<float>&, int, const float*, const float*, float*,
-                                                 hipStream_t);
+                                                 hipStream_t, const int*);
 template hipError_t launch_apply_geometry<__bf16>(const Geo<float>&, int, const float*, const __bf16*, float*,
-                                                  hipStream_t);
+                                                  hipStream_t, const int*);
 template hipError_t launch_geometry_adjoint<float>(const Geo<float>&, int, const float*, const float*, float*,
-                                                   hipStream_t);
+                                                   hipStream_t, const int*);
 template hipError_t launch_geometry_adjoint<__bf16>(const Geo<float>&, int, const float*, const __bf16*, float*,
-                                                    hipStream_t);
+                                                    hipStream_t, const int*);
 
 }  // namespace pdrt

@@ -73,10 +73,10 @@ template <typename T>
 hipError_t launch_ca_depth(const Geo<T>& g, int nb, const T* frame, const T* rho_t, T* z, hipStream_t s);
 template <typename T>
 hipError_t launch_march(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* F, const T* z,
-                        const T* dd, T* P, hipStream_t s);
+                        const T* dd, T* P, hipStream_t s, const int* box = nullptr);
 template <typename T>
 hipError_t launch_march_adj(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* z, const T* dd,
-                            const T* H, T* A, hipStream_t s);
+                            const T* H, T* A, hipStream_t s, const int* box = nullptr);
 // Support of a lateral convolution: box[b] = {u0, u1, v0, v1} (int4 per control
 // point) bounds the aperture; CONV_IN_BOX: inputs outside it are zero; CONV_OUT_BOX:
 // only outputs inside it are needed (the rest are written as 0).
@@ -90,10 +90,11 @@ template <typename E>
 hipError_t launch_march_geometry(const Geo<float>& g, int nb, const float* frame, const float* rho_t, const float* z,
                                  const float* dd, E* G, hipStream_t s);
 template <typename E>
-hipError_t launch_apply_geometry(const Geo<float>& g, int nb, const float* F, const E* G, float* P, hipStream_t s);
+hipError_t launch_apply_geometry(const Geo<float>& g, int nb, const float* F, const E* G, float* P, hipStream_t s,
+                                 const int* box = nullptr);
 template <typename E>
 hipError_t launch_geometry_adjoint(const Geo<float>& g, int nb, const float* H, const E* G, float* A,
-                                   hipStream_t s);
+                                   hipStream_t s, const int* box = nullptr);
 template <typename T>
 hipError_t launch_conv_direct(const Geo<T>& g, int nb, const T* z, const T* in, T* out, hipStream_t s);
 // Small kernels (odd n <= 11) whose plane band fits the LDS budget.
