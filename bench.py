@@ -57,7 +57,8 @@ def measured_traffic(kernel: str, workload: str):
     return e.get("bytes_per_launch")
 
 
-KERNEL_SYMBOLS = {"conv_mfma_f32": "k_conv_mfma_f32<"}
+# the FP32 convolution's two kernels (forward on the aperture's inputs, adjoint on its outputs)
+KERNEL_SYMBOLS = {"conv_mfma_f32": ("k_conv_mfma_f32<", "k_conv_mfma_f32_adj<")}
 COPY_BYTES = 1 << 30   # the counter run's calibration copy
 
 
@@ -100,8 +101,8 @@ def traffic_from_counters(fetch_csv, write_csv, workload="c4bench_fp32"):
     for k, (cnt, fb, wb) in per.items():
         rec["all_kernels_" + workload][k] = {"dispatches": cnt, "fetch_bytes_per_launch": fb / cnt,
                                              "write_bytes_per_launch": wb / cnt}
-    for name, sym in KERNEL_SYMBOLS.items():
-        hits = [(n, v, v2) for (n, v), (_, v2) in zip(fetch, write) if sym in n]
+    for name, syms in KERNEL_SYMBOLS.items():
+        hits = [(n, v, v2) for (n, v), (_, v2) in zip(fetch, write) if any(sy in n for sy in syms)]
         if hits:
             fb = sum(h[1] for h in hits) * 1024.0 * kf / len(hits)
             wb = sum(h[2] for h in hits) * 1024.0 * kw / len(hits)
@@ -125,15 +126,17 @@ def aperture_pixels(jaws, lat, Nu, Nv):
     return np.array([count(j[0], j[1], Nu) * count(j[2], j[3], Nv) for j in np.asarray(jaws)])
 
 
-def hbm_table(kernels, steps, n_cp, nodes, plane, vox):
+def hbm_table(kernels, steps, n_cp, nodes, ap_nodes, plane, vox):
     """Achieved bandwidth of the memory-bound kernels from their algorithmic bytes
     (each byte the kernel must move once): nodes = beam-frame nodes of the plan,
-    plane = fluence pixels per control point, vox = CT voxels."""
+    ap_nodes = those on the control points' apertures (the only rays the march
+    and its adjoint process), plane = fluence pixels per control point, vox = CT
+    voxels."""
     b = {
-        "march": 4 * nodes + 4 * n_cp * plane + 4 * vox,              # write P; read F, rho
+        "march": 4 * ap_nodes + 4 * n_cp * plane + 4 * vox,           # write P on the aperture; read F, rho
         "gather": 4 * nodes + 2 * 4 * vox,                            # read Dfan; write dose + compensation
         "backproject_adj": 4 * nodes + 4 * vox,                       # write G; read g
-        "march_adj": 4 * nodes + 4 * n_cp * plane + 4 * vox,          # read H; write A; read rho
+        "march_adj": 4 * ap_nodes + 4 * n_cp * plane + 4 * vox,       # read H on the aperture; write A; read rho
     }
     out = {}
     for k, by in b.items():
@@ -356,7 +359,8 @@ def main():
                              "%d of %d nodes" % (ap_nodes, nodes),
                      "dense_equivalent_TFLOPs": round(dense_flops / avg_s / 1e12, 3) if avg_s > 0 else 0.0},
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(kernels.items())},
-        "hbm_kernels": hbm_table(kernels, args.steps, n_cp, nodes, eng.Nu * eng.Nv, int(np.prod(case.shape))),
+        "hbm_kernels": hbm_table(kernels, args.steps, n_cp, nodes, ap_nodes, eng.Nu * eng.Nv,
+                                 int(np.prod(case.shape))),
         "paper_context": {"value": 35.3, "unit": "control points/s (fwd+bwd)", "hardware": "NVIDIA A40",
                           "workload": "105x224x224 grid, 180 control points, kernel 55 (Table 6: 5.102 s)"},
     }
