@@ -250,8 +250,9 @@ __global__ void __launch_bounds__(256) k_backproject_adj(Geo<T> g, int tiles_i, 
 // their Nv sums in registers (lanes along j).  Its members are the voxel columns
 // with floor(kappa) in [k0-1, k0+TK) and floor(iota) in [i0-1, i0+TI), found by
 // testing the voxel columns of the block's rotated bounding box 64 at a time with
-// the forward's index arithmetic; each member's z sum T_c[j] is formed once and
-// added with weight w_k w_i to the (at most four) columns of the block it touches.
+// the forward's index arithmetic; each member's z sum T_c[j] (tent form below) is
+// formed once and added with weight w_k w_i to the (at most four) columns of the
+// block it touches.
 // Members are taken in scan order and z in increasing order, so every sum has a
 // fixed order; no LDS, no barriers, no atomics.
 constexpr int BR_TK = 4, BR_TI = 4;
@@ -266,6 +267,22 @@ __device__ __forceinline__ double bcast(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ int bcast(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+
+// z sum of one member column for beam-frame j in tent form: along the column the
+// continuous index jj(z) = A + B z is affine (A = rel_oz q / lat + c_v,
+// B = s_z q / lat), and the trilinear weight of node j is max(0, 1 - |jj - j|);
+// only the z with jj in (j - 1, j + 1), found from the inverse map, are visited.
+template <typename T, typename Col>
+__device__ __forceinline__ T z_sum_tent(const Geo<T>& g, int j, T A, T B, T invB, Col col) {
+  const T za = (T(j - 1) - A) * invB, zb = (T(j + 1) - A) * invB;
+  const int z0 = max(0, (int)dfloor(za)), z1 = min(g.nz - 1, (int)dfloor(zb));
+  T part = T(0);
+  for (int z = z0; z <= z1; ++z) {
+    const T jj = A + T(z) * B;
+    part += fmax(T(0), T(1) - fabs(jj - T(j))) * col(z);
+  }
+  return part;
+}
 
 template <typename T, int JS>
 __global__ void __launch_bounds__(256) k_backproject_reg(Geo<T> g, int nb, int tiles_k, int tiles_i, int per_xcd,
@@ -339,11 +356,13 @@ __global__ void __launch_bounds__(256) k_backproject_reg(Geo<T> g, int nb, int t
       const int ck = bcast(kf, src), ci = bcast(ifl, src), cc = bcast(col, src);
       const T cwk = bcast(wk, src), cwi = bcast(wi, src), cq = bcast(q, src), cdq = bcast(dq, src);
       const T* gcol = g_t + (size_t)cc * g.nz;
+      const T qi = cq * g.inv_lat;
+      const T A = g.rel_oz * qi + g.cv, B = g.sz * qi, invB = cdq * g.lat * g.inv_sz;
       T part[JS];
 #pragma unroll
       for (int s = 0; s < JS; ++s) {
         const int j = 64 * s + lane;
-        part[s] = j < g.Nv ? z_sum(g, j, cq, cdq, [&](int z) { return gcol[z]; }) : T(0);
+        part[s] = j < g.Nv ? z_sum_tent(g, j, A, B, invB, [&](int z) { return gcol[z]; }) : T(0);
       }
       T wK[BR_TK], wI[BR_TI];
 #pragma unroll

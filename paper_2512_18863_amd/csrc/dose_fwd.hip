@@ -225,28 +225,14 @@ enum { MARCH_PRIMARY = 0, MARCH_ADJOINT = 1, MARCH_GEOMETRY = 2 };
 // convolution honours it) rays outside it are skipped: the convolution never
 // reads P there, and the adjoint's A there is written as 0 (the parameter
 // gradients only read it inside).
+// One ray (i, j) of control point b.
 template <typename T, int MODE, typename E>
-__global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ frame, const T* __restrict__ rho_t,
-                                               const T* __restrict__ F, const T* __restrict__ zca,
-                                               const T* __restrict__ dd, E* __restrict__ vol, T* __restrict__ A,
-                                               const int* __restrict__ box) {
-  constexpr bool ADJ = MODE == MARCH_ADJOINT;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* tab = reinterpret_cast<T*>(smem_raw);
-  for (int q = threadIdx.x; q < g.n_dd; q += 256) tab[q] = dd[q];
-  __syncthreads();
-  int b = blockIdx.y;
-  int plane = g.Nu * g.Nv;
-  int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= plane) return;
-  int i = r / g.Nv, j = r - i * g.Nv;
-  if (box) {
-    const int* bx = box + 4 * b;
-    if (!(i >= bx[0] && i < bx[1] && j >= bx[2] && j < bx[3])) {
-      if (MODE == MARCH_ADJOINT) A[(size_t)b * plane + r] = T(0);
-      return;
-    }
-  }
+__device__ __forceinline__ void march_ray(const Geo<T>& g, int b, int i, int j, const T* __restrict__ frame,
+                                          const T* __restrict__ rho_t, const T* __restrict__ F,
+                                          const T* __restrict__ zca, const T* tab, E* __restrict__ vol,
+                                          T* __restrict__ A) {
+  const int plane = g.Nu * g.Nv;
+  const int r = i * g.Nv + j;
   E* vb = vol + (size_t)b * g.Nk * plane + r;
   T Fv = T(1);
   if (MODE == MARCH_PRIMARY) {
@@ -263,7 +249,7 @@ __global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ f
   const T* zb = zca + (size_t)b * g.Nk;
   T W = T(0), c = T(0), acc = T(0);
   // one step of the march: the water-equivalent depth Wk of plane k, then the
-  // primary (or, for ADJ, its adjoint) at that plane
+  // primary (or its adjoint, or the factor itself) at that plane
   auto step = [&](int k, T Wk) {
     const T e = g.e0 + T(k) * g.dstep;
     const T gk = T(1) + e * g.inv_sad;
@@ -293,13 +279,56 @@ __global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ f
   } else {
     for (int k = 0; k < g.Nk; ++k) step(k, zb[k]);
   }
-  if (ADJ) A[(size_t)b * plane + r] = acc;
+  if (MODE == MARCH_ADJOINT) A[(size_t)b * plane + r] = acc;
+}
+
+// Without a box, one thread per ray of the plane; with a box, the block row
+// blockIdx.y = b walks only the rays of control point b's rectangle (grid-stride),
+// so no lanes idle on rays outside it.  (In adjoint mode A outside the box is
+// cleared beforehand.)
+template <typename T, int MODE, typename E>
+__global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ frame, const T* __restrict__ rho_t,
+                                               const T* __restrict__ F, const T* __restrict__ zca,
+                                               const T* __restrict__ dd, E* __restrict__ vol, T* __restrict__ A,
+                                               const int* __restrict__ box) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tab = reinterpret_cast<T*>(smem_raw);
+  for (int q = threadIdx.x; q < g.n_dd; q += 256) tab[q] = dd[q];
+  __syncthreads();
+  const int b = blockIdx.y;
+  if (box) {
+    const int* bx = box + 4 * b;
+    const int bw = bx[3] - bx[2], area = bx[1] > bx[0] && bw > 0 ? (bx[1] - bx[0]) * bw : 0;
+    for (int rr = blockIdx.x * 256 + threadIdx.x; rr < area; rr += gridDim.x * 256) {
+      const int li = rr / bw;
+      march_ray<T, MODE, E>(g, b, bx[0] + li, bx[2] + rr - li * bw, frame, rho_t, F, zca, tab, vol, A);
+    }
+  } else {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < g.Nu * g.Nv) march_ray<T, MODE, E>(g, b, r / g.Nv, r % g.Nv, frame, rho_t, F, zca, tab, vol, A);
+  }
+}
+
+template <typename T>
+__global__ void k_fill_zero(size_t n, T* __restrict__ p) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+    p[q] = T(0);
+}
+
+// Blocks per control point for a box-restricted march: enough for the largest
+// jaw rectangle the field limit allows (the plane minus the kernel halo, plus the
+// rectangle's margins); the walk is grid-stride, so a larger box (fluence
+// corrections, jaws beyond the field limit) is still covered.
+template <typename T>
+int march_box_blocks(const Geo<T>& g) {
+  const int bu = min(g.Nu, g.Nu - 2 * g.h + 6), bv = min(g.Nv, g.Nv - 2 * g.h + 6);
+  return max(1, (bu * bv + 255) / 256);
 }
 
 template <typename T>
 hipError_t launch_march(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* F, const T* z, const T* dd,
                         T* P, hipStream_t s, const int* box) {
-  dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
+  dim3 grid(box ? march_box_blocks(g) : (g.Nu * g.Nv + 255) / 256, nb);
   hipLaunchKernelGGL((k_march<T, MARCH_PRIMARY, T>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t, F, z,
                      dd, P, (T*)nullptr, box);
   return hipGetLastError();
@@ -321,7 +350,13 @@ template hipError_t launch_march_geometry<__bf16>(const Geo<float>&, int, const 
 template <typename T>
 hipError_t launch_march_adj(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* z, const T* dd,
                             const T* H, T* A, hipStream_t s, const int* box) {
-  dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
+  if (box) {
+    const size_t n = (size_t)nb * g.Nu * g.Nv;
+    hipLaunchKernelGGL(k_fill_zero<T>, dim3((unsigned)((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048)), dim3(256), 0,
+                       s, n, A);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+  }
+  dim3 grid(box ? march_box_blocks(g) : (g.Nu * g.Nv + 255) / 256, nb);
   hipLaunchKernelGGL((k_march<T, MARCH_ADJOINT, T>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t,
                      (const T*)nullptr, z, dd, const_cast<T*>(H), A, box);
   return hipGetLastError();
