@@ -463,6 +463,23 @@ __device__ void block_reduce(T (&v)[N], T* red) {
   for (int q = 0; q < N; ++q) v[q] = red[q * 256];
 }
 
+__device__ __forceinline__ float dceil(float x) { return ceilf(x); }
+__device__ __forceinline__ double dceil(double x) { return ceil(x); }
+
+// First leaf pair whose upper edge lies above x (edges ascending; L if none).
+template <typename T>
+__device__ __forceinline__ int leaf_first(const Geo<T>& g, T x) {
+  int lo = 0, hi = g.L;  // answer in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (g.leaf_edges[mid + 1] > x)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
 // One block per control point.  With F = fx fy [tau S + (1 - tau) O] and
 // O = sum_l w_l f(u; l_l, r_l):
 //   dL/dMU = calib sum A F,  gF = calib MU A,
@@ -477,33 +494,44 @@ __global__ void __launch_bounds__(256) k_param_grad(Geo<T> g, const T* __restric
                                                     T* __restrict__ gjaws, T* __restrict__ gmu) {
   __shared__ T red[5 * 256];
   const int b = blockIdx.x, tid = threadIdx.x;
-  const int plane = g.Nu * g.Nv, L = g.L;
+  const int L = g.L;
   const T D = g.lat, iD = g.inv_lat, tau = g.tau;
   const T* jw = jaws + 4 * b;
   const T* lv = leaves + (size_t)2 * L * b;
-  const T* Ab = A + (size_t)b * plane;
+  const T* Ab = A + (size_t)b * g.Nu * g.Nv;
   const T scale = g.calib * mu[b];
+  // Every term carries fx fy or one of their jaw derivatives, which vanish on
+  // pixels that do not overlap the jaw opening: only the pixels of the jaw
+  // rectangle (one pixel wider each side) are visited, and for each pixel row
+  // only the leaf pairs whose rows it overlaps.
+  const int u0 = max(0, (int)dfloor(jw[0] * iD + g.cu - T(0.5)) - 1);
+  const int u1 = min(g.Nu, (int)dceil(jw[1] * iD + g.cu + T(0.5)) + 1);
+  const int v0 = max(0, (int)dfloor(jw[2] * iD + g.cv - T(0.5)) - 1);
+  const int v1 = min(g.Nv, (int)dceil(jw[3] * iD + g.cv + T(0.5)) + 1);
+  const bool finite = jw[0] == jw[0] && jw[1] == jw[1] && jw[2] == jw[2] && jw[3] == jw[3];
+  const int iu0 = finite ? u0 : 0, iu1 = finite ? u1 : g.Nu, iv0 = finite ? v0 : 0, iv1 = finite ? v1 : g.Nv;
+  const int bw = iv1 - iv0, area = iu1 > iu0 && bw > 0 ? (iu1 - iu0) * bw : 0;
   T acc[5] = {T(0), T(0), T(0), T(0), T(0)};
-  for (int r = tid; r < plane; r += 256) {
-    int i = r / g.Nv, j = r - i * g.Nv;
-    T u = (T(i) - g.cu) * D, v = (T(j) - g.cv) * D;
-    T fx = overlap(u, jw[0], jw[1], D, iD), fy = overlap(v, jw[2], jw[3], D, iD);
-    T dx1 = overlap_da(u, jw[0], jw[1], D, iD), dx2 = overlap_db(u, jw[0], jw[1], D, iD);
-    T dy1 = overlap_da(v, jw[2], jw[3], D, iD), dy2 = overlap_db(v, jw[2], jw[3], D, iD);
+  for (int rr = tid; rr < area; rr += 256) {
+    const int i = iu0 + rr / bw, j = iv0 + rr % bw;
+    const T u = (T(i) - g.cu) * D, v = (T(j) - g.cv) * D;
+    const T fx = overlap(u, jw[0], jw[1], D, iD), fy = overlap(v, jw[2], jw[3], D, iD);
+    const T dx1 = overlap_da(u, jw[0], jw[1], D, iD), dx2 = overlap_db(u, jw[0], jw[1], D, iD);
+    const T dy1 = overlap_da(v, jw[2], jw[3], D, iD), dy2 = overlap_db(v, jw[2], jw[3], D, iD);
     if (fx == T(0) && fy == T(0)) continue;
     if (fx == T(0) && dx1 == T(0) && dx2 == T(0)) continue;
     if (fy == T(0) && dy1 == T(0) && dy2 == T(0)) continue;
     T S = T(0), O = T(0);
-    for (int l = 0; l < L; ++l) {
-      T w = overlap(v, g.leaf_edges[l], g.leaf_edges[l + 1], D, iD);
+    for (int l = leaf_first(g, v - T(0.5) * D); l < L && g.leaf_edges[l] < v + T(0.5) * D; ++l) {
+      const T w = overlap(v, g.leaf_edges[l], g.leaf_edges[l + 1], D, iD);
       if (w > T(0)) {
         S += w;
         O += w * overlap(u, lv[l], lv[L + l], D, iD);
       }
     }
-    T br = tau * S + (T(1) - tau) * O;
-    T a = Ab[r];
-    T gF = scale * a;
+    const T br = tau * S + (T(1) - tau) * O;
+    const T a = Ab[(size_t)i * g.Nv + j];
+    const T gF = scale * a;
     acc[0] += a * fx * fy * br;
     acc[1] += gF * dx1 * fy * br;
     acc[2] += gF * dx2 * fy * br;
@@ -515,22 +543,46 @@ __global__ void __launch_bounds__(256) k_param_grad(Geo<T> g, const T* __restric
     gmu[b] = g.calib * acc[0];
     for (int q = 0; q < 4; ++q) gjaws[4 * b + q] = acc[1 + q];
   }
+  // A leaf edge's derivative lives on the pixel columns next to the edge and the
+  // pixel rows the leaf pair overlaps.
   for (int t = tid; t < 2 * L; t += 256) {
-    int side = t / L, l = t - side * L;
-    T lo = lv[l], hi = lv[L + l];
+    const int side = t / L, l = t - side * L;
+    const T lo = lv[l], hi = lv[L + l];
+    const T edge = side ? hi : lo;
     T s = T(0);
-    for (int j = 0; j < g.Nv; ++j) {
-      T v = (T(j) - g.cv) * D;
-      T w = overlap(v, g.leaf_edges[l], g.leaf_edges[l + 1], D, iD);
-      if (!(w > T(0))) continue;
-      T fy = overlap(v, jw[2], jw[3], D, iD);
-      if (fy == T(0)) continue;
-      for (int i = 0; i < g.Nu; ++i) {
-        T u = (T(i) - g.cu) * D;
-        T d = side ? overlap_db(u, lo, hi, D, iD) : overlap_da(u, lo, hi, D, iD);
-        if (d == T(0)) continue;
-        T fx = overlap(u, jw[0], jw[1], D, iD);
-        s += scale * Ab[(size_t)i * g.Nv + j] * fx * fy * (T(1) - tau) * w * d;
+    if (edge == edge && fabs(edge) < T(1e8)) {
+      const int ic = (int)dfloor(edge * iD + g.cu + T(0.5));
+      const int ja = max(0, (int)dfloor(g.leaf_edges[l] * iD + g.cv - T(0.5)) - 1);
+      const int jb = min(g.Nv - 1, (int)dceil(g.leaf_edges[l + 1] * iD + g.cv + T(0.5)) + 1);
+      for (int j = ja; j <= jb; ++j) {
+        const T v = (T(j) - g.cv) * D;
+        const T w = overlap(v, g.leaf_edges[l], g.leaf_edges[l + 1], D, iD);
+        if (!(w > T(0))) continue;
+        const T fy = overlap(v, jw[2], jw[3], D, iD);
+        if (fy == T(0)) continue;
+        for (int i = max(0, ic - 1); i <= min(g.Nu - 1, ic + 1); ++i) {
+          const T u = (T(i) - g.cu) * D;
+          const T d = side ? overlap_db(u, lo, hi, D, iD) : overlap_da(u, lo, hi, D, iD);
+          if (d == T(0)) continue;
+          const T fx = overlap(u, jw[0], jw[1], D, iD);
+          s += scale * Ab[(size_t)i * g.Nv + j] * fx * fy * (T(1) - tau) * w * d;
+        }
+      }
+    } else {
+      // non-finite edge: the full scan (it contributes only where its overlap derivative is defined)
+      for (int j = 0; j < g.Nv; ++j) {
+        const T v = (T(j) - g.cv) * D;
+        const T w = overlap(v, g.leaf_edges[l], g.leaf_edges[l + 1], D, iD);
+        if (!(w > T(0))) continue;
+        const T fy = overlap(v, jw[2], jw[3], D, iD);
+        if (fy == T(0)) continue;
+        for (int i = 0; i < g.Nu; ++i) {
+          const T u = (T(i) - g.cu) * D;
+          const T d = side ? overlap_db(u, lo, hi, D, iD) : overlap_da(u, lo, hi, D, iD);
+          if (d == T(0)) continue;
+          const T fx = overlap(u, jw[0], jw[1], D, iD);
+          s += scale * Ab[(size_t)i * g.Nv + j] * fx * fy * (T(1) - tau) * w * d;
+        }
       }
     }
     gleaves[(size_t)2 * L * b + t] = s;
