@@ -566,17 +566,42 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
       if (cur.nr == 0) p_hi = p_lo - 1;
       a_lo = max(0, floor_div16(cur.c0 - (J0 - h)));
       a_hi = min(na - 1, floor_div16(cur.c0 + cur.nc - 1 - (J0 - h)));
-    } else if (SUP == CONV_OUT_BOX) {
-      const int4 bx = box[bk / g.Nk];
-      if (bx.y <= I || bx.x >= I + 32 || bx.y <= bx.x || bx.w <= bx.z) p_hi = p_lo - 1;  // strip not needed
-      t_lo = max(0, (bx.z - J0) >= 0 ? (bx.z - J0) / 32 : -((31 - (bx.z - J0)) / 32));
-      t_hi = min(RJ - 1, (bx.w - 1 - J0) >= 0 ? (bx.w - 1 - J0) / 32 : -1);
-      if (t_hi < t_lo) p_hi = p_lo - 1;
-      a_lo = 2 * t_lo;
-      a_hi = min(na - 1, 2 * t_hi + S - 1);
     }
     const int n_need = p_hi >= p_lo ? p_hi - p_lo + 1 : 0, per = (n_need + BQ - 1) / BQ;
-    const int p_begin = p_lo + quarter * per, p_end = min(p_lo + n_need, p_begin + per);
+    int p_begin = p_lo + quarter * per, p_end = min(p_lo + n_need, p_begin + per);
+    // CONV_OUT_BOX: nS strips of 32 rows placed at the box's top row (Iw) and nJ
+    // tiles at its left column rounded down to a multiple of 8 (Jw, so the 16-byte
+    // fragment reads stay aligned); the NW wavefronts split as nS strips x C chunks
+    // of the tap rows, whose partial sums are added in a fixed binary tree.
+    const __bf16* a_base = abase;
+    int C = BQ, chunk = quarter, s_idx = strip, nS = 0, out_I = I, out_J = J0;
+    if (SUP == CONV_OUT_BOX) {
+      const int4 bx = box[bk / g.Nk];
+      const int Ie = min(g.Nu, I0 + 32 * bs.RI), Je = min(g.Nv, J0 + 32 * RJ);
+      const int u0 = max(bx.x, I0), u1 = min(bx.y, Ie), v0 = max(bx.z, J0), v1 = min(bx.w, Je);
+      int nJ = 0, Iw = I0, Jw = J0;
+      if (u1 > u0 && v1 > v0) {
+        nS = (u1 - u0 + 31) / 32;
+        Iw = min(u0, I0 + 32 * bs.RI - 32 * nS);
+        const int ja = v0 - ((v0 - J0) & 7);
+        nJ = (v1 - ja + 31) / 32;
+        Jw = min(ja, J0 + 32 * RJ - 32 * nJ);
+      }
+      C = nS > 0 ? NW / nS : NW;
+      s_idx = wave / C;
+      chunk = wave - s_idx * C;
+      a_base = tile + (Iw - I0 + 32 * s_idx + m + h) * pitch + (Jw - J0) + 8 * hi;
+      out_I = Iw + 32 * s_idx;
+      out_J = Jw;
+      t_lo = 0;
+      t_hi = nJ - 1;
+      a_lo = 0;
+      a_hi = min(na - 1, 2 * (nJ - 1) + S - 1);
+      const int n_p = 2 * h + 1;
+      p_begin = -h + (n_p * chunk) / C;
+      p_end = -h + (n_p * (chunk + 1)) / C;
+      if (s_idx >= nS || nJ == 0) p_end = p_begin;
+    }
     unique_taps(g, k, zca[bk], kq, tid, NT);
     __syncthreads();
     // Extended tap row x (x = q + h + 31) stored in copy r at position x + sigma_r,
@@ -614,7 +639,7 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
     for (int p = p_begin; p < p_end; ++p) {
       const int ap = p < 0 ? -p : p;
       const __bf16* brow = bbase + ap * 8 * CL;
-      const __bf16* arow = abase + p * pitch;
+      const __bf16* arow = a_base + p * pitch;
       bf16x8 Bf[SMAX];
 #pragma unroll
       for (int s2 = 0; s2 < SMAX; ++s2)
@@ -632,6 +657,52 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
           }
         }
       }
+    }
+    if (SUP == CONV_OUT_BOX) {
+      // binary tree over the chunks of each strip (the taps are dead now): in round
+      // d, chunk c = 2 d m + d parks its sums in slot m and chunk 2 d m adds them
+      const int spp = C / 2;  // slots per strip (C is even)
+      for (int d = 1; d < C; d <<= 1) {
+        __syncthreads();
+        if (s_idx < nS && chunk % (2 * d) == d) {
+          float* slot = part + (size_t)(s_idx * spp + chunk / (2 * d)) * RJ * 1024;
+#pragma unroll
+          for (int t = 0; t < RJ; ++t)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4)
+              *reinterpret_cast<f32x4*>(slot + t * 1024 + r4 * 256 + 4 * lane) =
+                  f32x4{acc[t][4 * r4], acc[t][4 * r4 + 1], acc[t][4 * r4 + 2], acc[t][4 * r4 + 3]};
+        }
+        __syncthreads();
+        if (s_idx < nS && chunk % (2 * d) == 0 && chunk + d < C) {
+          const float* slot = part + (size_t)(s_idx * spp + chunk / (2 * d)) * RJ * 1024;
+#pragma unroll
+          for (int t = 0; t < RJ; ++t)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+              const f32x4 v = *reinterpret_cast<const f32x4*>(slot + t * 1024 + r4 * 256 + 4 * lane);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) acc[t][4 * r4 + e] += v[e];
+            }
+        }
+      }
+      if (s_idx < nS && chunk == 0) {
+        float* dst = out + (size_t)bk * plane;
+#pragma unroll
+        for (int t = 0; t < RJ; ++t) {
+          if (t > t_hi) break;
+          const int j = out_J + 32 * t + m;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int i = out_I + 8 * (r >> 2) + 4 * hi + (r & 3);
+            if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[t][r];
+          }
+        }
+      }
+      prev = cur;
+      cur = nxt;
+      __syncthreads();  // the partial sums alias the next item's taps
+      continue;
     }
     // add the quarters 1..3 into quarter 0 through LDS (the taps are dead now)
     for (int qd = 1; qd < BQ; ++qd) {
@@ -767,6 +838,10 @@ template <int RJ, int SMAX, int SUP>
 static hipError_t launch_bf16_cfg(const Geo<float>& g, const BF16Shape& bs, size_t lds, int nb, const int4* box,
                                   const float* z, const float* in, float* out, hipStream_t s) {
   const void* kern = (const void*)k_conv_mfma_bf16<RJ, SMAX, SUP>;
+  if (SUP == CONV_OUT_BOX) {  // the tree's slots: NW / 2 of RJ tiles each
+    const size_t slots = bf16_tile_bytes(bs) + (size_t)(BQ * bs.RI / 2) * RJ * 1024 * sizeof(float);
+    if (slots > lds) lds = slots;
+  }
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
