@@ -62,6 +62,18 @@ __device__ __forceinline__ void store_tile_at(const Geo<float>& g, int i0, int j
   }
 }
 
+// The same, storing only rows >= ilo and columns >= jlo (tiles of a shifted grid).
+__device__ __forceinline__ void store_tile_from(const Geo<float>& g, int i0, int j0, int ilo, int jlo, int lane,
+                                                const f32x4& acc, float* dst) {
+  const int m = lane & 15, r4 = lane >> 4;
+  const int j = j0 + m;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + 4 * r4 + r;
+    if (i >= ilo && j >= jlo && i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[r];
+  }
+}
+
 // ------------------------------------------------------------------ FP32
 //
 // v_mfma_f32_16x16x4_f32 on 16 x 16 tiles, tap rows folded (rows i+p and i-p
@@ -95,19 +107,31 @@ static size_t f32_lds(int h, const F32Shape& fs) {
   return sizeof(float) * ((size_t)fs.rows * fs.pitch + (size_t)(h + 1) * fs.E + (size_t)(h + 1) * (h + 1)) + 16;
 }
 
+// CONV_IN_BOX: after the counter, per tile its step ranges (8 ints) and the tile
+// order (one int), RMAX x RMAX tiles.
+constexpr size_t kBoxTileLds = sizeof(int) * 9 * RMAX * RMAX;
+
 constexpr int PF = 12;  // prefetched elements per thread
+constexpr bool kFoldSegments = true;  // CONV_IN_BOX: split each tile's tap rows by fold side
 
 // The matrix loop over tap rows p in [pa, pb] and super-steps u in [ua, ub] for
 // NA tiles that share the Toeplitz operand.  Two operand sets are loaded
-// alternately one step ahead of their use: the loop body covers two steps, so no
-// register copies sit between a load and the matrix instructions it feeds.
+// alternately one step ahead of their use: the loop body covers two steps and
+// its loads are unconditional (the load past the last step reads the last step's
+// addresses again and is not used), so the body is straight-line code and each
+// matrix step waits only for its own operands, never for the loads in flight
+// for the next step.
 // B[k][n] of instruction s in super-step u = K[p][16 u + 4 k + s - h - n]
 //                                           = kx[p][16 u + 4 k + s + 15 - n].
-template <int NA>
+// MODE 0 adds the two folded rows i + p and i - p; MODE 1 uses row i + p only and
+// MODE 2 row i - p only (tap rows whose other row lies outside the input's
+// support, where it would add exact zeros): half the operand loads, no adds.
+template <int NA, int MODE = 0>
 __device__ __forceinline__ void f32_steps(const float* const* abase, const float* bbase, int pitch, int E, int pa,
                                           int pb, int ua, int ub, f32x4* acc) {
   const int nu = ub - ua + 1;
   const int total = (pb >= pa && nu > 0) ? (pb - pa + 1) * nu : 0;
+  if (total <= 0) return;
   const float* ab[NA];
 #pragma unroll
   for (int q = 0; q < NA; ++q) ab[q] = abase[q];
@@ -116,41 +140,42 @@ __device__ __forceinline__ void f32_steps(const float* const* abase, const float
   for (int q = 0; q < NA; ++q) ac_[q] = acc[q];
   int lp = pa, lu = ua;  // next step to load: tap row lp, super-step lu
   auto load = [&](f32x4v (&a0)[NA], f32x4v (&a1)[NA], float (&bb)[4]) {
-    const int op = lp * pitch + 16 * lu, om = 16 * lu - lp * pitch;
-    const float* br = bbase + lp * E + 16 * lu;
+    const int p = min(lp, pb);  // past the last step: reload the last tap row
+    const int op = p * pitch + 16 * lu, om = 16 * lu - p * pitch;
+    const float* br = bbase + p * E + 16 * lu;
 #pragma unroll
     for (int e = 0; e < 4; ++e) bb[e] = br[e];
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-      a0[q] = *reinterpret_cast<const f32x4v*>(ab[q] + op);
-      a1[q] = *reinterpret_cast<const f32x4v*>(ab[q] + om);
+      if (MODE != 2) a0[q] = *reinterpret_cast<const f32x4v*>(ab[q] + op);
+      if (MODE != 1) a1[q] = *reinterpret_cast<const f32x4v*>(ab[q] + om);
     }
-    if (++lu > ub) {
-      lu = ua;
-      ++lp;
-    }
+    const bool wrap = lu >= ub;
+    lu = wrap ? ua : lu + 1;
+    lp += wrap ? 1 : 0;
   };
   auto compute = [&](const f32x4v (&a0)[NA], const f32x4v (&a1)[NA], const float (&bb)[4]) {
     f32x4v ac[NA];
 #pragma unroll
-    for (int q = 0; q < NA; ++q) ac[q] = a0[q] + a1[q];
+    for (int q = 0; q < NA; ++q) ac[q] = MODE == 0 ? a0[q] + a1[q] : (MODE == 1 ? a0[q] : a1[q]);
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
       for (int q = 0; q < NA; ++q) ac_[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[q][e], bb[e], ac_[q], 0, 0, 0);
   };
-  if (total > 0) {
-    f32x4v x0[NA], x1[NA], y0[NA], y1[NA];
-    float bx[4], by[4];
-    load(x0, x1, bx);
-    for (int st = 0; st < total; st += 2) {
-      const bool two = st + 1 < total;
-      if (two) load(y0, y1, by);
-      compute(x0, x1, bx);
-      if (st + 2 < total) load(x0, x1, bx);
-      if (two) compute(y0, y1, by);
-    }
+  f32x4v x0[NA], x1[NA], y0[NA], y1[NA];
+  float bx[4], by[4];
+  load(x0, x1, bx);
+  int st = 0;
+  for (; st + 1 < total; st += 2) {
+    load(y0, y1, by);  // step st + 1
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the matrix work they overlap
+    compute(x0, x1, bx);
+    load(x0, x1, bx);  // step st + 2 (a repeat of the last step when st + 2 == total)
+    __builtin_amdgcn_sched_barrier(0);
+    compute(y0, y1, by);
   }
+  if (st < total) compute(x0, x1, bx);
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = ac_[q];
 }
@@ -170,6 +195,51 @@ __device__ __forceinline__ DataRect clip_rect(const DataRect& d, int4 bx) {
 }
 
 __device__ __forceinline__ int floor_div16(int a) { return a >= 0 ? a / 16 : -((15 - a) / 16); }
+
+// CONV_IN_BOX: the offset (gi, gj), each in [gmin, 0], of a region's tile grid that
+// minimises its matrix steps for the box [u0, u1) x [v0, v1).  Only a region whose
+// tiles reach past the plane has slack (the plane's last region along each
+// axis): its grid may start up to 15 rows or columns early, the rows and columns
+// before the region's first one being left to the previous region or lying
+// outside the plane.  The step count is separable, (sum over tile rows of the tap
+// rows in reach) x (sum over tile columns of the super-steps in reach), so each
+// offset is chosen alone: lanes 0-15 try the row offsets 0, -1, ..., -15 and lanes
+// 16-31 the column offsets; ties go to the offset nearest 0.
+__device__ __forceinline__ int2 grid_offsets(const Geo<float>& g, const RegionShape& rs, int I0, int J0, int SS,
+                                             int4 bx, int lane) {
+  const int h = g.h;
+  const bool col = lane >= 16;
+  const int cand = lane & 15;
+  const int N = col ? g.Nv : g.Nu, X0 = col ? J0 : I0, T = col ? rs.TJ : rs.TI;
+  const int lo = max(col ? bx.z : bx.x, 0), hi = min(col ? bx.w : bx.y, N);
+  const int gmin = max(-15, min(0, (N - X0) - MT * T));
+  const int end = min(N, X0 + MT * T);
+  int key = 0x7fffffff;
+  if (lane < 32 && -cand >= gmin) {
+    int cost = 0;
+    for (int t = 0; t < RMAX; ++t) {
+      const int X = X0 - cand + MT * t;
+      if (t >= T || X >= end || hi <= lo) continue;
+      if (col) {
+        const int cb = X - h, ca = max(cb, lo), cz = min(cb + 16 * SS - 1, hi - 1);
+        if (cz >= ca) {
+          const int o = ((ca - cb) >> 2) << 2;
+          cost += (cz - cb - o + 16) >> 4;
+        }
+      } else {
+        const int a1 = max(0, lo - X - 15), b1 = min(h, hi - X - 1);
+        const int a2 = max(0, X - hi + 1), b2 = min(h, X + 15 - lo);
+        const int n1 = a1 <= b1 ? b1 - a1 + 1 : 0, n2 = a2 <= b2 ? b2 - a2 + 1 : 0;
+        const int ov = n1 > 0 && n2 > 0 ? max(0, min(b1, b2) - max(a1, a2) + 1) : 0;
+        cost += n1 + n2 - ov;
+      }
+    }
+    key = (cost << 4) | cand;
+  }
+#pragma unroll
+  for (int sh = 8; sh >= 1; sh >>= 1) key = min(key, __shfl_xor(key, sh));
+  return int2{-(__builtin_amdgcn_readlane(key, 0) & 15), -(__builtin_amdgcn_readlane(key, 16) & 15)};
+}
 
 // Support of the convolution (box: per control point [u0, u1) x [v0, v1), the
 // aperture's rectangle outside which the fluence and its derivatives vanish):
@@ -198,6 +268,9 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
   float* kx = lds + rows * pitch;  // (h + 1) x E, zero outside |q| <= h, row 0 halved
   float* kq = kx + (h + 1) * E;    // (h + 1) x (h + 1) unique taps
   int* grab = reinterpret_cast<int*>(kq + (h + 1) * (h + 1));  // next tile to take (CONV_IN_BOX)
+  // CONV_IN_BOX: per tile {a1, b1, a2, b2, column offset o, super-steps nu, steps, -}
+  int* trange = grab + 4;
+  int* order = trange + 8 * RMAX * RMAX;  // CONV_IN_BOX: tiles by decreasing step count
   const int nreg = rs.regions_i * rs.regions_j;
   const int region = blockIdx.x % nreg;
   const int I0 = (region / rs.regions_j) * rs.TI * MT;
@@ -205,6 +278,7 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
   const size_t plane = (size_t)g.Nu * g.Nv;
   const int tid = threadIdx.x;
   const DataRect dr = data_rect(g, I0, J0, MT * rs.TI, MT * rs.TJ);
+  const int n_tiles = rs.TI * rs.TJ;
 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int m = lane & 15, kk = lane >> 4;
@@ -222,15 +296,22 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
   const float* bbase = kx + 4 * kk + 15 - m;
   const int off = h + 15;
   auto a_of = [&](int ti, int tj) { return tile + (MT * ti + m + h) * pitch + MT * tj + 4 * kk; };
-  auto rect_of = [&](int item) {
-    if (SUP == CONV_IN_BOX) return clip_rect(dr, box[(item / nreg) / g.Nk]);
+  // an item's data rectangle and, with CONV_IN_BOX, its tile-grid offset
+  auto rect_of = [&](int item, int2& go) {
+    go = int2{0, 0};
+    if (SUP == CONV_IN_BOX) {
+      const int4 bx = box[(item / nreg) / g.Nk];
+      go = grid_offsets(g, rs, I0, J0, SS, bx, lane);
+      return clip_rect(data_rect(g, I0 + go.x, J0 + go.y, MT * rs.TI, MT * rs.TJ), bx);
+    }
     return dr;
   };
 
   zero_lds(tile, rows * pitch, tid, NT);
   float buf[PF];
   int it = blockIdx.x;
-  DataRect cur = rect_of(it < n_items ? it : 0);
+  int2 cur_go, nxt_go;
+  DataRect cur = rect_of(it < n_items ? it : 0, cur_go);
   DataRect prev = cur;
   prev.nr = 0;
   prev.nc = 1;
@@ -243,6 +324,37 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     put_rect<PF>(src, g.Nv, cur, pitch, tid, NT, buf, tile);
     if (SUP == CONV_IN_BOX) {
       if (tid == 0) *grab = 0;
+      if (tid < n_tiles) {
+        // the steps of tile tid that meet the input rectangle: tap rows p whose row
+        // I + p .. I + p + 15 (plus side, p in [a1, b1]) or I - p .. I - p + 15 (minus
+        // side, p in [a2, b2]) meets [r0, r1), and nu super-steps of 16 input columns
+        // starting at column J - h + o (o a multiple of 4, so the 16-byte reads stay
+        // aligned) that cover the rectangle's columns in reach
+        const int ti = tid / rs.TJ, tj = tid - (tid / rs.TJ) * rs.TJ;
+        const int I = I0 + cur_go.x + MT * ti, J = J0 + cur_go.y + MT * tj;
+        const int r0 = cur.r0, r1 = cur.r0 + cur.nr;
+        const int a1 = max(0, r0 - I - 15), b1 = min(h, r1 - I - 1);
+        const int a2 = max(0, I - r1 + 1), b2 = min(h, I + 15 - r0);
+        const int cb = J - h;
+        const int ca = max(cb, cur.c0), cz = min(cb + 16 * SS - 1, cur.c0 + cur.nc - 1);
+        int o = 0, nu = 0;
+        if (cur.nr > 0 && cz >= ca && I < g.Nu && J < g.Nv) {
+          o = ((ca - cb) >> 2) << 2;
+          nu = (cz - cb - o + 16) >> 4;
+          o = min(o, 16 * (SS - nu));
+        }
+        // tap rows in the union of the two intervals
+        const int n1 = a1 <= b1 ? b1 - a1 + 1 : 0, n2 = a2 <= b2 ? b2 - a2 + 1 : 0;
+        const int lo = max(a1, a2), hi_ = min(b1, b2), both = n1 > 0 && n2 > 0 && lo <= hi_ ? hi_ - lo + 1 : 0;
+        int* tr = trange + 8 * tid;
+        tr[0] = a1;
+        tr[1] = nu > 0 ? b1 : a1 - 1;
+        tr[2] = a2;
+        tr[3] = nu > 0 ? b2 : a2 - 1;
+        tr[4] = o;
+        tr[5] = nu;
+        tr[6] = (n1 + n2 - both) * nu;
+      }
       // clear what the previous item wrote outside this item's rectangle
       for (int idx = tid; idx < prev.nr * prev.nc; idx += NT) {
         const int r = idx / prev.nc, c = idx - r * prev.nc;
@@ -253,6 +365,17 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     }
     unique_taps(g, k, zca[bk], kq, tid, NT);
     __syncthreads();
+    if (SUP == CONV_IN_BOX && tid < n_tiles) {
+      // rank by step count, largest first (ties by index), so the last tiles taken are short
+      auto work = [&](int t) { return trange[8 * t + 6]; };
+      const int w = work(tid);
+      int rank = 0;
+      for (int t = 0; t < n_tiles; ++t) {
+        const int v = work(t);
+        rank += (v > w || (v == w && t < tid)) ? 1 : 0;
+      }
+      order[rank] = tid;
+    }
     for (int idx = tid; idx < (h + 1) * E; idx += NT) {
       int p = idx / E, c = idx - p * E;
       int q = c - off;
@@ -264,46 +387,56 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     // next item's input, in flight while this item's matrix work runs
     const int nx = it + gridDim.x;
     DataRect nxt = cur;
+    nxt_go = cur_go;
     if (nx < n_items) {
-      nxt = rect_of(nx);
+      nxt = rect_of(nx, nxt_go);
       fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, nxt, tid, NT, buf);
     }
     float* dst = out + (size_t)bk * plane;
 
     if (SUP == CONV_IN_BOX) {
-      // Tiles are taken one at a time from a shared counter (row-major order), each
-      // with only the tap rows and super-steps that reach the input rectangle, so
+      // Tiles are taken one at a time from a shared counter, longest first, each with
+      // only the tap rows and super-steps that reach the input rectangle, so
       // wavefronts whose tiles need little work take more tiles.  Every tile is
       // computed by one wavefront in a fixed step order.
-      const int r0 = cur.r0, r1 = cur.r0 + cur.nr, c0 = cur.c0, c1 = cur.c0 + cur.nc;
-      const int n_tiles = rs.TI * rs.TJ;
       while (true) {
         int t = 0;
         if (lane == 0) t = atomicAdd(grab, 1);
         t = __builtin_amdgcn_readfirstlane(t);
         if (t >= n_tiles) break;
+        t = __builtin_amdgcn_readfirstlane(order[t]);
         const int ti = t / rs.TJ, tj = t - (t / rs.TJ) * rs.TJ;
-        const int I = I0 + MT * ti, J = J0 + MT * tj;
+        const int I = I0 + cur_go.x + MT * ti, J = J0 + cur_go.y + MT * tj;
         if (I >= g.Nu || J >= g.Nv) continue;
-        const int cb = J - h;
-        const int ua = max(0, floor_div16(c0 - cb)), ub = min(SS - 1, floor_div16(c1 - 1 - cb));
-        // rows I + p .. I + p + 15 or I - p .. I - p + 15 meet [r0, r1)
-        int pa = h + 1, pb = -1;
-        const int a1 = max(0, r0 - I - 15), b1 = min(h, r1 - I - 1);
-        if (a1 <= b1) {
-          pa = min(pa, a1);
-          pb = max(pb, b1);
-        }
-        const int a2 = max(0, I - r1 + 1), b2 = min(h, I + 15 - r0);
-        if (a2 <= b2) {
-          pa = min(pa, a2);
-          pb = max(pb, b2);
-        }
-        if (cur.nr == 0) pb = pa - 1;
-        const float* ab[1] = {a_of(ti, tj)};
+        const int* tr = trange + 8 * t;
+        const int a1 = __builtin_amdgcn_readfirstlane(tr[0]), b1 = __builtin_amdgcn_readfirstlane(tr[1]);
+        const int a2 = __builtin_amdgcn_readfirstlane(tr[2]), b2 = __builtin_amdgcn_readfirstlane(tr[3]);
+        const int o = __builtin_amdgcn_readfirstlane(tr[4]), nu = __builtin_amdgcn_readfirstlane(tr[5]);
+        const float* ab[1] = {a_of(ti, tj) + o};
+        const float* bb = bbase + o;
         f32x4 acc[1] = {f32x4{0.f, 0.f, 0.f, 0.f}};
-        f32_steps<1>(ab, bbase, pitch, E, pa, pb, ua, ub, acc);
-        store_tile_at(g, I, J, lane, acc[0], dst);
+        if (kFoldSegments) {
+          // segments of p in increasing order, each loading only the sides it needs
+          int p = min(a1 <= b1 ? a1 : h + 1, a2 <= b2 ? a2 : h + 1);
+          const int p_top = max(a1 <= b1 ? b1 : -1, a2 <= b2 ? b2 : -1);
+          while (p <= p_top) {
+            const bool plus = a1 <= p && p <= b1, minus = a2 <= p && p <= b2;
+            int e = p_top;  // the segment ends before the next interval boundary
+            if (plus) e = min(e, b1);
+            else if (a1 > p && a1 <= b1) e = min(e, a1 - 1);
+            if (minus) e = min(e, b2);
+            else if (a2 > p && a2 <= b2) e = min(e, a2 - 1);
+            if (plus && minus) f32_steps<1, 0>(ab, bb, pitch, E, p, e, 0, nu - 1, acc);
+            else if (plus) f32_steps<1, 1>(ab, bb, pitch, E, p, e, 0, nu - 1, acc);
+            else if (minus) f32_steps<1, 2>(ab, bb, pitch, E, p, e, 0, nu - 1, acc);
+            p = e + 1;
+          }
+        } else {
+          const int pa = min(a1 <= b1 ? a1 : h + 1, a2 <= b2 ? a2 : h + 1);
+          const int pb = max(a1 <= b1 ? b1 : -1, a2 <= b2 ? b2 : -1);
+          f32_steps<1>(ab, bb, pitch, E, pa, pb, 0, nu - 1, acc);
+        }
+        store_tile_from(g, I, J, I0, J0, lane, acc[0], dst);
       }
     } else {
       const float* ab[TPW];
@@ -319,6 +452,7 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     }
     prev = cur;
     cur = nxt;
+    cur_go = nxt_go;
     __syncthreads();  // the LDS image and taps are rewritten for the next item
   }
 }
@@ -778,6 +912,9 @@ static hipError_t launch_f32_sup(const Geo<float>& g, const RegionShape& rs, con
   if (tiles <= 8) return launch_f32_cfg<8, 1, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
   if (tiles <= 16) return launch_f32_cfg<8, 2, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
   if (tiles <= 24) return launch_f32_cfg<8, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
+  // CONV_IN_BOX: tiles are taken dynamically, so more wavefronts than tiles / 3 only
+  // add latency hiding; CONV_DENSE: three fixed tiles per wavefront
+  if (SUP == CONV_IN_BOX) return launch_f32_cfg<16, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
   return launch_f32_cfg<12, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
 }
 
@@ -826,7 +963,7 @@ hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, con
   for (int rmax = RMAX; rmax >= 1; --rmax) {  // the largest region whose LDS image fits
     rs = region_shape(g.Nu, g.Nv, rmax);
     fs = f32_shape(g.h, rs);
-    lds = adj ? f32_adj_lds(g.h, fs, 12) : f32_lds(g.h, fs);
+    lds = adj ? f32_adj_lds(g.h, fs, 12) : f32_lds(g.h, fs) + (bx && support == CONV_IN_BOX ? kBoxTileLds : 0);
     if (lds <= LDS_MAX) break;
   }
   if (adj) return launch_f32_adj(g, rs, fs, nb, bx, z, in, out, s);
