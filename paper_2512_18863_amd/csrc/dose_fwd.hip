@@ -470,77 +470,155 @@ hipError_t launch_conv_direct(const Geo<T>& g, int nb, const T* z, const T* in, 
 // Workgroups are numbered so that each of the eight XCDs (which receive
 // workgroups round robin) walks a contiguous range of y slabs: neighbouring voxel
 // columns read the same beam-frame columns, and they then share one L2.
+// The part of one control point's trilinear lookup that depends only on the
+// voxel column (x, y): the beam-frame plane k and row i of the column (the same
+// for every z), the four (k, i) corner weights with their in-grid masks and the
+// corners' element offsets within the control point's beam-frame volume, and
+// SAD / d, which scales z into the lateral coordinate j.
+template <typename T>
+struct GatherCol {
+  T q;
+  T w[4];     // corner (dk, di) = (c >> 1, c & 1): in-grid mask x (1 - wk or wk) x (1 - wi or wi)
+  int off[4]; // element offset of the corner's row (clamped into the grid)
+};
+
+constexpr int GATHER_CHUNK = 64;  // control points whose column terms sit in LDS at once
+
+// A wavefront-uniform value read from LDS, moved to scalar registers (so that
+// addresses built from it use the scalar base of a global load).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL)), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// dose(x, y, z) += sum_b MU_b trilinear(Dfan_b at the voxel's beam-frame position).
+// A block covers 64 consecutive z of four voxel columns (one wavefront per
+// column); the column terms of each control point are computed once per block
+// (into LDS) instead of once per voxel, and each lane does only the z-dependent
+// part: the lateral coordinate j, the eight loads and the interpolation.  The
+// arithmetic of every term is that of a direct per-voxel evaluation (same
+// operations in the same order), and the terms are summed in control-point order
+// with a compensated sum.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather(Geo<T> g, int nb, int first, int last, int zc, int xc,
                                                 const T* __restrict__ frame, const T* __restrict__ mu,
                                                 const T* __restrict__ Dfan, T* __restrict__ dose,
                                                 T* __restrict__ comp) {
+  __shared__ GatherCol<T> cols[4][GATHER_CHUNK];
   const int nblk = zc * xc * g.ny;
   const int per_xcd = (nblk + 7) / 8;
   const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (w >= nblk) return;
+  if (w >= nblk) return;  // uniform over the block
   const int zq = w % zc, xq = (w / zc) % xc;
-  int z = zq * 64 + (threadIdx.x & 63);
-  int x = xq * 4 + (threadIdx.x >> 6);
-  int y = w / (zc * xc);
-  if (z >= g.nz || x >= g.nx) return;
-  size_t vox = ((size_t)z * g.ny + y) * g.nx + x;
-  T tx = g.rel_ox + T(x) * g.sx, ty = g.rel_oy + T(y) * g.sy, tz = g.rel_oz + T(z) * g.sz;
+  const int wave = threadIdx.x >> 6;
+  const int z = zq * 64 + (threadIdx.x & 63);
+  const int x = xq * 4 + wave;
+  const int y = w / (zc * xc);
+  const bool active = z < g.nz && x < g.nx;
+  const size_t vox = ((size_t)z * g.ny + y) * g.nx + x;
+  const T tz = g.rel_oz + T(z) * g.sz, ty = g.rel_oy + T(y) * g.sy;
   T s = T(0), c = T(0);
-  if (!first) {
+  if (active && !first) {
     s = dose[vox];
     c = comp[vox];
   }
   const int plane = g.Nu * g.Nv;
-  // Branch free per control point (clamped addresses, masked weights) and
-  // unrolled, so the loads of several control points are in flight at once; the
-  // terms and the compensated sum keep the order of a masked loop.
-#pragma unroll 4
-  for (int b = 0; b < nb; ++b) {
-    T sn = frame[2 * b], cs = frame[2 * b + 1];
-    FanIdx<T> f = voxel_to_fan(g, sn, cs, tx, ty, tz);
-    T fk = dfloor(f.k), fi = dfloor(f.i), fj = dfloor(f.j);
-    // (bitwise & keeps the flags branch free)
-    const bool inside = (fk >= T(-1)) & (fk < T(g.Nk)) & (fi >= T(-1)) & (fi < T(g.Nu)) & (fj >= T(-1)) &
-                        (fj < T(g.Nv));
-    int k0 = inside ? (int)fk : 0, i0 = inside ? (int)fi : 0, j0 = inside ? (int)fj : 0;
-    T wk = f.k - fk, wi = f.i - fi, wj = f.j - fj;
-    const T* base = Dfan + (size_t)b * g.Nk * plane;
-    const int ja = max(j0, 0), jb = min(j0 + 1, g.Nv - 1);
-    const bool jin0 = j0 >= 0, jin1 = j0 + 1 < g.Nv;
-    T lo[2][2], hi[2][2];
-    bool ok[2][2];
+  const size_t cp_elems = (size_t)g.Nk * plane;
+  for (int b0 = 0; b0 < nb; b0 += GATHER_CHUNK) {
+    const int nbc = min(GATHER_CHUNK, nb - b0);
+    __syncthreads();  // the previous chunk's column terms are no longer read
+    for (int e = threadIdx.x; e < 4 * nbc; e += 256) {
+      const int cw = e / nbc, bb = e - cw * nbc, b = b0 + bb;
+      const T tx = g.rel_ox + T(xq * 4 + cw) * g.sx;
+      const T sn = frame[2 * b], cs = frame[2 * b + 1];
+      // voxel_to_fan without the z part
+      const T ev = -sn * tx + cs * ty;
+      const T q = T(1) / (T(1) + ev * g.inv_sad);
+      const T u = (cs * tx + sn * ty) * q;
+      const T fkv = (ev - g.e0) * g.inv_dstep, fiv = u * g.inv_lat + g.cu;
+      const T fk = dfloor(fkv), fi = dfloor(fiv);
+      const bool in_ki = (fk >= T(-1)) & (fk < T(g.Nk)) & (fi >= T(-1)) & (fi < T(g.Nu));
+      const int k0 = in_ki ? (int)fk : 0, i0 = in_ki ? (int)fi : 0;
+      const T wk = fkv - fk, wi = fiv - fi;
+      GatherCol<T> col;
+      col.q = q;
 #pragma unroll
-    for (int dk = 0; dk < 2; ++dk)
+      for (int dk = 0; dk < 2; ++dk)
 #pragma unroll
-      for (int di = 0; di < 2; ++di) {
-        const int kk = k0 + dk, ii = i0 + di;
-        ok[dk][di] = (kk >= 0) & (kk < g.Nk) & (ii >= 0) & (ii < g.Nu);
-        const int ck = min(max(kk, 0), g.Nk - 1), ci = min(max(ii, 0), g.Nu - 1);
-        const T* colp = base + (size_t)ck * plane + (size_t)ci * g.Nv;
-        lo[dk][di] = colp[ja];
-        hi[dk][di] = colp[jb];
+        for (int di = 0; di < 2; ++di) {
+          const int kk = k0 + dk, ii = i0 + di;
+          const bool ok = in_ki & (kk >= 0) & (kk < g.Nk) & (ii >= 0) & (ii < g.Nu);
+          const T wkk = dk ? wk : T(1) - wk, wii = di ? wi : T(1) - wi;
+          col.w[2 * dk + di] = T(ok) * (wkk * wii);
+          col.off[2 * dk + di] = min(max(kk, 0), g.Nk - 1) * plane + min(max(ii, 0), g.Nu - 1) * g.Nv;
+        }
+      cols[cw][bb] = col;
+    }
+    __syncthreads();
+    if (active) {
+      // the eight loads of a control point, then its term (in control-point order);
+      // groups of four control points keep 32 loads in flight
+      struct Term {
+        T lo[4], hi[4], wj, jin0, jin1, in_j;
+      };
+      auto fetch = [&](int bb, Term& tm) {
+        const GatherCol<T>& col = cols[wave][bb];
+        const T q = uniform(col.q);
+        const T fjv = tz * q * g.inv_lat + g.cv;
+        const T fj = dfloor(fjv);
+        const bool in_j = (fj >= T(-1)) & (fj < T(g.Nv));
+        const int j0 = in_j ? (int)fj : 0;
+        tm.wj = fjv - fj;
+        tm.in_j = T(in_j);
+        const int ja = max(j0, 0), jb = min(j0 + 1, g.Nv - 1);
+        tm.jin0 = T(j0 >= 0);
+        tm.jin1 = T(j0 + 1 < g.Nv);
+        const T* base = Dfan + (size_t)(b0 + bb) * cp_elems;
+        // 32-bit unsigned byte offsets from a scalar row address (the load's scalar base)
+        const unsigned oa = (unsigned)ja * (unsigned)sizeof(T), ob = (unsigned)jb * (unsigned)sizeof(T);
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const char* row = reinterpret_cast<const char*>(base + uniform(col.off[cc]));
+          tm.lo[cc] = *reinterpret_cast<const T*>(row + oa);
+          tm.hi[cc] = *reinterpret_cast<const T*>(row + ob);
+        }
+      };
+      auto add = [&](int bb, const Term& tm) {
+        const GatherCol<T>& col = cols[wave][bb];
+        T acc = T(0);
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const T a = tm.jin0 * tm.lo[cc];
+          const T bv = tm.jin1 * tm.hi[cc];
+          acc += uniform(col.w[cc]) * (a + tm.wj * (bv - a));
+        }
+        // outside the beam-frame grid the term is +0, which leaves s and c unchanged
+        const T val = tm.in_j * (mu[b0 + bb] * acc);
+        const T t = s + val;
+        c += fabs(s) >= fabs(val) ? (s - t) + val : (val - t) + s;
+        s = t;
+      };
+      int bb = 0;
+      for (; bb + 4 <= nbc; bb += 4) {
+        Term tm[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) fetch(bb + u, tm[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add(bb + u, tm[u]);
       }
-    T acc = T(0);
-#pragma unroll
-    for (int dk = 0; dk < 2; ++dk) {
-      const T wkk = dk ? wk : T(1) - wk;
-#pragma unroll
-      for (int di = 0; di < 2; ++di) {
-        const T wii = di ? wi : T(1) - wi;
-        // masks as 0/1 factors (not selects), so the compiler keeps every load
-        // unconditional and can issue them early; the clamped corners hold finite data
-        const T a = T(jin0) * lo[dk][di];
-        const T bv = T(jin1) * hi[dk][di];
-        acc += T(ok[dk][di]) * (wkk * wii * (a + wj * (bv - a)));
+      for (; bb < nbc; ++bb) {
+        Term tm;
+        fetch(bb, tm);
+        add(bb, tm);
       }
     }
-    // outside the beam-frame grid the term is +0, which leaves s and c unchanged
-    const T val = T(inside) * (mu[b] * acc);
-    const T t = s + val;
-    c += fabs(s) >= fabs(val) ? (s - t) + val : (val - t) + s;
-    s = t;
   }
+  if (!active) return;
   if (last) {
     dose[vox] = g.calib * (s + c);
   } else {
@@ -555,6 +633,7 @@ hipError_t launch_gather(const Geo<T>& g, int nb, int first, int last, const T* 
   const int zc = (g.nz + 63) / 64, xc = (g.nx + 3) / 4;
   const long nblk = (long)zc * xc * g.ny;
   if (nblk > 0x7ffffff0L) return hipErrorInvalidConfiguration;
+  if ((long)g.Nk * g.Nu * g.Nv > 0x7fffffffL) return hipErrorInvalidConfiguration;  // 32-bit corner offsets
   const int grid = (int)((nblk + 7) / 8 * 8);
   hipLaunchKernelGGL(k_gather<T>, dim3(grid), dim3(256), 0, s, g, nb, first, last, zc, xc, frame, mu, Dfan, dose,
                      comp);
