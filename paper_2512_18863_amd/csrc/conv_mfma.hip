@@ -609,8 +609,15 @@ __host__ __device__ static size_t bf16_tile_bytes(const BF16Shape& bs) {
   return ((size_t)bs.rows * bs.pitch * 2 + 15) & ~(size_t)15;
 }
 __host__ __device__ static size_t bf16_copy_bytes(int h, const BF16Shape& bs) { return (size_t)(h + 1) * 8 * bs.CL * 2; }
+// One padded BF16 tap row per p: positions x = -8 .. CL + 7 of the extended row
+// (x = q + h + 31) at index x + 8, zero outside |q| <= h; the shifted copies are
+// cut from it.
+__host__ __device__ static int bf16_ext_len(const BF16Shape& bs) { return bs.CL + 16; }
+__host__ __device__ static size_t bf16_kq_end(int h, const BF16Shape& bs) {
+  return (bf16_copy_bytes(h, bs) + sizeof(float) * (size_t)(h + 1) * (h + 1) + 15) & ~(size_t)15;
+}
 __host__ __device__ static size_t bf16_taps_bytes(int h, const BF16Shape& bs) {
-  return bf16_copy_bytes(h, bs) + sizeof(float) * (size_t)(h + 1) * (h + 1);
+  return bf16_kq_end(h, bs) + (size_t)(h + 1) * bf16_ext_len(bs) * 2;
 }
 // one quarter's partial sums (all strips and tiles of the region)
 __host__ __device__ static size_t bf16_part_bytes(const BF16Shape& bs) {
@@ -643,6 +650,7 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
   unsigned char* taps_area = smem_raw + bf16_tile_bytes(bs);
   __bf16* bcopy = reinterpret_cast<__bf16*>(taps_area);  // [h+1][8][CL]
   float* kq = reinterpret_cast<float*>(taps_area + bf16_copy_bytes(h, bs));
+  unsigned short* ext = reinterpret_cast<unsigned short*>(taps_area + bf16_kq_end(h, bs));  // [h+1][CL+16]
   float* part = reinterpret_cast<float*>(taps_area);
   const int nreg = bs.regions_i * bs.regions_j;
   const int region = blockIdx.x % nreg;
@@ -738,23 +746,49 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
     }
     unique_taps(g, k, zca[bk], kq, tid, NT);
     __syncthreads();
-    // Extended tap row x (x = q + h + 31) stored in copy r at position x + sigma_r,
-    // sigma_r = (8 - r) % 8, so that a run starting at x with x % 8 == r is aligned.
-    // (written as bf16 pairs: CL is even)
-    for (int row = wave; row < (h + 1) * 8; row += NW) {
-      const int p = row >> 3, r = row & 7;
-      unsigned* dst = reinterpret_cast<unsigned*>(bcopy + (size_t)row * CL);
-      for (int y2 = lane; 2 * y2 < CL; y2 += 64) {
+    // the padded BF16 row of each tap row (bf16 pairs)
+    {
+      const int XE = bf16_ext_len(bs), XE2 = XE / 2;
+      for (int d = tid; d < (h + 1) * XE2; d += NT) {
+        const int p = d / XE2, e2 = d - p * XE2;
         unsigned packed = 0;
 #pragma unroll
         for (int hlf = 0; hlf < 2; ++hlf) {
-          const int x = 2 * y2 + hlf - ((8 - r) & 7);
+          const int x = 2 * e2 + hlf - 8;
           const int q = x - (h + 31);
           const float v = (x >= 0 && q >= -h && q <= h) ? kq[p * (h + 1) + (q < 0 ? -q : q)] : 0.f;
           const __bf16 bv = (__bf16)v;
           packed |= (unsigned)(*reinterpret_cast<const unsigned short*>(&bv)) << (16 * hlf);
         }
-        dst[y2] = packed;
+        reinterpret_cast<unsigned*>(ext)[d] = packed;
+      }
+    }
+    __syncthreads();
+    // Extended tap row x stored in copy r at position x + sigma_r, sigma_r =
+    // (8 - r) % 8, so that a run starting at x with x % 8 == r is aligned.  A lane
+    // writes 8 positions (16 bytes) of one copy: padded-row entries e0 .. e0 + 7,
+    // e0 = 8 g - sigma_r + 8, funnel-shifted out of five aligned pairs.
+    {
+      const int XE = bf16_ext_len(bs);
+      const int lpr = CL / 8, rpi = 64 / lpr;  // lanes per copy row, copy rows per wavefront pass
+      const int rsub = lane / lpr, g8 = lane - rsub * lpr;
+      for (int row0 = wave * rpi; row0 < (h + 1) * 8; row0 += NW * rpi) {
+        const int row = row0 + rsub;
+        if (rsub < rpi && row < (h + 1) * 8) {
+          const int p = row >> 3, r = row & 7;
+          const int e0 = 8 * g8 - ((8 - r) & 7) + 8;
+          const unsigned* w = reinterpret_cast<const unsigned*>(ext + (size_t)p * XE) + (e0 >> 1);
+          const unsigned sh = 2u * (unsigned)(e0 & 1);
+          unsigned v[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) v[c] = w[c];
+          uint4 o;
+          o.x = __builtin_amdgcn_alignbyte(v[1], v[0], sh);
+          o.y = __builtin_amdgcn_alignbyte(v[2], v[1], sh);
+          o.z = __builtin_amdgcn_alignbyte(v[3], v[2], sh);
+          o.w = __builtin_amdgcn_alignbyte(v[4], v[3], sh);
+          *reinterpret_cast<uint4*>(bcopy + (size_t)row * CL + 8 * g8) = o;
+        }
       }
     }
     __syncthreads();
