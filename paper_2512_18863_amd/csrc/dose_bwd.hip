@@ -364,19 +364,21 @@ __global__ void __launch_bounds__(256) k_backproject_reg(Geo<T> g, int nb, int t
         const int j = 64 * s + lane;
         part[s] = j < g.Nv ? z_sum_tent(g, j, A, B, invB, [&](int z) { return gcol[z]; }) : T(0);
       }
-      T wK[BR_TK], wI[BR_TI];
+      // only the (at most) 2 x 2 block columns the member touches: the member's
+      // corner (ck, ci) is wavefront-uniform, so these are scalar branches
+      const int ak = ck - k0, ai = ci - i0;
 #pragma unroll
-      for (int a = 0; a < BR_TK; ++a) wK[a] = k0 + a == ck ? T(1) - cwk : (k0 + a == ck + 1 ? cwk : T(0));
-#pragma unroll
-      for (int c = 0; c < BR_TI; ++c) wI[c] = i0 + c == ci ? T(1) - cwi : (i0 + c == ci + 1 ? cwi : T(0));
-#pragma unroll
-      for (int a = 0; a < BR_TK; ++a)
+      for (int a = 0; a < BR_TK; ++a) {
+        if (a != ak && a != ak + 1) continue;
+        const T wkk = a == ak ? T(1) - cwk : cwk;
 #pragma unroll
         for (int c = 0; c < BR_TI; ++c) {
-          const T w2 = wK[a] * wI[c];
+          if (c != ai && c != ai + 1) continue;
+          const T w2 = wkk * (c == ai ? T(1) - cwi : cwi);
 #pragma unroll
           for (int s = 0; s < JS; ++s) acc[a][c][s] += w2 * part[s];
         }
+      }
     }
   }
   const size_t plane = (size_t)g.Nu * g.Nv;
