@@ -9,10 +9,22 @@
 namespace pdrt {
 
 // Unique taps K[p][q], 0 <= p, q <= h, of the plane into `kq` ((h+1) x (h+1)).
+// The kernel is radial (K[p][q] = K[q][p], the same expression of p^2 + q^2), so
+// only the pairs p <= q are evaluated, numbered column by column (pair t is
+// q = floor((sqrt(8t + 1) - 1) / 2), p = t - q (q + 1) / 2), and each is written
+// to both places.
 __device__ __forceinline__ void unique_taps(const Geo<float>& g, int k, float zk, float* kq, int tid, int nt) {
   TapParams<float> tp = tap_params(g, k, zk);
   const int h1 = g.h + 1;
-  for (int idx = tid; idx < h1 * h1; idx += nt) kq[idx] = tap_value(tp, idx / h1, idx % h1);
+  for (int t = tid; t < h1 * (h1 + 1) / 2; t += nt) {
+    int q = (int)((sqrtf((float)(8 * t + 1)) - 1.f) * 0.5f);
+    if ((q + 1) * (q + 2) / 2 <= t) ++q;
+    if (q * (q + 1) / 2 > t) --q;
+    const int p = t - q * (q + 1) / 2;
+    const float v = tap_value(tp, p, q);
+    kq[p * h1 + q] = v;
+    kq[q * h1 + p] = v;
+  }
 }
 
 // The part of the plane that a region's LDS image holds: rows [r0, r0 + nr) and

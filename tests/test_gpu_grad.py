@@ -79,6 +79,30 @@ def _aperture_case(fcorr=False, large=False):
     return c
 
 
+def test_aperture_positions_shift_the_tile_grid():
+    """n = 31 on a 71 x 71 plane (one convolution region with 25 pixels of slack):
+    six jaw openings at different positions and widths, so the forward picks a
+    different tile-grid offset and column alignment for each control point, and
+    the adjoint anchors its tiles at six different corners."""
+    from tests.test_gpu_parity import gpu_dose, oracle_dose, _rel_err
+    _say("jaw openings sliding across a 71 x 71 plane, n=31")
+    c = inputs.tiny_case(seed=38, n_cp=6, n_taps=31, shape=(20, 20, 14), spacing=3.0, field=60.0, n_leaf=12,
+                         leaf_width=10.0)
+    c.leaves = np.stack([np.stack([np.full(12, -45.0), np.full(12, 45.0)]) for _ in range(6)])
+    c.jaws = np.array([[-30.0 + 7.1 * b, -5.0 + 9.3 * b, -22.0 + 5.3 * b, 4.0 + 6.7 * b] for b in range(6)])
+    ref, _, _ = oracle_dose(c)
+    got, _ = gpu_dose(c)
+    err = _rel_err(got, ref)
+    _say("forward max|dD|/maxD = %.3e" % err)
+    assert err <= 1e-5
+    w = np.random.default_rng(38).uniform(size=c.shape)
+    gl, gj, gm, _ = _grads_gpu(c, w)
+    rl, rj, rm = _grads_oracle(c, w)
+    _check("leaves", gl, rl)
+    _check("jaws", gj, rj)
+    _check("mu", gm, rm)
+
+
 @pytest.mark.parametrize("fcorr,large", [(False, False), (True, False), (False, True)],
                          ids=["plain", "fluence-corrections", "large-plane"])
 def test_aperture_rectangles_forward_and_gradient(fcorr, large):
