@@ -142,40 +142,50 @@ __global__ void __launch_bounds__(256) k_conv3d_tiled(Vol v, ConvIO io) {
     for (int t = 0; t < NT; ++t) acc[r][t] = nf32x4{0.f, 0.f, 0.f, 0.f};
   __syncthreads();  // the tile is staged
   // K loop: A from the LDS tile, B (weights, shared by every workgroup and so
-  // cache resident) straight from global memory, one step ahead of its use
-  // (two operand sets, alternating)
+  // cache resident) straight from global memory.  Both operands of step t + 1
+  // are loaded while the matrix instructions of step t run (two operand sets,
+  // alternating).  The loads are unconditional (past the last step they read
+  // the last step's weights and a zero A), so the loop body is straight-line code
+  // and each step waits only for its own operands, not for the next step's loads.
   const int nsteps = io.Kp / 32;
+  const int last_kb = 32 * (nsteps - 1);
   const __bf16* wrow[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) wrow[t] = io.w + (size_t)(16 * t + m) * io.Kp + 8 * kq;
   int kb = 0;
-  auto load_b = [&](nbf16x8 (&b)[NT]) {
+  auto load = [&](nbf16x8 (&b)[NT], nbf16x8 (&a)[2]) {
+    const int kbc = kb < last_kb ? kb : last_kb;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) b[t] = *reinterpret_cast<const nbf16x8*>(wrow[t] + kb);
+    for (int t = 0; t < NT; ++t) b[t] = *reinterpret_cast<const nbf16x8*>(wrow[t] + kbc);
     kb += 32;
-  };
-  auto step = [&](const nbf16x8 (&b)[NT]) {
-    const int off = ((sgn * (kp.td - 1)) * CT_HH + sgn * (kp.th - 1)) * CT_HW + sgn * (kp.tw - 1);
-    const bool kin = kp.tap < 27;
-    nbf16x8 a[2];
+    const bool kin = kp.tap < 27;  // K padding past the 27 taps reads as zero
+    const int off = kin ? ((sgn * (kp.td - 1)) * CT_HH + sgn * (kp.th - 1)) * CT_HW + sgn * (kp.tw - 1) : 0;
+    const int ci = kin ? kp.ci : 0;
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
-      a[r] = kin ? *reinterpret_cast<const nbf16x8*>(tin + (size_t)(base[r] + off) * CinP + kp.ci) : nbf16x8{};
+    for (int r = 0; r < 2; ++r) {
+      const nbf16x8 x = *reinterpret_cast<const nbf16x8*>(tin + (size_t)(base[r] + off) * CinP + ci);
+      a[r] = kin ? x : nbf16x8{};
+    }
+    kp.advance(32, Cin);
+  };
+  auto compute = [&](const nbf16x8 (&b)[NT], const nbf16x8 (&a)[2]) {
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[t], acc[r][t], 0, 0, 0);
-    kp.advance(32, Cin);
   };
-  nbf16x8 bx[NT], by[NT];
-  load_b(bx);
-  for (int st = 0; st < nsteps; st += 2) {
-    const bool two = st + 1 < nsteps;
-    if (two) load_b(by);
-    step(bx);
-    if (st + 2 < nsteps) load_b(bx);
-    if (two) step(by);
+  nbf16x8 bx[NT], by[NT], ax[2], ay[2];
+  load(bx, ax);
+  int st = 0;
+  for (; st + 1 < nsteps; st += 2) {
+    load(by, ay);  // step st + 1
+    __builtin_amdgcn_sched_barrier(0);
+    compute(bx, ax);
+    load(bx, ax);  // step st + 2 (a repeat of the last weights when st + 2 == nsteps)
+    __builtin_amdgcn_sched_barrier(0);
+    compute(by, ay);
   }
+  if (st < nsteps) compute(bx, ax);
   // write: row r, lane (m = channel within the tile, kq) holds positions w0 + 4 kq + e
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
