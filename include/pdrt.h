@@ -309,13 +309,15 @@ int pdrt_net_scale(int32_t n, const float* dose, float* scale, int32_t* argmax, 
                    void* stream);
 /* out = a * scale[0] (inverse == 0) or a / scale[0] (inverse != 0); out may alias a. */
 int pdrt_scale_by(int32_t n, const float* a, const float* scale, int32_t inverse, float* out, void* stream);
-/* out = a + b over n bf16 elements (out may alias a or b). */
+/* out = a + b over n bf16 elements (out may alias a or b); a, b, out 16-byte
+ * aligned, else PDRT_E_INVALID. */
 int pdrt_add_bf16(size_t n, const void* a, const void* b, void* out, void* stream);
 /* 2 x 2 x 2 average pooling of the fine volume `fine` (even dims) and its
  * backward (backward != 0: x = gradient w.r.t. the pooled output, y = gradient
- * w.r.t. the fine input). */
+ * w.r.t. the fine input).  c a multiple of 8, x and y 16-byte aligned and
+ * D H W c < 2^31, else PDRT_E_INVALID. */
 int pdrt_pool2(const pdrt_vol* fine, int32_t c, const void* x, void* y, int32_t backward, void* stream);
-/* Nearest-neighbour x2 upsampling to `fine` and its backward. */
+/* Nearest-neighbour x2 upsampling to `fine` and its backward (same requirements). */
 int pdrt_upsample2(const pdrt_vol* fine, int32_t c, const void* x, void* y, int32_t backward, void* stream);
 /* Output head (FP32): pred = dose * scale + hb[0] + hw[0] . x, resid = hb[1] + hw[1] . x. */
 int pdrt_net_head(int32_t n, int32_t c, const void* x, const float* hw, const float* hb, const float* dose,

@@ -323,59 +323,69 @@ __global__ void k_net_input(int P, const float* __restrict__ dose, const float* 
 }
 
 // 2 x 2 x 2 average pooling (dims of the input; even).
+// Pooling, upsampling and their transposes move eight channels (16 bytes) per
+// thread with 32-bit index arithmetic; per channel the sums run in the same order
+// (the eight children in a = 0..7 order) as a one-channel-per-thread loop.
 __global__ void k_pool2(Vol v, int C, const __bf16* __restrict__ X, __bf16* __restrict__ Y) {
-  int Do = v.D / 2, Ho = v.H / 2, Wo = v.W / 2;
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t n = (size_t)Do * Ho * Wo * C;
-  if (i >= n) return;
-  int c = i % C;
-  size_t po = i / C;
-  int w = po % Wo, t = po / Wo, h = t % Ho, d = t / Ho;
-  float s = 0.f;
+  const int Do = v.D / 2, Ho = v.H / 2, Wo = v.W / 2, CG = C / 8;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Do * Ho * Wo * CG) return;
+  const int po = i / CG, c = 8 * (i - po * CG);
+  const int w = po % Wo, t = po / Wo, h = t % Ho, d = t / Ho;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int a = 0; a < 8; ++a) {
-    int dd = 2 * d + (a >> 2), hh = 2 * h + ((a >> 1) & 1), ww = 2 * w + (a & 1);
-    s += (float)X[(((size_t)dd * v.H + hh) * v.W + ww) * C + c];
+    const int dd = 2 * d + (a >> 2), hh = 2 * h + ((a >> 1) & 1), ww = 2 * w + (a & 1);
+    const nbf16x8 x = *reinterpret_cast<const nbf16x8*>(X + ((dd * v.H + hh) * v.W + ww) * C + c);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] += (float)x[e];
   }
-  Y[i] = (__bf16)(0.125f * s);
+  nbf16x8 y;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) y[e] = (__bf16)(0.125f * s[e]);
+  *reinterpret_cast<nbf16x8*>(Y + po * C + c) = y;
 }
 
 __global__ void k_pool2_bwd(Vol v, int C, const __bf16* __restrict__ dY, __bf16* __restrict__ dX) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t n = (size_t)v.D * v.H * v.W * C;
-  if (i >= n) return;
-  int c = i % C;
-  size_t p = i / C;
-  int w = p % v.W, t = p / v.W, h = t % v.H, d = t / v.H;
-  int Ho = v.H / 2, Wo = v.W / 2;
-  dX[i] = (__bf16)(0.125f * (float)dY[(((size_t)(d / 2) * Ho + h / 2) * Wo + w / 2) * C + c]);
+  const int CG = C / 8, Ho = v.H / 2, Wo = v.W / 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= v.D * v.H * v.W * CG) return;
+  const int p = i / CG, c = 8 * (i - p * CG);
+  const int w = p % v.W, t = p / v.W, h = t % v.H, d = t / v.H;
+  const nbf16x8 g = *reinterpret_cast<const nbf16x8*>(dY + (((d / 2) * Ho + h / 2) * Wo + w / 2) * C + c);
+  nbf16x8 o;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) o[e] = (__bf16)(0.125f * (float)g[e]);
+  *reinterpret_cast<nbf16x8*>(dX + p * C + c) = o;
 }
 
 // Nearest-neighbour upsampling x2 (dims of the output).
 __global__ void k_up2(Vol v, int C, const __bf16* __restrict__ X, __bf16* __restrict__ Y) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t n = (size_t)v.D * v.H * v.W * C;
-  if (i >= n) return;
-  int c = i % C;
-  size_t p = i / C;
-  int w = p % v.W, t = p / v.W, h = t % v.H, d = t / v.H;
-  int Hi = v.H / 2, Wi = v.W / 2;
-  Y[i] = X[(((size_t)(d / 2) * Hi + h / 2) * Wi + w / 2) * C + c];
+  const int CG = C / 8, Hi = v.H / 2, Wi = v.W / 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= v.D * v.H * v.W * CG) return;
+  const int p = i / CG, c = 8 * (i - p * CG);
+  const int w = p % v.W, t = p / v.W, h = t % v.H, d = t / v.H;
+  *reinterpret_cast<nbf16x8*>(Y + p * C + c) =
+      *reinterpret_cast<const nbf16x8*>(X + (((d / 2) * Hi + h / 2) * Wi + w / 2) * C + c);
 }
 
 __global__ void k_up2_bwd(Vol v, int C, const __bf16* __restrict__ dY, __bf16* __restrict__ dX) {
-  int Di = v.D / 2, Hi = v.H / 2, Wi = v.W / 2;
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t n = (size_t)Di * Hi * Wi * C;
-  if (i >= n) return;
-  int c = i % C;
-  size_t po = i / C;
-  int w = po % Wi, t = po / Wi, h = t % Hi, d = t / Hi;
-  float s = 0.f;
+  const int Di = v.D / 2, Hi = v.H / 2, Wi = v.W / 2, CG = C / 8;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Di * Hi * Wi * CG) return;
+  const int po = i / CG, c = 8 * (i - po * CG);
+  const int w = po % Wi, t = po / Wi, h = t % Hi, d = t / Hi;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int a = 0; a < 8; ++a) {
-    int dd = 2 * d + (a >> 2), hh = 2 * h + ((a >> 1) & 1), ww = 2 * w + (a & 1);
-    s += (float)dY[(((size_t)dd * v.H + hh) * v.W + ww) * C + c];
+    const int dd = 2 * d + (a >> 2), hh = 2 * h + ((a >> 1) & 1), ww = 2 * w + (a & 1);
+    const nbf16x8 g = *reinterpret_cast<const nbf16x8*>(dY + ((dd * v.H + hh) * v.W + ww) * C + c);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] += (float)g[e];
   }
-  dX[i] = (__bf16)s;
+  nbf16x8 o;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) o[e] = (__bf16)s[e];
+  *reinterpret_cast<nbf16x8*>(dX + po * C + c) = o;
 }
 
 // Head: 1 x 1 x 1 convolution C -> 2 in FP32, output 0 added to the input dose
@@ -552,10 +562,19 @@ __global__ void k_scale_by(int P, const float* __restrict__ a, const float* __re
 }
 
 // out = a + b (bf16), e.g. two gradient contributions of one activation.
+// out = a + b in groups of eight (16 bytes), the tail one at a time.
 __global__ void k_add_bf16(size_t n, const __bf16* __restrict__ a, const __bf16* __restrict__ b,
                            __bf16* __restrict__ out) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (__bf16)((float)a[i] + (float)b[i]);
+  const size_t i = 8 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (i + 8 <= n) {
+    const nbf16x8 x = *reinterpret_cast<const nbf16x8*>(a + i), y = *reinterpret_cast<const nbf16x8*>(b + i);
+    nbf16x8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = (__bf16)((float)x[e] + (float)y[e]);
+    *reinterpret_cast<nbf16x8*>(out + i) = o;
+  } else {
+    for (size_t j = i; j < n; ++j) out[j] = (__bf16)((float)a[j] + (float)b[j]);
+  }
 }
 
 // Gradient w.r.t. the input dose: d dose[p] = scale (gp[p] + dX0[p][0]) (the dose
@@ -683,21 +702,24 @@ hipError_t launch_net_input(int P, const float* dose, const float* scale, const 
   return hipGetLastError();
 }
 
+// (v: the full-resolution volume; C a multiple of 8; the element count within 32 bits)
 hipError_t launch_pool2(Vol v, int C, const __bf16* X, __bf16* Y, int backward, hipStream_t s) {
-  size_t n = (size_t)v.D * v.H * v.W * C;
+  const size_t n = (size_t)v.D * v.H * v.W * C;
+  if (C % 8 != 0 || n > 0x7fffffffULL) return hipErrorInvalidValue;
   if (!backward)
-    hipLaunchKernelGGL(k_pool2, dim3(nblk(n / 8)), dim3(256), 0, s, v, C, X, Y);
+    hipLaunchKernelGGL(k_pool2, dim3(nblk(n / 64)), dim3(256), 0, s, v, C, X, Y);
   else
-    hipLaunchKernelGGL(k_pool2_bwd, dim3(nblk(n)), dim3(256), 0, s, v, C, X, Y);
+    hipLaunchKernelGGL(k_pool2_bwd, dim3(nblk(n / 8)), dim3(256), 0, s, v, C, X, Y);
   return hipGetLastError();
 }
 
 hipError_t launch_up2(Vol v, int C, const __bf16* X, __bf16* Y, int backward, hipStream_t s) {
-  size_t n = (size_t)v.D * v.H * v.W * C;
+  const size_t n = (size_t)v.D * v.H * v.W * C;
+  if (C % 8 != 0 || n > 0x7fffffffULL) return hipErrorInvalidValue;
   if (!backward)
-    hipLaunchKernelGGL(k_up2, dim3(nblk(n)), dim3(256), 0, s, v, C, X, Y);
+    hipLaunchKernelGGL(k_up2, dim3(nblk(n / 8)), dim3(256), 0, s, v, C, X, Y);
   else
-    hipLaunchKernelGGL(k_up2_bwd, dim3(nblk(n / 8)), dim3(256), 0, s, v, C, X, Y);
+    hipLaunchKernelGGL(k_up2_bwd, dim3(nblk(n / 64)), dim3(256), 0, s, v, C, X, Y);
   return hipGetLastError();
 }
 
@@ -769,7 +791,7 @@ hipError_t launch_scale_by(int P, const float* a, const float* scale, int inv, f
 }
 
 hipError_t launch_add_bf16(size_t n, const __bf16* a, const __bf16* b, __bf16* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_add_bf16, dim3(nblk(n)), dim3(256), 0, s, n, a, b, out);
+  hipLaunchKernelGGL(k_add_bf16, dim3(nblk((n + 7) / 8)), dim3(256), 0, s, n, a, b, out);
   return hipGetLastError();
 }
 

@@ -106,20 +106,26 @@ int pdrt_scale_by(int32_t n, const float* a, const float* scale, int32_t inverse
   return PDRT_OK;
 }
 
+// 16-byte alignment of a device pointer (the pooling kernels move eight channels at a time)
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+static bool fits32(const pdrt_vol* v, int32_t c) { return (size_t)v->D * v->H * v->W * (size_t)c <= 0x7fffffffULL; }
+
 int pdrt_add_bf16(size_t n, const void* a, const void* b, void* out, void* stream) {
-  if (!n || !a || !b || !out) return PDRT_E_INVALID;
+  if (!n || !a || !b || !out || !aligned16(a) || !aligned16(b) || !aligned16(out)) return PDRT_E_INVALID;
   PDRT_TIMED("add_bf16", (hipStream_t)stream, launch_add_bf16(n, (const __bf16*)a, (const __bf16*)b, (__bf16*)out, (hipStream_t)stream));
   return PDRT_OK;
 }
 
 int pdrt_pool2(const pdrt_vol* fine, int32_t c, const void* x, void* y, int32_t backward, void* stream) {
-  if (!even_vol(fine) || c < 1 || !x || !y) return PDRT_E_INVALID;
+  if (!even_vol(fine) || c < 8 || c % 8 != 0 || !x || !y || !aligned16(x) || !aligned16(y) || !fits32(fine, c))
+    return PDRT_E_INVALID;
   PDRT_TIMED("pool2", (hipStream_t)stream, launch_pool2(V(fine), c, (const __bf16*)x, (__bf16*)y, backward, (hipStream_t)stream));
   return PDRT_OK;
 }
 
 int pdrt_upsample2(const pdrt_vol* fine, int32_t c, const void* x, void* y, int32_t backward, void* stream) {
-  if (!even_vol(fine) || c < 1 || !x || !y) return PDRT_E_INVALID;
+  if (!even_vol(fine) || c < 8 || c % 8 != 0 || !x || !y || !aligned16(x) || !aligned16(y) || !fits32(fine, c))
+    return PDRT_E_INVALID;
   PDRT_TIMED("upsample2", (hipStream_t)stream, launch_up2(V(fine), c, (const __bf16*)x, (__bf16*)y, backward, (hipStream_t)stream));
   return PDRT_OK;
 }

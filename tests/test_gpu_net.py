@@ -129,6 +129,22 @@ def test_pool_upsample_head_loss_adam():
     lhs = (y.float() * g.float()).sum().item()
     rhs = (xg.float() * gx.float()).sum().item()
     assert abs(lhs - rhs) <= 1e-2 * max(1.0, abs(lhs))
+    # upsampling's backward sums the eight children of each coarse voxel
+    gu = torch.empty((D // 2, H // 2, W // 2, C), dtype=torch.bfloat16, device=dev)
+    assert lib.pdrt_upsample2(ctypes.byref(v), C, gx.data_ptr(), gu.data_ptr(), 1, s) == 0
+    ref_u = _to_ncdhw(gx.float().cpu())
+    ref_u = ref_u.reshape(1, C, D // 2, 2, H // 2, 2, W // 2, 2).sum(dim=(3, 5, 7))
+    _close("upsample backward", _to_ncdhw(gu.float().cpu()), ref_u)
+    # eight channels per thread: c must be a multiple of 8 and the buffers 16-byte aligned
+    assert lib.pdrt_pool2(ctypes.byref(v), 12, xg.data_ptr(), y.data_ptr(), 0, s) == -1
+    assert lib.pdrt_pool2(ctypes.byref(v), C, xg.data_ptr() + 2, y.data_ptr(), 0, s) == -1
+    # add in groups of eight with a tail
+    na = 1003
+    a1 = _bf(rng.normal(size=na)).to(dev)
+    a2 = _bf(rng.normal(size=na)).to(dev)
+    ao = torch.empty(na, dtype=torch.bfloat16, device=dev)
+    assert lib.pdrt_add_bf16(na, a1.data_ptr(), a2.data_ptr(), ao.data_ptr(), s) == 0
+    assert torch.equal(ao.cpu(), (a1.float() + a2.float()).to(torch.bfloat16).cpu())
     n = 500
     xh = _bf(rng.normal(size=(n, C))).to(dev)
     hw = torch.tensor(rng.normal(size=(2, C)), dtype=torch.float32, device=dev)
