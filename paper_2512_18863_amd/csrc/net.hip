@@ -32,14 +32,15 @@ __device__ __forceinline__ bool neighbour(const Vol& v, int p, int tap, int* q) 
 
 // ------------------------------------------------------------------ forward and data gradient
 //
-// Implicit GEMM on v_mfma_f32_16x16x32_bf16 over a tile of 16 (w) x 4 (h) x
+// Implicit GEMM on v_mfma_f32_16x16x32_bf16 over a tile of 16 (w) x 8 (h) x
 // 2 (d) output positions per workgroup: the input tile with its one-voxel halo
 // is read from global memory once and kept in LDS (every position's 27
 // neighbours are then LDS reads); the weights, shared by every workgroup, are
 // read from global memory (cache resident) one K step ahead of their use.  M = 16 positions along w, N = 16 output channels per tile, K
 // runs over (tap, input channel) in steps of 32, lane group kq holding 8
 // consecutive channels of one tap; each lane tracks its (tap, channel)
-// incrementally.  Each of the 4 wavefronts owns two position rows and all N.
+// incrementally.  Each of the 4 wavefronts owns four position rows and all N,
+// so each weight fragment it loads feeds four rows.
 // The data gradient is the same GEMM with the taps mirrored, K over (tap,
 // output channel), the ReLU mask applied while the tile is staged.
 
@@ -69,7 +70,8 @@ struct KPos {
   }
 };
 
-constexpr int CT_W = 16, CT_H = 4, CT_D = 2;                          // output tile
+constexpr int CT_W = 16, CT_H = 8, CT_D = 2;                          // output tile
+constexpr int CT_RPW = CT_H * CT_D / 4;                              // position rows per wavefront
 constexpr int CT_HW = CT_W + 2, CT_HH = CT_H + 2, CT_HD = CT_D + 2;   // with halo
 constexpr int CT_POS = CT_HW * CT_HH * CT_HD;
 
@@ -125,19 +127,19 @@ __global__ void __launch_bounds__(256) k_conv3d_tiled(Vol v, ConvIO io) {
     *reinterpret_cast<nbf16x8*>(tin + (size_t)pos * CinP + 8 * g) = val;
   }
   const int m = lane & 15, kq = lane >> 4;
-  // this wavefront's two position rows: (h, d) = (mt % CT_H, mt / CT_H), w = w0 + m
-  int base[2];
+  // this wavefront's CT_RPW position rows: (h, d) = (mt % CT_H, mt / CT_H), w = w0 + m
+  int base[CT_RPW];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int mt = 2 * wave + r;
+  for (int r = 0; r < CT_RPW; ++r) {
+    const int mt = CT_RPW * wave + r;
     base[r] = ((mt / CT_H + 1) * CT_HH + (mt % CT_H + 1)) * CT_HW + (m + 1);
   }
   const int sgn = io.mirror ? -1 : 1;
   KPos kp{0, 0, 0, 0, 0};
   kp.advance(8 * kq, Cin);
-  nf32x4 acc[2][NT];
+  nf32x4 acc[CT_RPW][NT];
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < CT_RPW; ++r)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[r][t] = nf32x4{0.f, 0.f, 0.f, 0.f};
   __syncthreads();  // the tile is staged
@@ -153,7 +155,7 @@ __global__ void __launch_bounds__(256) k_conv3d_tiled(Vol v, ConvIO io) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) wrow[t] = io.w + (size_t)(16 * t + m) * io.Kp + 8 * kq;
   int kb = 0;
-  auto load = [&](nbf16x8 (&b)[NT], nbf16x8 (&a)[2]) {
+  auto load = [&](nbf16x8 (&b)[NT], nbf16x8 (&a)[CT_RPW]) {
     const int kbc = kb < last_kb ? kb : last_kb;
 #pragma unroll
     for (int t = 0; t < NT; ++t) b[t] = *reinterpret_cast<const nbf16x8*>(wrow[t] + kbc);
@@ -162,19 +164,19 @@ __global__ void __launch_bounds__(256) k_conv3d_tiled(Vol v, ConvIO io) {
     const int off = kin ? ((sgn * (kp.td - 1)) * CT_HH + sgn * (kp.th - 1)) * CT_HW + sgn * (kp.tw - 1) : 0;
     const int ci = kin ? kp.ci : 0;
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < CT_RPW; ++r) {
       const nbf16x8 x = *reinterpret_cast<const nbf16x8*>(tin + (size_t)(base[r] + off) * CinP + ci);
       a[r] = kin ? x : nbf16x8{};
     }
     kp.advance(32, Cin);
   };
-  auto compute = [&](const nbf16x8 (&b)[NT], const nbf16x8 (&a)[2]) {
+  auto compute = [&](const nbf16x8 (&b)[NT], const nbf16x8 (&a)[CT_RPW]) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < CT_RPW; ++r)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[t], acc[r][t], 0, 0, 0);
   };
-  nbf16x8 bx[NT], by[NT], ax[2], ay[2];
+  nbf16x8 bx[NT], by[NT], ax[CT_RPW], ay[CT_RPW];
   load(bx, ax);
   int st = 0;
   for (; st + 1 < nsteps; st += 2) {
@@ -188,8 +190,8 @@ __global__ void __launch_bounds__(256) k_conv3d_tiled(Vol v, ConvIO io) {
   if (st < nsteps) compute(bx, ax);
   // write: row r, lane (m = channel within the tile, kq) holds positions w0 + 4 kq + e
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int mt = 2 * wave + r;
+  for (int r = 0; r < CT_RPW; ++r) {
+    const int mt = CT_RPW * wave + r;
     const int hh = h0 + mt % CT_H, dd = d0 + mt / CT_H;
     if (hh >= v.H || dd >= v.D) continue;
 #pragma unroll
