@@ -61,7 +61,8 @@ extern "C" {
 #define PDRT_MAX_BLUR_RADIUS 64
 #define PDRT_MAX_STRUCTS 32
 
-/* CT grid.  Voxel (i, j, k) has its centre at (ox + i sx, oy + j sy, oz + k sz). */
+/* CT grid.  Voxel (i, j, k) has its centre at (ox + i sx, oy + j sy, oz + k sz).
+ * At most 2^31 - 1 voxels (PDRT_E_INVALID otherwise). */
 typedef struct {
   int32_t nx, ny, nz;
   double sx, sy, sz;

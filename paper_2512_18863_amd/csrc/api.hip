@@ -65,7 +65,7 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 int validate(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spec* spec) {
   if (!grid || !beam || !spec) return PDRT_E_INVALID;
   if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return PDRT_E_INVALID;
-  if ((double)grid->nx * grid->ny * grid->nz > 4.0e9) return PDRT_E_INVALID;
+  if ((double)grid->nx * grid->ny * grid->nz >= 2147483648.0) return PDRT_E_INVALID;  // 32-bit voxel offsets
   if (!finite_pos(grid->sx) || !finite_pos(grid->sy) || !finite_pos(grid->sz)) return PDRT_E_INVALID;
   if (!std::isfinite(grid->ox) || !std::isfinite(grid->oy) || !std::isfinite(grid->oz)) return PDRT_E_INVALID;
   if (!finite_pos(beam->sad_mm)) return PDRT_E_INVALID;

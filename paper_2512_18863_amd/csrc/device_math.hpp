@@ -84,7 +84,7 @@ __device__ __forceinline__ RhoFetch<T> rho_fetch(const T* __restrict__ rho_t, in
       const int y = y0 + dy, x = x0 + dx;
       r.m_ok[dy][dx] = T((y >= 0) & (y < ny) & (x >= 0) & (x < nx));
       const int cy = min(max(y, 0), ny - 1), cx = min(max(x, 0), nx - 1);
-      const T* col = rho_t + ((size_t)cy * nx + cx) * nz;
+      const T* col = rho_t + (cy * nx + cx) * nz;  // (the volume holds fewer than 2^31 voxels)
       r.lo[dy][dx] = col[za];
       r.hi[dy][dx] = col[zb];
     }

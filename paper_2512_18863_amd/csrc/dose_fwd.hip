@@ -262,7 +262,7 @@ __device__ __forceinline__ void march_ray(const Geo<T>& g, int b, int i, int j, 
       vb[(size_t)k * plane] = E(geo);
   };
   if (g.wepl_mode == PDRT_WEPL_PER_RAY) {
-#pragma unroll 4
+#pragma unroll 8
     for (int k = 0; k < g.Nk; ++k) {
       const T e = g.e0 + T(k) * g.dstep;
       const T gk = T(1) + e * g.inv_sad;
