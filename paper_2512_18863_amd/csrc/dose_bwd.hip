@@ -272,14 +272,24 @@ __device__ __forceinline__ int bcast(int v, int src) { return __builtin_amdgcn_r
 // continuous index jj(z) = A + B z is affine (A = rel_oz q / lat + c_v,
 // B = s_z q / lat), and the trilinear weight of node j is max(0, 1 - |jj - j|);
 // only the z with jj in (j - 1, j + 1), found from the inverse map, are visited.
+// The z are taken four at a time, their loads issued together (addresses clamped
+// to z1, weights past z1 zero, which adds exact zeros), so a lane waits once per
+// four voxels rather than once per voxel; the terms keep their order.
 template <typename T, typename Col>
 __device__ __forceinline__ T z_sum_tent(const Geo<T>& g, int j, T A, T B, T invB, Col col) {
   const T za = (T(j - 1) - A) * invB, zb = (T(j + 1) - A) * invB;
   const int z0 = max(0, (int)dfloor(za)), z1 = min(g.nz - 1, (int)dfloor(zb));
   T part = T(0);
-  for (int z = z0; z <= z1; ++z) {
-    const T jj = A + T(z) * B;
-    part += fmax(T(0), T(1) - fabs(jj - T(j))) * col(z);
+  for (int z = z0; z <= z1; z += 4) {
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = col(min(z + u, z1));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T jj = A + T(z + u) * B;
+      const T w = z + u <= z1 ? fmax(T(0), T(1) - fabs(jj - T(j))) : T(0);
+      part += w * v[u];
+    }
   }
   return part;
 }
