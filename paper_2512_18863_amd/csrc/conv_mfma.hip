@@ -241,6 +241,22 @@ __device__ __forceinline__ int2 grid_offsets(const Geo<float>& g, const RegionSh
   return int2{-(__builtin_amdgcn_readlane(key, 0) & 15), -(__builtin_amdgcn_readlane(key, 16) & 15)};
 }
 
+// The extended, folded tap rows of the FP32 kernels: kx[p][c] = K[p][|c - off|]
+// where |c - off| <= h (halved for p = 0, whose row the fold counts twice), zero
+// elsewhere.  Wavefronts walk the tap rows, lanes the columns.
+__device__ __forceinline__ void build_kx(const float* kq, float* kx, int h, int E, int off, int wave, int lane,
+                                         int nw) {
+  for (int p = wave; p <= h; p += nw) {
+    const float sc = p == 0 ? 0.5f : 1.f;
+    for (int c = lane; c < E; c += 64) {
+      const int q = c - off;
+      float v = 0.f;
+      if (q >= -h && q <= h) v = kq[p * (h + 1) + (q < 0 ? -q : q)] * sc;
+      kx[p * E + c] = v;
+    }
+  }
+}
+
 // Support of the convolution (box: per control point [u0, u1) x [v0, v1), the
 // aperture's rectangle outside which the fluence and its derivatives vanish):
 //   CONV_DENSE    every input and output;
@@ -296,22 +312,23 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
   const float* bbase = kx + 4 * kk + 15 - m;
   const int off = h + 15;
   auto a_of = [&](int ti, int tj) { return tile + (MT * ti + m + h) * pitch + MT * tj + 4 * kk; };
-  // an item's data rectangle and, with CONV_IN_BOX, its tile-grid offset
-  auto rect_of = [&](int item, int2& go) {
-    go = int2{0, 0};
-    if (SUP == CONV_IN_BOX) {
-      const int4 bx = box[(item / nreg) / g.Nk];
-      go = grid_offsets(g, rs, I0, J0, SS, bx, lane);
-      return clip_rect(data_rect(g, I0 + go.x, J0 + go.y, MT * rs.TI, MT * rs.TJ), bx);
-    }
+  // with CONV_IN_BOX, an item's tile-grid offset (a whole wavefront's call) and its
+  // data rectangle for a given offset
+  auto offsets_of = [&](int item) {
+    if (SUP == CONV_IN_BOX) return grid_offsets(g, rs, I0, J0, SS, box[(item / nreg) / g.Nk], lane);
+    return int2{0, 0};
+  };
+  auto rect_at = [&](int item, int2 go) {
+    if (SUP == CONV_IN_BOX)
+      return clip_rect(data_rect(g, I0 + go.x, J0 + go.y, MT * rs.TI, MT * rs.TJ), box[(item / nreg) / g.Nk]);
     return dr;
   };
 
   zero_lds(tile, rows * pitch, tid, NT);
   float buf[PF];
   int it = blockIdx.x;
-  int2 cur_go, nxt_go;
-  DataRect cur = rect_of(it < n_items ? it : 0, cur_go);
+  int2 cur_go = offsets_of(it < n_items ? it : 0), nxt_go;
+  DataRect cur = rect_at(it < n_items ? it : 0, cur_go);
   DataRect prev = cur;
   prev.nr = 0;
   prev.nc = 1;
@@ -324,6 +341,15 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     put_rect<PF>(src, g.Nv, cur, pitch, tid, NT, buf, tile);
     if (SUP == CONV_IN_BOX) {
       if (tid == 0) *grab = 0;
+      // the next item's grid offset, searched by one wavefront and read by all
+      // after the barriers below
+      if (wave == 0 && it + (int)gridDim.x < n_items) {
+        const int2 go = offsets_of(it + gridDim.x);
+        if (lane == 0) {
+          grab[1] = go.x;
+          grab[2] = go.y;
+        }
+      }
       if (tid < n_tiles) {
         // the steps of tile tid that meet the input rectangle: tap rows p whose row
         // I + p .. I + p + 15 (plus side, p in [a1, b1]) or I - p .. I - p + 15 (minus
@@ -376,20 +402,15 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
       }
       order[rank] = tid;
     }
-    for (int idx = tid; idx < (h + 1) * E; idx += NT) {
-      int p = idx / E, c = idx - p * E;
-      int q = c - off;
-      float v = 0.f;
-      if (q >= -h && q <= h) v = kq[p * (h + 1) + (q < 0 ? -q : q)] * (p == 0 ? 0.5f : 1.f);
-      kx[idx] = v;
-    }
+    build_kx(kq, kx, h, E, off, wave, lane, NW);
     __syncthreads();
     // next item's input, in flight while this item's matrix work runs
     const int nx = it + gridDim.x;
     DataRect nxt = cur;
     nxt_go = cur_go;
     if (nx < n_items) {
-      nxt = rect_of(nx, nxt_go);
+      if (SUP == CONV_IN_BOX) nxt_go = int2{__builtin_amdgcn_readfirstlane(grab[1]), __builtin_amdgcn_readfirstlane(grab[2])};
+      nxt = rect_at(nx, nxt_go);
       fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, nxt, tid, NT, buf);
     }
     float* dst = out + (size_t)bk * plane;
@@ -505,13 +526,7 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32_adj(Geo<float> g, Reg
     put_rect<PF>(src, g.Nv, dr, pitch, tid, NT, buf, tile);
     unique_taps(g, k, zca[bk], kq, tid, NT);
     __syncthreads();
-    for (int idx = tid; idx < (h + 1) * E; idx += NT) {
-      int p = idx / E, c = idx - p * E;
-      int q = c - off;
-      float v = 0.f;
-      if (q >= -h && q <= h) v = kq[p * (h + 1) + (q < 0 ? -q : q)] * (p == 0 ? 0.5f : 1.f);
-      kx[idx] = v;
-    }
+    build_kx(kq, kx, h, E, off, wave, lane, NW);
     __syncthreads();
     const int nx = it + gridDim.x;
     if (nx < n_items) fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, dr, tid, NT, buf);
