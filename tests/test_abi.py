@@ -77,7 +77,7 @@ def test_fan_dims_agree_with_oracle(mk):
     assert abs(d0.value - om.d0) < 1e-9
 
 
-def test_survey_grid_sizes():
+def test_standard_workload_grid_sizes():
     """Beam-frame grids of the standard workloads."""
     for mk, want in [(inputs.config_c0, (27, 27, 47)), (lambda: inputs.config_c1(2), (43, 43, 183)),
                      (lambda: inputs.config_c2(2), (63, 63, 273)),
