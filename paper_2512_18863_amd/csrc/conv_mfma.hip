@@ -102,6 +102,25 @@ static F32Shape f32_shape(int h, const RegionShape& r) {
   return s;
 }
 
+// CONV_IN_BOX image.  A tile reads only the tap rows and column super-steps that
+// reach the input rectangle [r0, r1) x [c0, c1), so its reads stay inside rows
+// [r0 - 15, r1 + 15) and columns [c0 - 18, c1 + 15) (the window start is rounded
+// down to a multiple of 4 and may be moved left by less than 16 to keep the
+// window inside the extended tap row).  The image is therefore placed at the
+// rectangle, not at the region: its first row is R0 = max(I - h, r0 - 15) and its
+// first column C0 the largest of J - h, J - h + 4, ... not above c0 - 18 (so the
+// 16-byte reads stay aligned), with (I, J) the region's shifted origin.  The
+// rectangle is clipped to the plane and to the region's reach, so the image needs
+// at most min(Nu, rows of reach) + 30 rows and min(Nv, columns of reach) + 36
+// columns, and never more than the region image.
+static F32Shape f32_shape_in_box(int h, const RegionShape& r, int Nu, int Nv) {
+  F32Shape s = f32_shape(h, r);
+  auto lo = [](int a, int b) { return a < b ? a : b; };
+  s.rows = lo(lo(Nu, MT * r.TI + 2 * h) + 30, s.rows);
+  s.pitch = pitch_f32(lo(lo(Nv, MT * r.TJ + 2 * h) + 36, MT * r.TJ + 16 * s.SS));
+  return s;
+}
+
 static size_t f32_lds(int h, const F32Shape& fs) {
   // image, extended taps, unique taps, and one counter
   return sizeof(float) * ((size_t)fs.rows * fs.pitch + (size_t)(h + 1) * fs.E + (size_t)(h + 1) * (h + 1)) + 16;
@@ -318,9 +337,18 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     if (SUP == CONV_IN_BOX) return grid_offsets(g, rs, I0, J0, SS, box[(item / nreg) / g.Nk], lane);
     return int2{0, 0};
   };
+  // (CONV_IN_BOX: the image sits at the rectangle, see f32_shape_in_box; an image
+  // origin is always r0 - lr0, c0 - lc0 of the item's rectangle)
   auto rect_at = [&](int item, int2 go) {
-    if (SUP == CONV_IN_BOX)
-      return clip_rect(data_rect(g, I0 + go.x, J0 + go.y, MT * rs.TI, MT * rs.TJ), box[(item / nreg) / g.Nk]);
+    if (SUP == CONV_IN_BOX) {
+      DataRect c = clip_rect(data_rect(g, I0 + go.x, J0 + go.y, MT * rs.TI, MT * rs.TJ), box[(item / nreg) / g.Nk]);
+      const int Ilo = I0 + go.x - h, Clo = J0 + go.y - h;
+      const int R0 = max(Ilo, c.r0 - 15);
+      const int C0 = Clo + ((max(0, c.c0 - 18 - Clo) >> 2) << 2);
+      c.lr0 = c.r0 - R0;
+      c.lc0 = c.c0 - C0;
+      return c;
+    }
     return dr;
   };
 
@@ -433,7 +461,8 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
         const int a1 = __builtin_amdgcn_readfirstlane(tr[0]), b1 = __builtin_amdgcn_readfirstlane(tr[1]);
         const int a2 = __builtin_amdgcn_readfirstlane(tr[2]), b2 = __builtin_amdgcn_readfirstlane(tr[3]);
         const int o = __builtin_amdgcn_readfirstlane(tr[4]), nu = __builtin_amdgcn_readfirstlane(tr[5]);
-        const float* ab[1] = {a_of(ti, tj) + o};
+        const int R0 = cur.r0 - cur.lr0, C0 = cur.c0 - cur.lc0;
+        const float* ab[1] = {tile + (I + m - R0) * pitch + (J - h - C0) + 4 * kk + o};
         const float* bb = bbase + o;
         f32x4 acc[1] = {f32x4{0.f, 0.f, 0.f, 0.f}};
         if (kFoldSegments) {
@@ -961,9 +990,15 @@ static hipError_t launch_f32_sup(const Geo<float>& g, const RegionShape& rs, con
   if (tiles <= 8) return launch_f32_cfg<8, 1, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
   if (tiles <= 16) return launch_f32_cfg<8, 2, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
   if (tiles <= 24) return launch_f32_cfg<8, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
-  // CONV_IN_BOX: tiles are taken dynamically, so more wavefronts than tiles / 3 only
-  // add latency hiding; CONV_DENSE: three fixed tiles per wavefront
-  if (SUP == CONV_IN_BOX) return launch_f32_cfg<16, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
+  // CONV_IN_BOX: tiles are taken dynamically.  When two workgroups' images fit in
+  // one CU's LDS, two workgroups of 8 wavefronts share each CU, so one's matrix loop
+  // runs while the other stages its next plane, builds its taps or waits at a
+  // barrier; otherwise one of 16 wavefronts.  CONV_DENSE: three fixed tiles per
+  // wavefront.
+  if (SUP == CONV_IN_BOX) {
+    if (2 * lds <= LDS_MAX) return launch_f32_cfg<8, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
+    return launch_f32_cfg<16, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
+  }
   return launch_f32_cfg<12, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
 }
 
@@ -1011,8 +1046,9 @@ hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, con
   size_t lds = 0;
   for (int rmax = RMAX; rmax >= 1; --rmax) {  // the largest region whose LDS image fits
     rs = region_shape(g.Nu, g.Nv, rmax);
-    fs = f32_shape(g.h, rs);
-    lds = adj ? f32_adj_lds(g.h, fs, 12) : f32_lds(g.h, fs) + (bx && support == CONV_IN_BOX ? kBoxTileLds : 0);
+    const bool in_box = bx && support == CONV_IN_BOX;
+    fs = in_box ? f32_shape_in_box(g.h, rs, g.Nu, g.Nv) : f32_shape(g.h, rs);
+    lds = adj ? f32_adj_lds(g.h, fs, 12) : f32_lds(g.h, fs) + (in_box ? kBoxTileLds : 0);
     if (lds <= LDS_MAX) break;
   }
   if (adj) return launch_f32_adj(g, rs, fs, nb, bx, z, in, out, s);
