@@ -57,19 +57,38 @@ __device__ __forceinline__ int opaque(int x) {
   return x;
 }
 
+// Row and column of the elements tid, tid + nt, tid + 2 nt, ... of a rectangle nc
+// wide (element idx at row idx / nc, column idx % nc), advanced by one addition
+// and a carry instead of a division per element.
+struct RectWalk {
+  int r, c, dr, dc;
+  __device__ __forceinline__ RectWalk(int tid, int nt, int nc) {
+    r = opaque(tid) / nc;
+    c = tid - r * nc;
+    dr = nt / nc;
+    dc = nt - dr * nc;
+  }
+  __device__ __forceinline__ void next(int nc) {
+    r += dr;
+    c += dc;
+    if (c >= nc) {
+      c -= nc;
+      ++r;
+    }
+  }
+};
+
 template <int PF>
 __device__ __forceinline__ void fetch_rect(const float* __restrict__ src, int Nv, const DataRect& d, int tid, int nt,
                                            float (&buf)[PF]) {
-  const int area = d.nr * d.nc;
+  RectWalk w(tid, nt, d.nc);
+  const float* s0 = src + (size_t)d.r0 * Nv + d.c0;
 #pragma unroll
   for (int e = 0; e < PF; ++e) {
-    const int idx = opaque(tid + e * nt);
     float v = 0.f;
-    if (idx < area) {
-      const int r = idx / d.nc, c = idx - r * d.nc;
-      v = src[(size_t)(d.r0 + r) * Nv + d.c0 + c];
-    }
+    if (w.r < d.nr) v = s0[w.r * Nv + w.c];
     buf[e] = v;
+    w.next(d.nc);
   }
 }
 
@@ -78,19 +97,15 @@ __device__ __forceinline__ void fetch_rect(const float* __restrict__ src, int Nv
 template <int PF, typename E>
 __device__ __forceinline__ void put_rect(const float* __restrict__ src, int Nv, const DataRect& d, int pitch,
                                          int tid, int nt, const float (&buf)[PF], E* tile) {
-  const int area = d.nr * d.nc;
+  RectWalk w(tid, nt, d.nc);
+  E* t0 = tile + d.lr0 * pitch + d.lc0;
 #pragma unroll
   for (int e = 0; e < PF; ++e) {
-    const int idx = opaque(tid + e * nt);
-    if (idx < area) {
-      const int r = idx / d.nc, c = idx - r * d.nc;
-      tile[(d.lr0 + r) * pitch + d.lc0 + c] = (E)buf[e];
-    }
+    if (w.r < d.nr) t0[w.r * pitch + w.c] = (E)buf[e];
+    w.next(d.nc);
   }
-  for (int idx = tid + PF * nt; idx < area; idx += nt) {
-    const int r = idx / d.nc, c = idx - r * d.nc;
-    tile[(d.lr0 + r) * pitch + d.lc0 + c] = (E)src[(size_t)(d.r0 + r) * Nv + d.c0 + c];
-  }
+  const float* s0 = src + (size_t)d.r0 * Nv + d.c0;
+  for (; w.r < d.nr; w.next(d.nc)) t0[w.r * pitch + w.c] = (E)s0[w.r * Nv + w.c];
 }
 
 template <typename E>

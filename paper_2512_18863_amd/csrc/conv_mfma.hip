@@ -410,9 +410,8 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
         tr[6] = (n1 + n2 - both) * nu;
       }
       // clear what the previous item wrote outside this item's rectangle
-      for (int idx = tid; idx < prev.nr * prev.nc; idx += NT) {
-        const int r = idx / prev.nc, c = idx - r * prev.nc;
-        const int lr = prev.lr0 + r, lc = prev.lc0 + c;
+      for (RectWalk w(tid, NT, prev.nc); w.r < prev.nr; w.next(prev.nc)) {
+        const int lr = prev.lr0 + w.r, lc = prev.lc0 + w.c;
         const bool in_cur = lr >= cur.lr0 && lr < cur.lr0 + cur.nr && lc >= cur.lc0 && lc < cur.lc0 + cur.nc;
         if (!in_cur) tile[lr * pitch + lc] = 0.f;
       }
@@ -736,9 +735,8 @@ __global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Sh
     const float* src = in + (size_t)bk * plane;
     put_rect<PF>(src, g.Nv, cur, pitch, tid, NT, buf, tile);
     if (SUP == CONV_IN_BOX) {
-      for (int idx = tid; idx < prev.nr * prev.nc; idx += NT) {
-        const int r = idx / prev.nc, c = idx - r * prev.nc;
-        const int lr = prev.lr0 + r, lc = prev.lc0 + c;
+      for (RectWalk w(tid, NT, prev.nc); w.r < prev.nr; w.next(prev.nc)) {
+        const int lr = prev.lr0 + w.r, lc = prev.lc0 + w.c;
         const bool in_cur = lr >= cur.lr0 && lr < cur.lr0 + cur.nr && lc >= cur.lc0 && lc < cur.lc0 + cur.nc;
         if (!in_cur) tile[lr * pitch + lc] = (__bf16)0.f;
       }
