@@ -1000,6 +1000,10 @@ static hipError_t launch_f32_sup(const Geo<float>& g, const RegionShape& rs, con
   return launch_f32_cfg<12, 3, SUP>(g, rs, fs, lds, nb, box, z, in, out, s);
 }
 
+// Wavefronts of the adjoint kernel for regions of more than 24 tiles (four per
+// SIMD, which hide the LDS latency of the matrix loop better than three).
+constexpr int kAdjNW = 16;
+
 // LDS of the adjoint kernel: the FP32 image and taps plus NW x 256 partial sums
 // (16-byte aligned).
 static size_t f32_adj_lds(int h, const F32Shape& fs, int nw) { return f32_lds(h, fs) + 16 + sizeof(float) * 256 * nw; }
@@ -1032,7 +1036,7 @@ static hipError_t launch_f32_adj(const Geo<float>& g, const RegionShape& rs, con
   if (tiles <= 8) return launch_f32_adj_cfg<8, 1>(g, rs, fs, nb, box, z, in, out, s);
   if (tiles <= 16) return launch_f32_adj_cfg<8, 2>(g, rs, fs, nb, box, z, in, out, s);
   if (tiles <= 24) return launch_f32_adj_cfg<8, 3>(g, rs, fs, nb, box, z, in, out, s);
-  return launch_f32_adj_cfg<12, 3>(g, rs, fs, nb, box, z, in, out, s);
+  return launch_f32_adj_cfg<kAdjNW, 3>(g, rs, fs, nb, box, z, in, out, s);
 }
 
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
@@ -1046,7 +1050,7 @@ hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, con
     rs = region_shape(g.Nu, g.Nv, rmax);
     const bool in_box = bx && support == CONV_IN_BOX;
     fs = in_box ? f32_shape_in_box(g.h, rs, g.Nu, g.Nv) : f32_shape(g.h, rs);
-    lds = adj ? f32_adj_lds(g.h, fs, 12) : f32_lds(g.h, fs) + (in_box ? kBoxTileLds : 0);
+    lds = adj ? f32_adj_lds(g.h, fs, kAdjNW) : f32_lds(g.h, fs) + (in_box ? kBoxTileLds : 0);
     if (lds <= LDS_MAX) break;
   }
   if (adj) return launch_f32_adj(g, rs, fs, nb, bx, z, in, out, s);
