@@ -199,6 +199,61 @@ __device__ __forceinline__ void f32_steps(const float* const* abase, const float
   for (int q = 0; q < NA; ++q) acc[q] = ac_[q];
 }
 
+// The same loop for two horizontally adjacent tiles whose column windows start at
+// the same input column: they share the A operand (the same input rows and
+// columns) and each multiplies it by its own Toeplitz operand, the right tile's
+// starting 16 entries earlier in the extended tap row.  Four LDS reads feed eight
+// matrix instructions instead of six; each tile's sum keeps the order of f32_steps.
+template <int MODE>
+__device__ __forceinline__ void f32_steps_hpair(const float* abase, const float* bbase0, const float* bbase1,
+                                                int pitch, int E, int pa, int pb, int ua, int ub, f32x4& acc0,
+                                                f32x4& acc1) {
+  const int nu = ub - ua + 1;
+  const int total = (pb >= pa && nu > 0) ? (pb - pa + 1) * nu : 0;
+  if (total <= 0) return;
+  f32x4 c0 = acc0, c1 = acc1;
+  int lp = pa, lu = ua;
+  auto load = [&](f32x4v& a0, f32x4v& a1, float (&b0)[4], float (&b1)[4]) {
+    const int p = min(lp, pb);  // past the last step: reload the last tap row
+    const int op = p * pitch + 16 * lu, om = 16 * lu - p * pitch;
+    const float* r0 = bbase0 + p * E + 16 * lu;
+    const float* r1 = bbase1 + p * E + 16 * lu;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      b0[e] = r0[e];
+      b1[e] = r1[e];
+    }
+    if (MODE != 2) a0 = *reinterpret_cast<const f32x4v*>(abase + op);
+    if (MODE != 1) a1 = *reinterpret_cast<const f32x4v*>(abase + om);
+    const bool wrap = lu >= ub;
+    lu = wrap ? ua : lu + 1;
+    lp += wrap ? 1 : 0;
+  };
+  auto compute = [&](const f32x4v& a0, const f32x4v& a1, const float (&b0)[4], const float (&b1)[4]) {
+    const f32x4v a = MODE == 0 ? a0 + a1 : (MODE == 1 ? a0 : a1);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b0[e], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b1[e], c1, 0, 0, 0);
+    }
+  };
+  f32x4v x0, x1, y0, y1;
+  float bx0[4], bx1[4], by0[4], by1[4];
+  load(x0, x1, bx0, bx1);
+  int st = 0;
+  for (; st + 1 < total; st += 2) {
+    load(y0, y1, by0, by1);  // step st + 1
+    __builtin_amdgcn_sched_barrier(0);
+    compute(x0, x1, bx0, bx1);
+    load(x0, x1, bx0, bx1);  // step st + 2 (a repeat of the last step when st + 2 == total)
+    __builtin_amdgcn_sched_barrier(0);
+    compute(y0, y1, by0, by1);
+  }
+  if (st < total) compute(x0, x1, bx0, bx1);
+  acc0 = c0;
+  acc1 = c1;
+}
+
 // The part of a plane's data rectangle that lies inside the box [u0, u1) x [v0, v1).
 __device__ __forceinline__ DataRect clip_rect(const DataRect& d, int4 bx) {
   DataRect c;
@@ -303,7 +358,7 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
   float* kx = lds + rows * pitch;  // (h + 1) x E, zero outside |q| <= h, row 0 halved
   float* kq = kx + (h + 1) * E;    // (h + 1) x (h + 1) unique taps
   int* grab = reinterpret_cast<int*>(kq + (h + 1) * (h + 1));  // next tile to take (CONV_IN_BOX)
-  // CONV_IN_BOX: per tile {a1, b1, a2, b2, column offset o, super-steps nu, steps, -}
+  // CONV_IN_BOX: per tile {a1, b1, a2, b2, column offset o, super-steps nu, steps, pair role}
   int* trange = grab + 4;
   int* order = trange + 8 * RMAX * RMAX;  // CONV_IN_BOX: tiles by decreasing step count
   const int nreg = rs.regions_i * rs.regions_j;
@@ -408,6 +463,34 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
         tr[4] = o;
         tr[5] = nu;
         tr[6] = (n1 + n2 - both) * nu;
+        // Horizontal pairs: scanning a tile row from the left, tiles j and j + 1 form
+        // a pair when their column windows start at the same input column with the
+        // same super-step count (the window depends on the tile column only, so
+        // every row pairs alike).  Role: 1 left tile of a pair, -1 right tile, 0 alone.
+        auto window = [&](int Jc, int& wo, int& wn) {
+          const int wb = Jc - h;
+          const int wa = max(wb, cur.c0), wz = min(wb + 16 * SS - 1, cur.c0 + cur.nc - 1);
+          wo = 0;
+          wn = 0;
+          if (cur.nr > 0 && wz >= wa && Jc < g.Nv) {
+            wo = ((wa - wb) >> 2) << 2;
+            wn = (wz - wb - wo + 16) >> 4;
+            wo = min(wo, 16 * (SS - wn));
+          }
+        };
+        int role = 0;
+        for (int jj = 0; jj < rs.TJ;) {
+          int oa, na, ob = 0, nb_ = 0;
+          window(J0 + cur_go.y + MT * jj, oa, na);
+          if (jj + 1 < rs.TJ) window(J0 + cur_go.y + MT * (jj + 1), ob, nb_);
+          if (jj + 1 < rs.TJ && na > 0 && nb_ == na && ob == oa - 16) {
+            role = jj == tj ? 1 : (jj + 1 == tj ? -1 : role);
+            jj += 2;
+          } else {
+            jj += 1;
+          }
+        }
+        tr[7] = role;
       }
       // clear what the previous item wrote outside this item's rectangle
       for (RectWalk w(tid, NT, prev.nc); w.r < prev.nr; w.next(prev.nc)) {
@@ -419,15 +502,19 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
     unique_taps(g, k, zca[bk], kq, tid, NT);
     __syncthreads();
     if (SUP == CONV_IN_BOX && tid < n_tiles) {
-      // rank by step count, largest first (ties by index), so the last tiles taken are short
-      auto work = [&](int t) { return trange[8 * t + 6]; };
+      // the units (single tiles and left tiles of pairs) ranked by matrix
+      // instructions, largest first (ties by index), so the last units taken are short
+      auto work = [&](int t) { return trange[8 * t + 6] * (trange[8 * t + 7] == 1 ? 2 : 1); };
       const int w = work(tid);
-      int rank = 0;
+      int rank = 0, units = 0;
       for (int t = 0; t < n_tiles; ++t) {
+        if (trange[8 * t + 7] < 0) continue;
         const int v = work(t);
         rank += (v > w || (v == w && t < tid)) ? 1 : 0;
+        ++units;
       }
-      order[rank] = tid;
+      if (trange[8 * tid + 7] >= 0) order[rank] = tid;
+      if (tid == 0) grab[3] = units;
     }
     build_kx(kq, kx, h, E, off, wave, lane, NW);
     __syncthreads();
@@ -447,11 +534,12 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
       // only the tap rows and super-steps that reach the input rectangle, so
       // wavefronts whose tiles need little work take more tiles.  Every tile is
       // computed by one wavefront in a fixed step order.
+      const int n_units = __builtin_amdgcn_readfirstlane(grab[3]);
       while (true) {
         int t = 0;
         if (lane == 0) t = atomicAdd(grab, 1);
         t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= n_tiles) break;
+        if (t >= n_units) break;
         t = __builtin_amdgcn_readfirstlane(order[t]);
         const int ti = t / rs.TJ, tj = t - (t / rs.TJ) * rs.TJ;
         const int I = I0 + cur_go.x + MT * ti, J = J0 + cur_go.y + MT * tj;
@@ -464,6 +552,28 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
         const float* ab[1] = {tile + (I + m - R0) * pitch + (J - h - C0) + 4 * kk + o};
         const float* bb = bbase + o;
         f32x4 acc[1] = {f32x4{0.f, 0.f, 0.f, 0.f}};
+        if (__builtin_amdgcn_readfirstlane(tr[7]) == 1) {
+          // a pair: this tile and the one to its right (same tap rows, the same input
+          // window, whose offset in the right tile's frame is o - 16)
+          f32x4 acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
+          int p = min(a1 <= b1 ? a1 : h + 1, a2 <= b2 ? a2 : h + 1);
+          const int p_top = max(a1 <= b1 ? b1 : -1, a2 <= b2 ? b2 : -1);
+          while (p <= p_top) {
+            const bool plus = a1 <= p && p <= b1, minus = a2 <= p && p <= b2;
+            int e = p_top;
+            if (plus) e = min(e, b1);
+            else if (a1 > p && a1 <= b1) e = min(e, a1 - 1);
+            if (minus) e = min(e, b2);
+            else if (a2 > p && a2 <= b2) e = min(e, a2 - 1);
+            if (plus && minus) f32_steps_hpair<0>(ab[0], bb, bb - 16, pitch, E, p, e, 0, nu - 1, acc[0], acc1);
+            else if (plus) f32_steps_hpair<1>(ab[0], bb, bb - 16, pitch, E, p, e, 0, nu - 1, acc[0], acc1);
+            else if (minus) f32_steps_hpair<2>(ab[0], bb, bb - 16, pitch, E, p, e, 0, nu - 1, acc[0], acc1);
+            p = e + 1;
+          }
+          store_tile_from(g, I, J, I0, J0, lane, acc[0], dst);
+          store_tile_from(g, I, J + MT, I0, J0, lane, acc1, dst);
+          continue;
+        }
         if (kFoldSegments) {
           // segments of p in increasing order, each loading only the sides it needs
           int p = min(a1 <= b1 ? a1 : h + 1, a2 <= b2 ? a2 : h + 1);

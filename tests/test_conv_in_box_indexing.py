@@ -10,13 +10,16 @@ image is placed at the rectangle: first row max(I - h, r0 - 15), first column th
 last multiple-of-4 offset of J - h not above c0 - 18, capacity
 min(min(Nu, 16 TI + 2h) + 30, 16 TI + 2h) rows by
 min(min(Nv, 16 TJ + 2h) + 36, 16 TJ + 16 SS) columns, reused from one item to the
-next with the previous rectangle cleared outside the new one.
+next with the previous rectangle cleared outside the new one.  Horizontally
+adjacent tiles whose column windows start at the same input column are run as a
+pair sharing the A operand, each with its own Toeplitz offset.
 
 This model follows the same integer arithmetic and checks, for random planes,
 kernel sizes and rectangles (inside, across and outside the plane, empty), that
 every image read lies inside that capacity, every Toeplitz read inside the
-extended tap row, every output is written exactly once, and the result equals a
-direct correlation of the masked input.  It needs no GPU.
+extended tap row, every output is written exactly once, the two tiles of every
+pair read the same input window, and the result equals a direct correlation of
+the masked input.  It needs no GPU.
 """
 import random
 
@@ -25,6 +28,7 @@ import pytest
 from scipy import ndimage
 
 MT, RMAX = 16, 6
+PAIRS = []  # (item, left tile column) of every horizontal pair formed
 
 
 def region_shape(N):
@@ -100,6 +104,27 @@ def segments(a1, b1, a2, b2, h):
     return out
 
 
+def pair_roles(J0p, TJ, Nv, c0, c1, nr, h, SS):
+    """Roles of the tile columns (1 left tile of a pair, -1 right tile, 0 alone):
+    scanning from the left, columns j and j + 1 pair when their windows start at
+    the same input column with the same super-step count."""
+    def window(Jc):
+        if not nr or Jc >= Nv:
+            return 0, 0
+        return col_window(Jc, c0, c1, h, SS)
+    roles = [0] * TJ
+    j = 0
+    while j < TJ:
+        oa, na = window(J0p + MT * j)
+        ob, nb = window(J0p + MT * (j + 1)) if j + 1 < TJ else (0, 0)
+        if j + 1 < TJ and na > 0 and nb == na and ob == oa - 16:
+            roles[j], roles[j + 1] = 1, -1
+            j += 2
+        else:
+            j += 1
+    return roles
+
+
 def image_capacity(Nu, Nv, h, TI, TJ, SS):
     rows = min(min(Nu, MT * TI + 2 * h) + 30, MT * TI + 2 * h)
     cols = min(min(Nv, MT * TJ + 2 * h) + 36, MT * TJ + 16 * SS)
@@ -151,6 +176,16 @@ def forward_in_box(inputs, K, boxes):
                 keep = (rr >= lr0) & (rr < lr0 + nr) & (cc >= lc0) & (cc < lc0 + nc)
                 img[pr:pr + pnr, pc:pc + pnc][~keep] = 0.0
             prev = (lr0, nr, lc0, nc)
+            roles = pair_roles(J0p, TJ, Nv, c0, c1, nr, h, SS)
+            for tj in range(TJ - 1):
+                if roles[tj] == 1:
+                    # the pair's two tiles read the same input columns (one A operand),
+                    # and the right tile's Toeplitz offset o - 16 is its own window offset
+                    oL, nL = col_window(J0p + MT * tj, c0, c1, h, SS)
+                    oR, nR = col_window(J0p + MT * (tj + 1), c0, c1, h, SS)
+                    assert nL == nR > 0 and oR == oL - 16 >= 0
+                    assert (J0p + MT * tj - h + oL) == (J0p + MT * (tj + 1) - h + oR)
+                    PAIRS.append((item, tj))
             for ti in range(TI):
                 for tj in range(TJ):
                     I, J = I0p + MT * ti, J0p + MT * tj
@@ -215,7 +250,10 @@ def _check(Nu, Nv, h, boxes, seed):
 def test_standard_plane_and_full_opening():
     """89 x 89 planes with n = 61: the benchmark's jaw opening, a shifted and a
     wider one, the whole plane, and a one-row slit, in sequence on one image."""
+    del PAIRS[:]
     _check(89, 89, 30, [(30, 59, 30, 59), (28, 61, 31, 58), (0, 89, 0, 89), (44, 45, 10, 80)], seed=1)
+    # at the benchmark's opening the inner tile columns pair up: (1, 2) and (3, 4)
+    assert sorted(tj for item, tj in PAIRS if item == 0) == [1, 3]
 
 
 def test_random_planes_and_rectangles():
