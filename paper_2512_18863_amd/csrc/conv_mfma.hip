@@ -131,7 +131,6 @@ static size_t f32_lds(int h, const F32Shape& fs) {
 constexpr size_t kBoxTileLds = sizeof(int) * 9 * RMAX * RMAX;
 
 constexpr int PF = 12;  // prefetched elements per thread
-constexpr bool kFoldSegments = true;  // CONV_IN_BOX: split each tile's tap rows by fold side
 
 // The matrix loop over tap rows p in [pa, pb] and super-steps u in [ua, ub] for
 // NA tiles that share the Toeplitz operand.  Two operand sets are loaded
@@ -574,26 +573,21 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32(Geo<float> g, RegionS
           store_tile_from(g, I, J + MT, I0, J0, lane, acc1, dst);
           continue;
         }
-        if (kFoldSegments) {
-          // segments of p in increasing order, each loading only the sides it needs
-          int p = min(a1 <= b1 ? a1 : h + 1, a2 <= b2 ? a2 : h + 1);
-          const int p_top = max(a1 <= b1 ? b1 : -1, a2 <= b2 ? b2 : -1);
-          while (p <= p_top) {
-            const bool plus = a1 <= p && p <= b1, minus = a2 <= p && p <= b2;
-            int e = p_top;  // the segment ends before the next interval boundary
-            if (plus) e = min(e, b1);
-            else if (a1 > p && a1 <= b1) e = min(e, a1 - 1);
-            if (minus) e = min(e, b2);
-            else if (a2 > p && a2 <= b2) e = min(e, a2 - 1);
-            if (plus && minus) f32_steps<1, 0>(ab, bb, pitch, E, p, e, 0, nu - 1, acc);
-            else if (plus) f32_steps<1, 1>(ab, bb, pitch, E, p, e, 0, nu - 1, acc);
-            else if (minus) f32_steps<1, 2>(ab, bb, pitch, E, p, e, 0, nu - 1, acc);
-            p = e + 1;
-          }
-        } else {
-          const int pa = min(a1 <= b1 ? a1 : h + 1, a2 <= b2 ? a2 : h + 1);
-          const int pb = max(a1 <= b1 ? b1 : -1, a2 <= b2 ? b2 : -1);
-          f32_steps<1>(ab, bb, pitch, E, pa, pb, 0, nu - 1, acc);
+        // segments of p in increasing order, each loading only the fold sides it
+        // needs (the image holds only the rows these clipped ranges reach)
+        int p = min(a1 <= b1 ? a1 : h + 1, a2 <= b2 ? a2 : h + 1);
+        const int p_top = max(a1 <= b1 ? b1 : -1, a2 <= b2 ? b2 : -1);
+        while (p <= p_top) {
+          const bool plus = a1 <= p && p <= b1, minus = a2 <= p && p <= b2;
+          int e = p_top;  // the segment ends before the next interval boundary
+          if (plus) e = min(e, b1);
+          else if (a1 > p && a1 <= b1) e = min(e, a1 - 1);
+          if (minus) e = min(e, b2);
+          else if (a2 > p && a2 <= b2) e = min(e, a2 - 1);
+          if (plus && minus) f32_steps<1, 0>(ab, bb, pitch, E, p, e, 0, nu - 1, acc);
+          else if (plus) f32_steps<1, 1>(ab, bb, pitch, E, p, e, 0, nu - 1, acc);
+          else if (minus) f32_steps<1, 2>(ab, bb, pitch, E, p, e, 0, nu - 1, acc);
+          p = e + 1;
         }
         store_tile_from(g, I, J, I0, J0, lane, acc[0], dst);
       }
