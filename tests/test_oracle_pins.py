@@ -220,6 +220,38 @@ def test_density_matches_numpy_interp():
     np.testing.assert_allclose(oracle.hu_to_density(hu, hp, rp), np.interp(hu, hp, rp), rtol=0, atol=1e-14)
 
 
+# ----------------------------------------------------------------- §2.2.3 primary
+
+
+@pytest.mark.parametrize("wepl_mode", [oracle.WEPL_PER_RAY, oracle.WEPL_CENTRAL_AXIS])
+def test_primary_is_fluence_inverse_square_depth_dose(wepl_mode):
+    """Eq. 6 with the depth dose of each ray: P_k = F (SAD / d_k)^2 DD(W_k), d_k = d0 + k Dd
+    (the plane's distance from the source along the central axis).  DD is the table
+    linearly interpolated in W and clamped at both ends, which is numpy.interp over the
+    table's abscissae.  The table here is short and irregular so that rays run past its
+    end (upper clamp) and start in air at W = 0 (lower end), on a heterogeneous CT; W is
+    the oracle's own depth, pinned by the water closed form and the brute force."""
+    c = inputs.tiny_case(seed=31, n_cp=1, n_taps=3, shape=(7, 6, 8), spacing=9.0, field=30.0,
+                         wepl_mode=wepl_mode)
+    rng = np.random.default_rng(32)
+    c.machine.dd_step = 7.5
+    c.machine.dd = rng.uniform(0.2, 1.0, size=9)          # covers W in [0, 60] mm only
+    m = oracle.Model(c)
+    rho = oracle.density(m)
+    r = oracle.forward_cp(m, rho, c.gantry[0], c.leaves[0], c.jaws[0])
+    F, W, P = r["F"], r["W"], r["P"]
+    wtab = np.arange(len(c.machine.dd)) * c.machine.dd_step
+    d = m.d0 + np.arange(m.Nk) * c.depth_step
+    assert abs(m.d0 - (c.machine.sad - m.Nk // 2 * c.depth_step)) <= c.depth_step
+    expect = F[None] * (c.machine.sad / d[:, None, None]) ** 2 * np.interp(W, wtab, c.machine.dd)
+    lit = F > 0
+    assert lit.sum() > 20
+    assert np.any(W[:, lit] > wtab[-1]) and np.any(W[:, lit] == 0.0)
+    inner = (W > 0) & (W < wtab[-1])
+    assert inner[:, lit].sum() > 100
+    np.testing.assert_allclose(P, expect, rtol=1e-13, atol=0)
+
+
 # ----------------------------------------------------------------- §2.2.5 kernel
 
 
@@ -272,6 +304,72 @@ def test_kernel_radial_symmetry_and_depth_clamp():
     np.testing.assert_array_equal(K, K[::-1, :])
     np.testing.assert_array_equal(oracle.taps(m, 1000.0, -5.0), oracle.taps(m, 1000.0, 0.0))
     np.testing.assert_array_equal(oracle.taps(m, 1000.0, 900.0), oracle.taps(m, 1000.0, 700.0))
+
+
+def _kernel_params(c, z):
+    kp = np.asarray(c.machine.kpoly)
+    zc = min(max(z, 0.0), c.machine.kz_max)
+    return [sum(kp[r][q] * zc ** q for q in range(4)) for r in range(4)]
+
+
+@pytest.mark.parametrize("z", [0.0, 80.0, 350.0, 700.0, 900.0])
+@pytest.mark.parametrize("lat,d", [(3.0, 1000.0), (2.5, 850.0), (1.0, 1200.0), (5.0, 930.0)])
+def test_centre_tap_is_the_equal_area_disc_mass(z, lat, d):
+    """§2.2.5: the radial kernel has a 1/r singularity on the axis, so the centre tap is
+    the kernel's mass over the disc whose area equals one tap cell, delta^2 with
+    delta = lat d / SAD (radius delta / sqrt(pi)).  Integrated here numerically from the
+    radial mass density p(r) 2 pi r (scipy quad), not from the closed form the oracle
+    uses; a different disc radius or a dropped term changes it beyond 1e-12."""
+    c = _custom_case(n_taps=5, lat=lat)
+    m = oracle.Model(c)
+    K = oracle.taps(m, d, z)
+    A, a, B, b = _kernel_params(c, z)
+    norm = A / a + B / b
+    delta = lat * d / c.machine.sad
+    r0 = math.sqrt(delta * delta / math.pi)            # pi r0^2 = delta^2
+    mass, _ = scipy.integrate.quad(lambda r: (A * math.exp(-a * r) + B * math.exp(-b * r)) / norm,
+                                   0.0, r0, epsabs=1e-16, epsrel=1e-13)
+    assert abs(K[2, 2] - mass) <= 1e-12, (K[2, 2], mass)
+
+
+@pytest.mark.parametrize("z", [0.0, 200.0, 700.0])
+@pytest.mark.parametrize("lat", [1.0, 2.5, 3.0])
+def test_centre_tap_close_to_the_square_cell_mass(z, lat):
+    """The equal-area disc stands in for the square tap cell [-delta/2, delta/2]^2: the
+    two masses agree within 1 % at the workloads' spacings (the exact square mass from
+    the radial closed form of the outer tail plus a quadrature of the corners)."""
+    c = _custom_case(n_taps=5, lat=lat)
+    K = oracle.taps(oracle.Model(c), c.machine.sad, z)
+    A, a, B, b = _kernel_params(c, z)
+    sq = _square_integral(A, a, B, b, 0.5 * lat)
+    assert abs(K[2, 2] - sq) < 0.01 * sq, (K[2, 2], sq)
+
+
+def test_off_centre_taps_are_midpoint_cell_masses():
+    """Off the axis a tap is the kernel's value at the cell centre times the cell area
+    (midpoint rule).  Against a 2-D quadrature of p over the cells centred at fixed
+    points 3 to 4 mm from the axis (scipy dblquad) its error is that of the midpoint
+    rule: a few per cent at 1 mm spacing, falling with the square of the spacing."""
+    z = 50.0
+    errs = []
+    for lat in (1.0, 0.5):
+        c = _custom_case(n_taps=33, lat=lat)
+        K = oracle.taps(oracle.Model(c), c.machine.sad, z)
+        A, a, B, b = _kernel_params(c, z)
+        norm = A / a + B / b
+
+        def p(y, x):
+            r = math.hypot(x, y)
+            return (A * math.exp(-a * r) + B * math.exp(-b * r)) / (2.0 * math.pi * r * norm)
+        worst = 0.0
+        for (X, Y) in [(3.0, 0.0), (2.0, 2.0), (0.0, 4.0), (3.0, 1.0)]:
+            pp, qq = int(round(X / lat)), int(round(Y / lat))
+            cell, _ = scipy.integrate.dblquad(p, (qq - 0.5) * lat, (qq + 0.5) * lat,
+                                              (pp - 0.5) * lat, (pp + 0.5) * lat, epsabs=1e-14, epsrel=1e-12)
+            worst = max(worst, abs(K[16 + pp, 16 + qq] - cell) / cell)
+        errs.append(worst)
+    assert errs[0] < 0.03
+    assert errs[1] < 0.3 * errs[0]
 
 
 # ----------------------------------------------------------------- §2.2.6 convolution
