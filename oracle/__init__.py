@@ -47,6 +47,7 @@ class _Model(ctypes.Structure):
         ("kpoly", (ctypes.c_double * 4) * 4), ("kz_max", ctypes.c_double),
         ("fcorr", ctypes.c_int), ("pen_fwhm_u", ctypes.c_double), ("pen_fwhm_v", ctypes.c_double),
         ("hs_amp", ctypes.c_double), ("hs_sigma", ctypes.c_double), ("oar", ctypes.c_double * 2),
+        ("coll_rot", ctypes.c_int),
     ]
 
 
@@ -65,6 +66,7 @@ def _lib_handle():
             "or_hu_to_density": (None, [ctypes.c_long, _P, _P, I, _P, _P]),
             "or_raster": (None, [M, _P, _P, _P]),
             "or_fluence_correct": (None, [M, _P, _P, I]),
+            "or_rotate_fluence": (None, [M, D, _P, _P, I]),
             "or_rho_sample": (D, [M, _P, D, D, D]),
             "or_ca_depth": (None, [M, _P, D, _P]),
             "or_wepl": (None, [M, _P, D, _P]),
@@ -72,9 +74,9 @@ def _lib_handle():
             "or_conv_plane": (None, [I, I, I, _P, _P, _P]),
             "or_gather": (None, [M, D, _P, _P]),
             "or_scatter": (None, [M, D, _P, _P]),
-            "or_forward_cp": (None, [M, _P, D, _P, _P, _P, _P, _P, _P, _P, _P]),
-            "or_forward": (None, [M, _P, I, _P, _P, _P, _P, _P]),
-            "or_backward": (None, [M, _P, I, _P, _P, _P, _P, _P, _P, _P, _P]),
+            "or_forward_cp": (None, [M, _P, D, D, _P, _P, _P, _P, _P, _P, _P, _P]),
+            "or_forward": (None, [M, _P, I, _P, _P, _P, _P, _P, _P]),
+            "or_backward": (None, [M, _P, I, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
             "or_raster_backward": (None, [M, _P, _P, _P, _P, _P]),
             "or_project": (None, [I, I, _P, _P, _P, D, D, D, D, D]),
         }
@@ -100,7 +102,7 @@ def _ptr(a: np.ndarray):
 class Model:
     """The problem description the oracle needs, built from an inputs.Case."""
 
-    def __init__(self, case, n_taps=None, wepl_mode=None):
+    def __init__(self, case, n_taps=None, wepl_mode=None, coll_rot=None):
         m = case.machine
         nz, ny, nx = case.shape
         self.case = case
@@ -128,6 +130,9 @@ class Model:
         s.pen_fwhm_u, s.pen_fwhm_v = m.pen_fwhm_u, m.pen_fwhm_v
         s.hs_amp, s.hs_sigma = m.hs_amp, m.hs_sigma
         s.oar[:] = [float(m.oar[0]), float(m.oar[1])]
+        # a plan with collimator angles gets the square fan grid of the rotation
+        s.coll_rot = (1 if getattr(case, "collimator", None) is not None else 0) if coll_rot is None \
+            else (1 if coll_rot else 0)
         self.s = s
         dims = (ctypes.c_int * 3)()
         d0 = ctypes.c_double()
@@ -179,6 +184,14 @@ def fluence_correct(model: Model, F, transpose: bool = False) -> np.ndarray:
     return out
 
 
+def rotate_fluence(model: Model, coll_deg, F, transpose: bool = False) -> np.ndarray:
+    """Collimator rotation of one map [Nv][Nu] (or its transpose)."""
+    F = _f64(F)
+    out = np.empty_like(F)
+    _lib_handle().or_rotate_fluence(model.ref, float(coll_deg), _ptr(F), _ptr(out), 1 if transpose else 0)
+    return out
+
+
 def rho_sample(model: Model, rho, x, y, z) -> float:
     return _lib_handle().or_rho_sample(model.ref, _ptr(_f64(rho)), x, y, z)
 
@@ -221,8 +234,17 @@ def scatter(model: Model, gantry, g) -> np.ndarray:
     return out
 
 
-def forward_cp(model: Model, rho, gantry, leaves, jaws) -> dict:
-    """Every intermediate of one control point (fan arrays in [Nk][Nv][Nu])."""
+def _coll(coll, n):
+    if coll is None:
+        return None
+    c = _f64(coll).reshape(-1)
+    assert len(c) == n
+    return c
+
+
+def forward_cp(model: Model, rho, gantry, leaves, jaws, coll: float = 0.0) -> dict:
+    """Every intermediate of one control point (fan arrays in [Nk][Nv][Nu]; F in the
+    beam frame)."""
     r = {
         "F": np.empty((model.Nv, model.Nu)),
         "z": np.empty(model.Nk),
@@ -231,27 +253,30 @@ def forward_cp(model: Model, rho, gantry, leaves, jaws) -> dict:
         "Dfan": np.empty(model.fan_shape),
         "D": np.empty(model.vol_shape),
     }
-    _lib_handle().or_forward_cp(model.ref, _ptr(_f64(rho)), float(gantry), _ptr(_f64(leaves)),
+    _lib_handle().or_forward_cp(model.ref, _ptr(_f64(rho)), float(gantry), float(coll), _ptr(_f64(leaves)),
                                 _ptr(_f64(jaws)), _ptr(r["F"]), _ptr(r["z"]), _ptr(r["W"]), _ptr(r["P"]),
                                 _ptr(r["Dfan"]), _ptr(r["D"]))
     return r
 
 
-def forward(model: Model, rho, gantry, leaves, jaws, mu) -> np.ndarray:
+def forward(model: Model, rho, gantry, leaves, jaws, mu, coll=None) -> np.ndarray:
+    """Plan dose; coll = per-control-point collimator angles (None: all 0)."""
     gantry, leaves, jaws, mu = _f64(gantry), _f64(leaves), _f64(jaws), _f64(mu)
+    c = _coll(coll, len(gantry))
     dose = np.empty(model.vol_shape)
-    _lib_handle().or_forward(model.ref, _ptr(_f64(rho)), len(gantry), _ptr(gantry), _ptr(leaves),
+    _lib_handle().or_forward(model.ref, _ptr(_f64(rho)), len(gantry), _ptr(gantry), _ptr(c), _ptr(leaves),
                              _ptr(jaws), _ptr(mu), _ptr(dose))
     return dose
 
 
-def backward(model: Model, rho, gantry, leaves, jaws, mu, g):
+def backward(model: Model, rho, gantry, leaves, jaws, mu, g, coll=None):
     gantry, leaves, jaws, mu = _f64(gantry), _f64(leaves), _f64(jaws), _f64(mu)
     n = len(gantry)
+    c = _coll(coll, n)
     gl = np.empty((n, 2, model.n_leaf))
     gj = np.empty((n, 4))
     gm = np.empty(n)
-    _lib_handle().or_backward(model.ref, _ptr(_f64(rho)), n, _ptr(gantry), _ptr(leaves), _ptr(jaws),
+    _lib_handle().or_backward(model.ref, _ptr(_f64(rho)), n, _ptr(gantry), _ptr(c), _ptr(leaves), _ptr(jaws),
                               _ptr(mu), _ptr(_f64(g)), _ptr(gl), _ptr(gj), _ptr(gm))
     return gl, gj, gm
 

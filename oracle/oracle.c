@@ -124,15 +124,23 @@ static void trilinear_t(double* a, int n0, int n1, int n2, double c0, double c1,
 
 /* Fan grid covering the CT for every gantry angle:
  *   Nu = 2 ceil((F_u + h D) / D) + 1 (likewise Nv), h = (n - 1) / 2, so that the
- *   kernel's reach beyond the field edge stays on the grid;
+ *   kernel's reach beyond the field edge stays on the grid (with collimator rotation
+ *   F_u and F_v are both replaced by hypot(F_u, F_v));
  *   R = largest in-plane distance from the isocentre to a corner of the CT's
  *   voxel-edge box; planes d_k = SAD - R + k Dd, Nk = ceil(2R / Dd) + 1. */
 int or_fan_dims(const or_model* m, int dims[3], double* d0) {
   if (m->n_taps < 1 || (m->n_taps % 2) == 0 || m->lat_step <= 0 || m->depth_step <= 0) return -1;
   int h = (m->n_taps - 1) / 2;
   double D = m->lat_step;
-  dims[0] = 2 * (int)ceil((m->field_limit[0] + h * D) / D - 1e-9) + 1;
-  dims[1] = 2 * (int)ceil((m->field_limit[1] + h * D) / D - 1e-9) + 1;
+  if (m->coll_rot) {
+    /* any rotation of a jaw rectangle inside [-F_u, F_u] x [-F_v, F_v] stays within
+     * the radius hypot(F_u, F_v) of the central axis */
+    double F = hypot(m->field_limit[0], m->field_limit[1]);
+    dims[0] = dims[1] = 2 * (int)ceil((F + h * D) / D - 1e-9) + 1;
+  } else {
+    dims[0] = 2 * (int)ceil((m->field_limit[0] + h * D) / D - 1e-9) + 1;
+    dims[1] = 2 * (int)ceil((m->field_limit[1] + h * D) / D - 1e-9) + 1;
+  }
   double xs[2] = {m->ox - 0.5 * m->sx, m->ox + (m->nx - 0.5) * m->sx};
   double ys[2] = {m->oy - 0.5 * m->sy, m->oy + (m->ny - 0.5) * m->sy};
   double R = 0.0;
@@ -285,6 +293,38 @@ void or_fluence_correct(const or_model* m, const double* F, double* Fc, int tran
     blur_axis(Nu, Nv, gu, Ru, 0, a, Fc);
   }
   free(gu); free(gv); free(gh); free(a); free(b); free(c);
+}
+
+/* Bilinear sample of a [n1][n0] map at continuous index (c0, c1), zero padded. */
+static double bilinear(const double* a, int n0, int n1, double c0, double c1) {
+  return trilinear(a, n0, n1, 1, c0, c1, 0.0);
+}
+
+/* Collimator rotation of the fluence map (§2.2.2, last paragraph): the map rasterised
+ * in the collimator frame is turned about the central axis by the collimator angle
+ * before the rays are traced.  Beam-frame pixel (u, v) takes the collimator-frame map
+ * at (u', v') = (c u + s v, -s u + c v), sampled bilinearly between pixel centres
+ * (zero outside the grid); the transpose spreads each beam-frame value back onto the
+ * same four pixels with the same weights. */
+void or_rotate_fluence(const or_model* m, double coll_deg, const double* in, double* out, int transpose) {
+  int dims[3];
+  double d0;
+  or_fan_dims(m, dims, &d0);
+  int Nu = dims[0], Nv = dims[1];
+  double D = m->lat_step, cu = 0.5 * (Nu - 1), cv = 0.5 * (Nv - 1);
+  double sn, cs;
+  gantry_frame(coll_deg, &sn, &cs);
+  long plane = (long)Nu * Nv;
+  if (transpose) memset(out, 0, sizeof(double) * plane);
+  for (int j = 0; j < Nv; ++j)
+    for (int i = 0; i < Nu; ++i) {
+      double u = (i - cu) * D, v = (j - cv) * D;
+      double ur = cs * u + sn * v, vr = -sn * u + cs * v;
+      double ci = ur / D + cu, cj = vr / D + cv;
+      long q = (long)j * Nu + i;
+      if (!transpose) out[q] = bilinear(in, Nu, Nv, ci, cj);
+      else if (in[q] != 0.0) trilinear_t(out, Nu, Nv, 1, ci, cj, 0.0, in[q]);
+    }
 }
 
 double or_rho_sample(const or_model* m, const double* rho, double x, double y, double z) {
@@ -482,9 +522,9 @@ static void conv_volume(const or_model* m, const int dims[3], double d0, const d
   }
 }
 
-void or_forward_cp(const or_model* m, const double* rho, double gantry_deg, const double* leaves,
-                   const double* jaws, double* F_out, double* z_out, double* W_out, double* P_out,
-                   double* Dfan_out, double* Db_out) {
+void or_forward_cp(const or_model* m, const double* rho, double gantry_deg, double coll_deg,
+                   const double* leaves, const double* jaws, double* F_out, double* z_out, double* W_out,
+                   double* P_out, double* Dfan_out, double* Db_out) {
   int dims[3];
   double d0;
   or_fan_dims(m, dims, &d0);
@@ -501,6 +541,12 @@ void or_forward_cp(const or_model* m, const double* rho, double gantry_deg, cons
     or_fluence_correct(m, Fr, F, 0);
     free(Fr);
   }
+  if (m->coll_rot) {
+    double* Fr = (double*)malloc(sizeof(double) * plane);
+    memcpy(Fr, F, sizeof(double) * plane);
+    or_rotate_fluence(m, coll_deg, Fr, F, 0);
+    free(Fr);
+  }
   or_ca_depth(m, rho, gantry_deg, z);
   or_wepl(m, rho, gantry_deg, W);
   primary(m, dims, d0, F, W, P);
@@ -515,13 +561,14 @@ void or_forward_cp(const or_model* m, const double* rho, double gantry_deg, cons
 
 /* Dose accumulation (§2.2.7, Eq. 9): D = calib sum_b MU_b D_b, summed in control-point order. */
 void or_forward(const or_model* m, const double* rho, int n_cp, const double* gantry_deg,
-                const double* leaves, const double* jaws, const double* mu, double* dose) {
+                const double* coll_deg, const double* leaves, const double* jaws, const double* mu,
+                double* dose) {
   long nvox = (long)m->nx * m->ny * m->nz;
   double* Db = (double*)malloc(sizeof(double) * nvox);
   memset(dose, 0, sizeof(double) * nvox);
   for (int b = 0; b < n_cp; ++b) {
-    or_forward_cp(m, rho, gantry_deg[b], leaves + (long)b * 2 * m->n_leaf, jaws + (long)b * 4, NULL, NULL,
-                  NULL, NULL, NULL, Db);
+    or_forward_cp(m, rho, gantry_deg[b], coll_deg ? coll_deg[b] : 0.0, leaves + (long)b * 2 * m->n_leaf,
+                  jaws + (long)b * 4, NULL, NULL, NULL, NULL, NULL, Db);
     for (long x = 0; x < nvox; ++x) dose[x] += mu[b] * Db[x];
   }
   for (long x = 0; x < nvox; ++x) dose[x] *= m->calib;
@@ -573,8 +620,8 @@ void or_raster_backward(const or_model* m, const double* leaves, const double* j
  * same taps), A_ji = sum_k H_kji (SAD/d_k)^2 DD(W_kji), dL/dMU_b = calib <A, F>,
  * dL/dF = calib MU_b A, then the fluence-map chain rule. */
 void or_backward(const or_model* m, const double* rho, int n_cp, const double* gantry_deg,
-                 const double* leaves, const double* jaws, const double* mu, const double* g,
-                 double* gleaves, double* gjaws, double* gmu) {
+                 const double* coll_deg, const double* leaves, const double* jaws, const double* mu,
+                 const double* g, double* gleaves, double* gjaws, double* gmu) {
   int dims[3];
   double d0;
   or_fan_dims(m, dims, &d0);
@@ -600,16 +647,26 @@ void or_backward(const or_model* m, const double* rho, int n_cp, const double* g
       double c = (m->sad / dk) * (m->sad / dk);
       for (long r = 0; r < plane; ++r) A[r] += H[k * plane + r] * c * dd_lookup(m, W[k * plane + r]);
     }
-    /* dL/dMU = calib <A, Fc>; dL/dFc = calib MU A, carried to the aperture fluence by
-     * the corrections' adjoint and then to leaves and jaws */
+    /* dL/dMU = calib <A, R Fc> (Fc the corrected map, R the collimator rotation);
+     * dL/d(R Fc) = calib MU A, carried back through the rotation's transpose and the
+     * corrections' adjoint to the aperture fluence, then to leaves and jaws */
+    const double cb = coll_deg ? coll_deg[b] : 0.0;
     if (m->fcorr) {
       memcpy(gF, F, sizeof(double) * plane);
       or_fluence_correct(m, gF, F, 0);
+    }
+    if (m->coll_rot) {
+      memcpy(gF, F, sizeof(double) * plane);
+      or_rotate_fluence(m, cb, gF, F, 0);
     }
     double s = 0.0;
     for (long r = 0; r < plane; ++r) s += A[r] * F[r];
     gmu[b] = m->calib * s;
     for (long r = 0; r < plane; ++r) gF[r] = m->calib * mu[b] * A[r];
+    if (m->coll_rot) {
+      memcpy(A, gF, sizeof(double) * plane);
+      or_rotate_fluence(m, cb, A, gF, 1);
+    }
     if (m->fcorr) {
       memcpy(A, gF, sizeof(double) * plane);
       or_fluence_correct(m, A, gF, 1);

@@ -63,6 +63,11 @@ typedef struct {
   double hs_amp;           /* head scatter: F + hs_amp (G * F), G an isotropic unit-sum Gaussian ... */
   double hs_sigma;         /* ... of standard deviation hs_sigma, mm */
   double oar[2];           /* off-axis factor 1 + oar[0] r + oar[1] r^2, r = distance from the central axis, mm */
+  /* collimator rotation (§2.2.2, last paragraph): 0 = none (every control point at
+   * collimator angle 0, fan grid as for the jaws); 1 = the plan carries collimator
+   * angles, and the fan grid is square, large enough for any rotation of the jaw
+   * rectangle (half-extent hypot(F_u, F_v) plus the kernel's reach) */
+  int coll_rot;
 } or_model;
 
 /* Fan-grid sizes; returns 0 on success. dims = {Nu, Nv, Nk}. */
@@ -79,6 +84,13 @@ void or_raster(const or_model* m, const double* leaves, const double* jaws, doub
  * map [Nv][Nu], out of place; the identity copy when m->fcorr == 0.  transpose != 0
  * applies the adjoint (the same operators in reverse order). */
 void or_fluence_correct(const or_model* m, const double* F, double* Fc, int transpose);
+
+/* Collimator rotation (§2.2.2, last paragraph) of one map [Nv][Nu] about the central
+ * axis: Fb(u, v) = bilinear sample of Fc at (c u + s v, -s u + c v), zero outside the
+ * grid, with (s, c) = (sin, cos) of the collimator angle, so that a positive angle
+ * turns the aperture from e_u towards e_v.  transpose != 0 applies the adjoint
+ * (Fc <- R^T Fb).  Out of place. */
+void or_rotate_fluence(const or_model* m, double coll_deg, const double* in, double* out, int transpose);
 
 /* Density sample at a patient-frame point, trilinear with zero padding (§2.2.4). */
 double or_rho_sample(const or_model* m, const double* rho, double x, double y, double z);
@@ -101,19 +113,22 @@ void or_gather(const or_model* m, double gantry_deg, const double* Dfan, double*
 /* Transpose of or_gather: accumulates g into Ghat [Nk][Nv][Nu] (overwritten). */
 void or_scatter(const or_model* m, double gantry_deg, const double* g, double* Ghat);
 
-/* Intermediates of one control point; any output pointer may be NULL. */
-void or_forward_cp(const or_model* m, const double* rho, double gantry_deg, const double* leaves,
-                   const double* jaws, double* F, double* z, double* W, double* P, double* Dfan,
-                   double* Db);
+/* Intermediates of one control point; any output pointer may be NULL.  F is the fluence
+ * in the beam frame (after the corrections and the collimator rotation). */
+void or_forward_cp(const or_model* m, const double* rho, double gantry_deg, double coll_deg,
+                   const double* leaves, const double* jaws, double* F, double* z, double* W, double* P,
+                   double* Dfan, double* Db);
 
-/* Whole plan: dose = calib * sum_b MU_b * D_b (§2.2.7, Eq. 9); dose [nz][ny][nx] overwritten. */
+/* Whole plan: dose = calib * sum_b MU_b * D_b (§2.2.7, Eq. 9); dose [nz][ny][nx] overwritten.
+ * coll_deg [n_cp] may be NULL (all collimator angles 0). */
 void or_forward(const or_model* m, const double* rho, int n_cp, const double* gantry_deg,
-                const double* leaves, const double* jaws, const double* mu, double* dose);
+                const double* coll_deg, const double* leaves, const double* jaws, const double* mu,
+                double* dose);
 
 /* Gradient of L with dL/dD = g w.r.t. leaves [n_cp][2][L], jaws [n_cp][4], mu [n_cp]. */
 void or_backward(const or_model* m, const double* rho, int n_cp, const double* gantry_deg,
-                 const double* leaves, const double* jaws, const double* mu, const double* g,
-                 double* gleaves, double* gjaws, double* gmu);
+                 const double* coll_deg, const double* leaves, const double* jaws, const double* mu,
+                 const double* g, double* gleaves, double* gjaws, double* gmu);
 
 /* Backward of the fluence map of one control point: gF [Nv][Nu] -> gleaves [2][L], gjaws [4]. */
 void or_raster_backward(const or_model* m, const double* leaves, const double* jaws, const double* gF,

@@ -106,6 +106,7 @@ class Case:
     lat_step: Optional[float] = None
     depth_step: Optional[float] = None
     loss_w: Optional[np.ndarray] = None   # weights of L = sum w D
+    collimator: Optional[np.ndarray] = None   # float [n_cp] collimator angles; None = no collimator rotation
 
     def __post_init__(self):
         s = min(self.spacing)
