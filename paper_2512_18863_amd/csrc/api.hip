@@ -3,6 +3,9 @@
 // never allocates, frees or synchronises.
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <type_traits>
 #include <vector>
 
@@ -44,6 +47,22 @@ int prof_mark(hipStream_t s) {
 }
 
 void prof_record(const char* name, int a, int b) { prof().recs.push_back(ProfRec{name, a, b}); }
+
+hipError_t ensure_lds_limit(const void* kern, int bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> done;  // (device, kernel) -> limit set
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto key = std::make_pair(dev, kern);
+  auto it = done.find(key);
+  if (it != done.end() && it->second >= bytes) return hipSuccess;
+  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  done[key] = bytes;
+  return hipSuccess;
+}
 
 }  // namespace pdrt
 

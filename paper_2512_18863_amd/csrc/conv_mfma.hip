@@ -1068,11 +1068,9 @@ template <int NW, int TPW, int SUP>
 static hipError_t launch_f32_cfg(const Geo<float>& g, const RegionShape& rs, const F32Shape& fs, size_t lds, int nb,
                                  const int4* box, const float* z, const float* in, float* out, hipStream_t s) {
   const void* kern = (const void*)k_conv_mfma_f32<NW, TPW, SUP>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+  {
+    hipError_t e = ensure_lds_limit(kern, (int)LDS_MAX);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   if (lds > LDS_MAX) return hipErrorInvalidConfiguration;
   const int nreg = rs.regions_i * rs.regions_j;
@@ -1116,11 +1114,9 @@ template <int NW, int TPW>
 static hipError_t launch_f32_adj_cfg(const Geo<float>& g, const RegionShape& rs, const F32Shape& fs, int nb,
                                      const int4* box, const float* z, const float* in, float* out, hipStream_t s) {
   const void* kern = (const void*)k_conv_mfma_f32_adj<NW, TPW>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+  {
+    hipError_t e = ensure_lds_limit(kern, (int)LDS_MAX);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   const size_t lds = f32_adj_lds(g.h, fs, NW);
   if (lds > LDS_MAX) return hipErrorInvalidConfiguration;
@@ -1170,11 +1166,9 @@ static hipError_t launch_bf16_cfg(const Geo<float>& g, const BF16Shape& bs, size
     const size_t slots = bf16_tile_bytes(bs) + (size_t)(BQ * bs.RI / 2) * RJ * 1024 * sizeof(float);
     if (slots > lds) lds = slots;
   }
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+  {
+    hipError_t e = ensure_lds_limit(kern, (int)LDS_MAX);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   if (lds > LDS_MAX) return hipErrorInvalidConfiguration;
   const int nreg = bs.regions_i * bs.regions_j;

@@ -166,11 +166,9 @@ hipError_t launch_small_n(const Geo<float>& g, const SmallShape& ss, int nb, con
                           float* out, hipStream_t s) {
   const void* kern = (const void*)k_conv_small<N>;
   const size_t lds = small_lds(N, ss);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)SMALL_LDS_MAX);
+  {
+    hipError_t e = ensure_lds_limit(kern, (int)SMALL_LDS_MAX);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   const long n_items = (long)ss.bands * g.Nk * nb;
   if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;

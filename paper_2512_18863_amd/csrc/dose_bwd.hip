@@ -424,12 +424,9 @@ static hipError_t launch_bp_reg(const Geo<T>& g, int nb, const T* frame, const T
 template <typename T, int JS, int ZS>
 static hipError_t launch_bp(const Geo<T>& g, int nb, const T* frame, const T* g_t, T* Ghat, hipStream_t s) {
   const size_t lds = sizeof(BpLds<T, JS>);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_backproject_adj<T, JS, ZS>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  {
+    hipError_t e = ensure_lds_limit((const void*)k_backproject_adj<T, JS, ZS>, (int)lds);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   const int tiles_i = (g.Nu + BP_BT - 1) / BP_BT, tiles_k = (g.Nk + BP_BT - 1) / BP_BT;
   dim3 grid(tiles_i * tiles_k, nb);

@@ -447,12 +447,9 @@ template <typename T>
 hipError_t launch_conv_direct(const Geo<T>& g, int nb, const T* z, const T* in, T* out, hipStream_t s) {
   size_t lds = conv_direct_lds(g);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_conv_direct<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
+  {
+    hipError_t e = ensure_lds_limit((const void*)k_conv_direct<T>, 160 * 1024);
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   int tiles = ((g.Nu + DC_ROWS - 1) / DC_ROWS) * ((g.Nv + DC_COLS - 1) / DC_COLS);
   dim3 grid(tiles, g.Nk, nb);

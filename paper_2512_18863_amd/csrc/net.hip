@@ -636,12 +636,9 @@ template <int NT>
 static hipError_t launch_tiled(Vol v, ConvIO io, hipStream_t s) {
   const size_t lds = conv_tile_lds(io.c1 + io.c2);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_conv3d_tiled<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
+  {
+    hipError_t e = ensure_lds_limit((const void*)k_conv3d_tiled<NT>, 160 * 1024);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   const unsigned tiles = (unsigned)(((v.W + CT_W - 1) / CT_W) * ((v.H + CT_H - 1) / CT_H) * ((v.D + CT_D - 1) / CT_D));
   hipLaunchKernelGGL(k_conv3d_tiled<NT>, dim3(tiles), dim3(256), lds, s, v, io);

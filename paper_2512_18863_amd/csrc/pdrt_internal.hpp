@@ -60,6 +60,11 @@ struct Layout {
   int batch;
 };
 
+// Raises a kernel's dynamic-LDS limit to at least `bytes` on the current device.
+// Each (device, kernel) pair is set once, or again when a larger limit is asked
+// for; safe to call from several host threads.  Defined in api.hip.
+hipError_t ensure_lds_limit(const void* kern, int bytes);
+
 // --- launchers (defined in the kernel translation units) -------------------
 template <typename T>
 hipError_t launch_frame(const Geo<T>& g, const T* gantry_deg, int n_cp, T* frame, hipStream_t s);

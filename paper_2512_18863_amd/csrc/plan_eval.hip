@@ -269,13 +269,8 @@ int pdrt_dose_histogram(int64_t n_vox, const float* dose, const uint32_t* labels
                                  dim3(256), 0, s, cells, hist);
                return hipGetLastError();
              }());
-  static bool attr = false;
-  if (!attr) {
-    if (hipFuncSetAttribute((const void*)k_histogram, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(HIST_LDS_BINS * sizeof(uint32_t))) != hipSuccess)
-      return PDRT_E_HIP;
-    attr = true;
-  }
+  if (ensure_lds_limit((const void*)k_histogram, (int)(HIST_LDS_BINS * sizeof(uint32_t))) != hipSuccess)
+    return PDRT_E_HIP;
   const int grid = ev_grid(n_vox);
   const int per_pass = HIST_LDS_BINS / n_bins;
   for (int s0 = 0; s0 < n_struct; s0 += per_pass) {
