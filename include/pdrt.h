@@ -46,6 +46,7 @@ extern "C" {
 #define PDRT_E_WORKSPACE (-2)   /* workspace NULL or smaller than pdrt_workspace_bytes() */
 #define PDRT_E_HIP (-3)         /* a HIP launch or API call failed */
 #define PDRT_E_UNSUPPORTED (-4) /* valid request the library does not implement */
+#define PDRT_E_SCRATCH (-5)     /* problem larger than pdrt_dose_forward_noalloc's static scratch */
 
 #define PDRT_WEPL_PER_RAY 0      /* water-equivalent depth along every divergent ray */
 #define PDRT_WEPL_CENTRAL_AXIS 1 /* every ray takes the central-axis depth profile (§2.2.4) */
@@ -169,6 +170,27 @@ int pdrt_dose_backward(const pdrt_grid* grid, const float* rho, const pdrt_beam*
                        const float* jaws, const float* mu, const pdrt_kernel_spec* spec, const float* grad_dose,
                        float* grad_leaves, float* grad_jaws, float* grad_mu, void* ws, size_t ws_bytes,
                        void* stream);
+
+/* ---------------------------------------------------------------- allocation-free forward
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): pdrt_dose_forward with
+ * the workspace taken from a static device array of PDRT_NOALLOC_SCRATCH_BYTES
+ * (128 MiB) inside the library, one copy per device, held from the library's
+ * first use on that device until the process ends.  The control points are run
+ * in the largest batches whose forward workspace fits that array (at most
+ * spec->max_cp_batch when it is set); the dose is the same as pdrt_dose_forward's
+ * up to the grouping of the batches (the compensated sum over control points is
+ * carried across batches).  Arguments as for pdrt_dose_forward, without ws.
+ * Nothing in the scratch needs to start at zero: every call writes each part
+ * before it reads it.  The call allocates and frees nothing.
+ * Returns PDRT_E_SCRATCH when even one control point's workspace exceeds the
+ * scratch (for example a CT of more than about 16 M voxels), before anything is
+ * enqueued.  All calls on one device share its scratch: calls that overlap on
+ * one device (different streams or host threads without ordering) race. */
+#define PDRT_NOALLOC_SCRATCH_BYTES (128u << 20)
+int pdrt_dose_forward_noalloc(const pdrt_grid* grid, const float* rho, const pdrt_beam* beam,
+                              const float* leaves, const float* jaws, const float* mu,
+                              const pdrt_kernel_spec* spec, float* dose, void* stream);
 
 /* The forward in double precision throughout (for finite-difference checks):
  * every array argument is double, beam->gantry_deg and spec->dd point to

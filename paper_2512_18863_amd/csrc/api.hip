@@ -507,6 +507,30 @@ bool valid_limits(const pdrt_limits* lim) {
          std::isfinite(lim->w_min_mm) && lim->w_min_mm >= 0 && std::isfinite(lim->mu_min);
 }
 
+// ------------------------------------------------------------------ allocation-free forward
+// Device memory of pdrt_dose_forward_noalloc: one copy per device, held from the
+// library's first use on that device until the process ends.  Host code never
+// passes `scratch` itself to a kernel (on the host it names a stand-in, not the
+// device copy): it looks up each device's address once and uses that.
+static __device__ __align__(256) unsigned char scratch[PDRT_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device -> address of that device's scratch
+
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PDRT_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PDRT_E_HIP;
+    it = g_scratch_addr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return PDRT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -581,6 +605,34 @@ int pdrt_dose_backward(const pdrt_grid* grid, const float* rho, const pdrt_beam*
                        void* stream) {
   return backward_impl<float>(grid, rho, beam, leaves, jaws, mu, spec, grad_dose, grad_leaves, grad_jaws, grad_mu,
                               ws, ws_bytes, stream);
+}
+
+int pdrt_dose_forward_noalloc(const pdrt_grid* grid, const float* rho, const pdrt_beam* beam, const float* leaves,
+                              const float* jaws, const float* mu, const pdrt_kernel_spec* spec, float* dose,
+                              void* stream) {
+  if (!grid || !beam || !spec || !rho || !leaves || !jaws || !mu || !dose) return PDRT_E_INVALID;
+  // the largest control-point batch whose forward workspace fits the scratch
+  pdrt_kernel_spec sp = *spec;
+  Problem P;
+  sp.max_cp_batch = 1;
+  int st = size_problem(grid, beam, &sp, 0, 4, &P);
+  if (st != PDRT_OK) return st;
+  if (P.lay.total > (size_t)PDRT_NOALLOC_SCRATCH_BYTES) return PDRT_E_SCRATCH;
+  int lo = 1, hi = (spec->max_cp_batch > 0 && spec->max_cp_batch < beam->n_cp) ? spec->max_cp_batch : beam->n_cp;
+  while (lo < hi) {
+    int mid = lo + (hi - lo + 1) / 2;
+    sp.max_cp_batch = mid;
+    if (size_problem(grid, beam, &sp, 0, 4, &P) == PDRT_OK && P.lay.total <= (size_t)PDRT_NOALLOC_SCRATCH_BYTES)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  sp.max_cp_batch = lo;
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != PDRT_OK) return st;
+  return forward_impl<float>(grid, rho, beam, leaves, jaws, mu, &sp, dose, ws, (size_t)PDRT_NOALLOC_SCRATCH_BYTES,
+                             stream);
 }
 
 int pdrt_dose_forward_f64(const pdrt_grid* grid, const double* rho, const pdrt_beam* beam, const double* leaves,
@@ -737,6 +789,7 @@ const char* pdrt_status_string(int status) {
     case PDRT_E_WORKSPACE: return "workspace missing or too small";
     case PDRT_E_HIP: return "HIP launch or runtime error";
     case PDRT_E_UNSUPPORTED: return "unsupported request";
+    case PDRT_E_SCRATCH: return "problem too large for the allocation-free entry point's scratch";
     default: return "unknown status";
   }
 }

@@ -92,6 +92,8 @@ _SIGS = {
                                          ctypes.POINTER(Spec), _VP, _VP, ctypes.c_size_t, _VP]),
     "pdrt_dose_backward": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, ctypes.POINTER(Beam), _VP, _VP, _VP,
                                           ctypes.POINTER(Spec), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "pdrt_dose_forward_noalloc": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, ctypes.POINTER(Beam), _VP, _VP, _VP,
+                                                 ctypes.POINTER(Spec), _VP, _VP]),
     "pdrt_dose_forward_f64": (ctypes.c_int, [ctypes.POINTER(Grid), _VP, ctypes.POINTER(Beam), _VP, _VP, _VP,
                                              ctypes.POINTER(Spec), _VP, _VP, ctypes.c_size_t, _VP]),
     "pdrt_geometry_cache_bytes": (ctypes.c_size_t, [ctypes.POINTER(Grid), ctypes.POINTER(Beam),
@@ -295,6 +297,16 @@ class DoseEngine:
         _check(lib().pdrt_dose_forward(ctypes.byref(self.grid), self.rho.data_ptr(), ctypes.byref(self.beam), lp, jp,
                                        mp, ctypes.byref(self.spec), op, self.ws.data_ptr(), self.ws.numel(),
                                        _stream_ptr(self.device)), "pdrt_dose_forward")
+        return out
+
+    def forward_noalloc(self, leaves, jaws, mu, out: torch.Tensor) -> torch.Tensor:
+        """The forward through pdrt_dose_forward_noalloc: the library's static
+        scratch instead of this engine's workspace; `out` is caller-allocated."""
+        lp, jp, mp = self._ptrs(leaves, jaws, mu)
+        op = _dptr(out, torch.float32, self.device, self.vol_shape, "out")
+        _check(lib().pdrt_dose_forward_noalloc(ctypes.byref(self.grid), self.rho.data_ptr(), ctypes.byref(self.beam),
+                                               lp, jp, mp, ctypes.byref(self.spec), op, _stream_ptr(self.device)),
+               "pdrt_dose_forward_noalloc")
         return out
 
     def backward(self, leaves, jaws, mu, grad_dose):

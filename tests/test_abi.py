@@ -153,3 +153,21 @@ def test_invalid_arguments_rejected_on_host():
     lim.w_min_mm = float("nan")
     assert lib.pdrt_project_params(1, 60, 0x10, 0x10, 0x10, ctypes.byref(lim), 0x10, 0x10, 0x10, None) == -1
     assert lib.pdrt_hu_to_density(ctypes.byref(g), 0x10, 0x10, 1, None, None, None) == -1
+
+
+def test_noalloc_forward_rejects_on_host():
+    """The allocation-free forward refuses NULL arrays and a problem whose one-
+    control-point workspace exceeds its static scratch, before touching the GPU."""
+    case = inputs.config_c0()
+    g, b, s, _keep = _structs(case)
+    lib = E.lib()
+    r = lib.pdrt_dose_forward_noalloc(ctypes.byref(g), None, ctypes.byref(b), 0x10, 0x10, 0x10, ctypes.byref(s),
+                                      0x10, None)
+    assert r == -1
+    g.nx = g.ny = g.nz = 260        # 17.6 M voxels: the density copy and the compensation alone exceed 128 MiB
+    g.sx = g.sy = g.sz = 1.0
+    g.ox = g.oy = g.oz = -129.5
+    r = lib.pdrt_dose_forward_noalloc(ctypes.byref(g), 0x10, ctypes.byref(b), 0x10, 0x10, 0x10, ctypes.byref(s),
+                                      0x10, None)
+    assert r == -5
+    assert b"scratch" in lib.pdrt_status_string(-5)
