@@ -70,8 +70,18 @@ typedef struct {
   double ox, oy, oz;
 } pdrt_grid;
 
-/* Beam geometry shared by all control points (§2.2, beam parameter vector; the
- * collimator angle is fixed at 0). */
+/* Beam geometry shared by all control points (§2.2, beam parameter vector).
+ * Collimator rotation (§2.2.2, last paragraph): with collimator_deg == NULL every
+ * control point has collimator angle 0, leaves travel along e_u and the beam-frame
+ * grid spans the field limit along each axis.  With collimator_deg given, the
+ * fluence map of control point b is rasterised (and corrected) in its collimator
+ * frame and then turned about the central axis by collimator_deg[b]: beam-frame
+ * pixel (u, v) takes the collimator-frame map at (c u + s v, -s u + c v), (s, c) =
+ * (sin, cos) of the angle, sampled bilinearly between pixel centres with zero
+ * outside the grid (a positive angle turns the aperture from e_u towards z); the
+ * beam-frame grid is then square, with half-extent hypot(field_limit_mm[0],
+ * field_limit_mm[1]) plus the kernel's reach, so any rotation of the jaw rectangle
+ * stays on it.  The angles carry no gradient. */
 typedef struct {
   double sad_mm;               /* source-to-isocentre distance */
   double iso_mm[3];            /* isocentre in the patient frame */
@@ -80,6 +90,7 @@ typedef struct {
   int32_t n_cp;                /* number of control points, >= 1 */
   const void* gantry_deg;      /* device [n_cp]: float for the FP32 entry points, double for _f64 */
   double field_limit_mm[2];    /* largest |jaw| along e_u and z; fixes the beam-frame grid extent */
+  const void* collimator_deg;  /* device [n_cp] (float / double like gantry_deg) or NULL: collimator angles */
 } pdrt_beam;
 
 /* Dose model: kernel size, depth mode, convolution precision and machine tables. */
@@ -130,10 +141,13 @@ size_t pdrt_workspace_bytes(const pdrt_grid* grid, const pdrt_beam* beam, const 
  * P and Dfan ([B][Nk][Nu][Nv]), A ([B][Nu][Nv]), comp, the two fluence-correction
  * scratch maps fc_tmp (2 x [B][Nu][Nv], present only with fluence corrections) and
  * box (int32 [B][4]: each control point's aperture rectangle u0, u1, v0, v1 of fan
- * pixels outside which the fluence and its derivatives vanish); B = control points
- * per batch; the arrays hold the last batch. */
+ * pixels outside which the beam-frame fluence and its derivatives vanish), and with
+ * collimator angles cframe ([n_cp][2]: sin, cos of each angle) and rot ([B][Nu][Nv]:
+ * the beam-frame fluence after the rotation in a forward call; F then holds the
+ * collimator-frame map); B = control points per batch; the arrays hold the last
+ * batch.  Offsets of absent arrays equal the next one's. */
 typedef struct {
-  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, fc_tmp, box, total;
+  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, fc_tmp, box, cframe, rot, total;
   int32_t batch;
 } pdrt_ws_layout;
 int pdrt_workspace_layout(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spec* spec,

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdrt.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build", "pdrt")
 SOURCES = ["api.hip", "dose_fwd.hip", "dose_bwd.hip", "conv_mfma.hip", "conv_small.hip", "geometry_cache.hip",
-           "fluence_corr.hip", "plan_eval.hip", "net.hip", "net_api.hip"]
+           "fluence_corr.hip", "collimator.hip", "plan_eval.hip", "net.hip", "net_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

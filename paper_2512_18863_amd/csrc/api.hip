@@ -155,6 +155,13 @@ int size_problem(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel
   double D = spec->lateral_step_mm;
   double nu = 2.0 * std::ceil((beam->field_limit_mm[0] + h * D) / D - 1e-9) + 1.0;
   double nv = 2.0 * std::ceil((beam->field_limit_mm[1] + h * D) / D - 1e-9) + 1.0;
+  const bool rot = beam->collimator_deg != nullptr;
+  if (rot) {
+    // any rotation of a jaw rectangle inside the field limits stays within the
+    // radius hypot(F_u, F_v) of the central axis
+    const double F = std::hypot(beam->field_limit_mm[0], beam->field_limit_mm[1]);
+    nu = nv = 2.0 * std::ceil((F + h * D) / D - 1e-9) + 1.0;
+  }
   double xs[2] = {grid->ox - 0.5 * grid->sx, grid->ox + (grid->nx - 0.5) * grid->sx};
   double ys[2] = {grid->oy - 0.5 * grid->sy, grid->oy + (grid->ny - 0.5) * grid->sy};
   double R = 0.0;
@@ -197,6 +204,10 @@ int size_problem(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel
   if (spec->fluence_corr) off += align256((size_t)2 * B * plane * elem);
   L.box = off;
   off += align256((size_t)4 * B * sizeof(int));
+  L.cframe = off;
+  if (rot) off += align256((size_t)2 * beam->n_cp * elem);
+  L.rot = off;
+  if (rot) off += align256((size_t)B * plane * elem);
   L.total = off;
   return PDRT_OK;
 }
@@ -390,6 +401,10 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
   FcTaps<T> fct;
   if (g.fcorr) make_fc_taps<T>(spec, &fct);
   int* box = (int*)(w + P.lay.box);
+  // collimator rotation: F holds the collimator-frame map, Fb the beam-frame one
+  const bool rot = beam->collimator_deg != nullptr;
+  T* cframe = (T*)(w + P.lay.cframe);
+  T* Fb = rot ? (T*)(w + P.lay.rot) : F;
   // the corrections spread the aperture's fluence by their blur radii
   const int box_du = g.fcorr ? fct.pu.R + fct.hs.R : 0, box_dv = g.fcorr ? fct.pv.R + fct.hs.R : 0;
   // rays outside the box are skipped only when the convolution reads just the box
@@ -397,6 +412,7 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
   const T* dd = (const T*)spec->dd;
   const int L = beam->n_leaf_pairs, n_cp = beam->n_cp;
   LAUNCH("frame", launch_frame<T>(g, (const T*)beam->gantry_deg, n_cp, frame, s));
+  if (rot) LAUNCH("frame", launch_frame<T>(g, (const T*)beam->collimator_deg, n_cp, cframe, s));
   if (!gc) LAUNCH("transpose_rho", launch_transpose_rho<T>(g, rho, rho_t, s));
   for (int cp0 = 0; cp0 < n_cp; cp0 += P.batch) {
     int nb = n_cp - cp0 < P.batch ? n_cp - cp0 : P.batch;
@@ -411,18 +427,22 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
       LAUNCH("fluence_corr", launch_blur<T>(g, nb, 1, fct.hs, t0, F, s));
       LAUNCH("fluence_corr", launch_fcorr_combine<T>(g, nb, g.hs_amp, 1, t1, F, F, s));
     }
+    if (rot) {
+      LAUNCH("collimator", launch_rotate<T>(g, nb, cframe + 2 * cp0, F, Fb, 0, s));
+      LAUNCH("collimator", launch_collimator_box<T>(g, nb, cframe + 2 * cp0, box, s));
+    }
     const T* zb = z;
     if constexpr (std::is_same<T, float>::value) {
       if (gc) {
         zb = gc->z + (size_t)cp0 * g.Nk;
         LAUNCH("apply_geometry", gc->type == PDRT_CACHE_F32
-                                     ? apply_geometry<float>(g, nb, cp0, *gc, F, vol0, s, ray_box)
-                                     : apply_geometry<__bf16>(g, nb, cp0, *gc, F, vol0, s, ray_box));
+                                     ? apply_geometry<float>(g, nb, cp0, *gc, Fb, vol0, s, ray_box)
+                                     : apply_geometry<__bf16>(g, nb, cp0, *gc, Fb, vol0, s, ray_box));
       }
     }
     if (!gc) {
       LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
-      LAUNCH("march", launch_march<T>(g, nb, fr, rho_t, F, z, dd, vol0, s, ray_box));
+      LAUNCH("march", launch_march<T>(g, nb, fr, rho_t, Fb, z, dd, vol0, s, ray_box));
     }
     LAUNCH(conv_name<T>(g, spec->conv_mode),
            run_conv<T>(g, spec->conv_mode, nb, zb, vol0, vol1, s, box, CONV_IN_BOX));
@@ -456,6 +476,11 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
   FcTaps<T> fct;
   if (g.fcorr) make_fc_taps<T>(spec, &fct);
   int* box = (int*)(w + P.lay.box);
+  // collimator rotation: the march's adjoint gives dL/d(beam-frame map) in Ab, its
+  // transpose through the rotation the collimator-frame A the rest reads
+  const bool rot = beam->collimator_deg != nullptr;
+  T* cframe = (T*)(w + P.lay.cframe);
+  T* Ab = rot ? (T*)(w + P.lay.rot) : A;
   // the parameter gradients read A inside the aperture rectangle; the corrections'
   // adjoint gathers it from as far as their blur radii
   const int box_du = g.fcorr ? fct.pu.R + fct.hs.R : 0, box_dv = g.fcorr ? fct.pv.R + fct.hs.R : 0;
@@ -464,6 +489,7 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
   const T* dd = (const T*)spec->dd;
   const int L = beam->n_leaf_pairs, n_cp = beam->n_cp;
   LAUNCH("frame", launch_frame<T>(g, (const T*)beam->gantry_deg, n_cp, frame, s));
+  if (rot) LAUNCH("frame", launch_frame<T>(g, (const T*)beam->collimator_deg, n_cp, cframe, s));
   if (!gc) LAUNCH("transpose_rho", launch_transpose_rho<T>(g, rho, rho_t, s));
   LAUNCH("transpose_grad", launch_transpose_rho<T>(g, grad, g_t, s));
   for (int cp0 = 0; cp0 < n_cp; cp0 += P.batch) {
@@ -475,16 +501,18 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
     }
     if (!gc) LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
     LAUNCH("aperture_box", launch_aperture_box<T>(g, nb, jaws + (size_t)4 * cp0, box_du, box_dv, box, s));
+    if (rot) LAUNCH("collimator", launch_collimator_box<T>(g, nb, cframe + 2 * cp0, box, s));
     LAUNCH("backproject_adj", launch_backproject_adj<T>(g, nb, fr, g_t, vol0, s));
     LAUNCH(conv_name<T>(g, spec->conv_mode),
            run_conv<T>(g, spec->conv_mode, nb, zb, vol0, vol1, s, box, CONV_OUT_BOX));
     if constexpr (std::is_same<T, float>::value) {
       if (gc)
         LAUNCH("geometry_adjoint", gc->type == PDRT_CACHE_F32
-                                       ? geometry_adjoint<float>(g, nb, cp0, *gc, vol1, A, s, ray_box)
-                                       : geometry_adjoint<__bf16>(g, nb, cp0, *gc, vol1, A, s, ray_box));
+                                       ? geometry_adjoint<float>(g, nb, cp0, *gc, vol1, Ab, s, ray_box)
+                                       : geometry_adjoint<__bf16>(g, nb, cp0, *gc, vol1, Ab, s, ray_box));
     }
-    if (!gc) LAUNCH("march_adj", launch_march_adj<T>(g, nb, fr, rho_t, z, dd, vol1, A, s, ray_box));
+    if (!gc) LAUNCH("march_adj", launch_march_adj<T>(g, nb, fr, rho_t, z, dd, vol1, Ab, s, ray_box));
+    if (rot) LAUNCH("collimator", launch_rotate<T>(g, nb, cframe + 2 * cp0, Ab, A, 1, s));
     if (g.fcorr) {
       // A <- G_u G_v (X + a G_hu G_hv X), X = O A: the corrections' adjoint, so that
       // the parameter gradients see dL/d(aperture fluence)
@@ -571,6 +599,8 @@ int pdrt_workspace_layout(const pdrt_grid* grid, const pdrt_beam* beam, const pd
   out->comp = P.lay.comp;
   out->fc_tmp = P.lay.fc_tmp;
   out->box = P.lay.box;
+  out->cframe = P.lay.cframe;
+  out->rot = P.lay.rot;
   out->total = P.lay.total;
   out->batch = P.batch;
   return PDRT_OK;

@@ -56,7 +56,7 @@ struct BlurTaps {
 
 // Workspace layout (byte offsets) plus sizes, computed on the host.
 struct Layout {
-  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, fc_tmp, box, total;
+  size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, fc_tmp, box, cframe, rot, total;
   int batch;
 };
 
@@ -88,6 +88,12 @@ hipError_t launch_march_adj(const Geo<T>& g, int nb, const T* frame, const T* rh
 enum { CONV_DENSE = 0, CONV_IN_BOX = 1, CONV_OUT_BOX = 2 };
 template <typename T>
 hipError_t launch_aperture_box(const Geo<T>& g, int nb, const T* jaws, int du, int dv, int* box, hipStream_t s);
+// Collimator rotation of the fluence maps (adjoint != 0: its transpose) and of the
+// aperture rectangles; cframe = (sin, cos) of each control point's collimator angle.
+template <typename T>
+hipError_t launch_rotate(const Geo<T>& g, int nb, const T* cframe, const T* in, T* out, int adjoint, hipStream_t s);
+template <typename T>
+hipError_t launch_collimator_box(const Geo<T>& g, int nb, const T* cframe, int* box, hipStream_t s);
 
 // Plan-level geometry cache: G = (SAD/d)^2 DD(W) per beam-frame node (E = float or
 // __bf16), P = F G, and A = sum_k H_k G_k.

@@ -38,7 +38,7 @@ class Beam(ctypes.Structure):
     _fields_ = [("sad_mm", ctypes.c_double), ("iso_mm", ctypes.c_double * 3),
                 ("n_leaf_pairs", ctypes.c_int32), ("leaf_edges_mm", ctypes.POINTER(ctypes.c_double)),
                 ("n_cp", ctypes.c_int32), ("gantry_deg", ctypes.c_void_p),
-                ("field_limit_mm", ctypes.c_double * 2)]
+                ("field_limit_mm", ctypes.c_double * 2), ("collimator_deg", ctypes.c_void_p)]
 
 
 class Spec(ctypes.Structure):
@@ -63,7 +63,7 @@ def set_fluence_corrections(s: "Spec", m) -> None:
 class WsLayout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_size_t) for n in
                 ("frame", "rho_t", "fluence", "depth", "vol0", "vol1", "adj", "comp", "fc_tmp", "box",
-                 "total")] + \
+                 "cframe", "rot", "total")] + \
                [("batch", ctypes.c_int32)]
 
 
@@ -195,6 +195,11 @@ class DoseEngine:
         b.n_cp = self.n_cp
         b.gantry_deg = self.gantry32.data_ptr()
         b.field_limit_mm[:] = list(case.field_limit)
+        # collimator angles (None: all 0, no rotation)
+        self.coll32 = None
+        if getattr(case, "collimator", None) is not None:
+            self.coll32 = torch.tensor(np.asarray(case.collimator), dtype=torch.float32, device=dev)
+            b.collimator_deg = self.coll32.data_ptr()
         self.beam = b
         s = Spec()
         s.n_taps = case.n_taps if n_taps is None else n_taps
@@ -339,12 +344,16 @@ class DoseEngine:
         dd = torch.tensor(np.asarray(self.case.machine.dd), dtype=torch.float64, device=dev)
         b = Beam.from_buffer_copy(self.beam)
         b.gantry_deg = gantry.data_ptr()
+        coll = None
+        if self.coll32 is not None:
+            coll = torch.tensor(np.asarray(self.case.collimator), dtype=torch.float64, device=dev)
+            b.collimator_deg = coll.data_ptr()
         s = Spec.from_buffer_copy(self.spec)
         s.dd = dd.data_ptr()
         s.conv_mode = CONV_FP32
         nbytes = lib().pdrt_workspace_bytes(ctypes.byref(self.grid), ctypes.byref(b), ctypes.byref(s), 0, 8)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        self._f64 = {"gantry": gantry, "dd": dd, "beam": b, "spec": s, "ws": ws,
+        self._f64 = {"gantry": gantry, "dd": dd, "coll": coll, "beam": b, "spec": s, "ws": ws,
                      "rho": self.rho.to(torch.float64)}
 
     def set_density_f64(self, rho64: torch.Tensor):

@@ -171,3 +171,26 @@ def test_noalloc_forward_rejects_on_host():
                                       0x10, None)
     assert r == -5
     assert b"scratch" in lib.pdrt_status_string(-5)
+
+
+def test_collimator_grid_agrees_with_oracle():
+    """With collimator angles the beam-frame grid is square and holds any rotation of
+    the jaw rectangle; the library's sizing matches the oracle's, and the layout
+    gains the angles' sines and cosines and the beam-frame map."""
+    c = inputs.config_c1(n_cp=4)
+    c.collimator = np.array([0.0, 30.0, 90.0, -45.0])
+    g, b, s, _keep = _structs(c)
+    lib = E.lib()
+    dims = (ctypes.c_int32 * 3)()
+    d0 = ctypes.c_double()
+    plain = (ctypes.c_int32 * 3)()
+    assert lib.pdrt_fan_dims(ctypes.byref(g), ctypes.byref(b), ctypes.byref(s), plain, ctypes.byref(d0)) == 0
+    b.collimator_deg = 0x3000          # never dereferenced by host-only calls
+    assert lib.pdrt_fan_dims(ctypes.byref(g), ctypes.byref(b), ctypes.byref(s), dims, ctypes.byref(d0)) == 0
+    om = oracle.Model(c)
+    assert (dims[0], dims[1], dims[2]) == (om.Nu, om.Nv, om.Nk)
+    assert dims[0] == dims[1] > plain[0]
+    lay = E.WsLayout()
+    assert lib.pdrt_workspace_layout(ctypes.byref(g), ctypes.byref(b), ctypes.byref(s), 1, 4, ctypes.byref(lay)) == 0
+    assert lay.cframe >= lay.box and lay.rot - lay.cframe >= 2 * 4 * 4
+    assert lay.total - lay.rot >= 4 * dims[0] * dims[1] * 4

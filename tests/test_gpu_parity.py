@@ -49,7 +49,8 @@ def gpu_dose(case, conv="fp32", n_taps=None, wepl_mode=None, max_cp_batch=0, lea
 def oracle_dose(case, n_taps=None, wepl_mode=None):
     m = oracle.Model(case, n_taps=n_taps, wepl_mode=wepl_mode)
     rho = oracle.density(m)
-    return oracle.forward(m, rho, case.gantry, case.leaves, case.jaws, case.mu), m, rho
+    return oracle.forward(m, rho, case.gantry, case.leaves, case.jaws, case.mu,
+                          coll=getattr(case, "collimator", None)), m, rho
 
 
 def _rel_err(a, ref):
@@ -64,6 +65,8 @@ def subset(case, idx):
     c.leaves = case.leaves[idx]
     c.jaws = case.jaws[idx]
     c.mu = case.mu[idx]
+    if getattr(case, "collimator", None) is not None:
+        c.collimator = case.collimator[idx]
     return c
 
 
