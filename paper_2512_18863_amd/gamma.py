@@ -3,7 +3,8 @@
 gamma(x_r) = min over x_e of sqrt(|x_e - x_r|^2 / dta^2 + (D_e(x_e) - D_r(x_r))^2 / (dd * max D_r)^2),
 evaluated on reference voxels with D_r >= cutoff * max D_r.  A point farther than
 dta already gives gamma > 1, so the search is exactly confined to the dta ball;
-it is sampled on a lattice of step dta * step_frac with D_e trilinear, nearest
+it is sampled on a lattice of step dta * step_frac with D_e trilinear and zero
+outside the grid (the engine's own convention for samples past the CT), nearest
 points first, stopping at the first point with gamma <= 1.  Runs on the host
 (numpy / scipy): an evaluation tool, not part of the dose path.
 """
@@ -49,7 +50,7 @@ def pass_rate(ref: np.ndarray, ev: np.ndarray, spacing, dose_pct: float = 1.0, d
         for a in range(0, zz.size, chunk):
             b = min(zz.size, a + chunk)
             coords = np.stack([zz[a:b] + dz / sz, yy[a:b] + dy / sy, xx[a:b] + dx / sx])
-            val = scipy.ndimage.map_coordinates(ev, coords, order=1, mode="nearest")
+            val = scipy.ndimage.map_coordinates(ev, coords, order=1, mode="grid-constant", cval=0.0)
             still[a:b] = d2 + ((val - rr[a:b]) / tol) ** 2 > 1.0
         zz, yy, xx, rr = zz[still], yy[still], xx[still], rr[still]
     return 1.0 - zz.size / n_sel

@@ -374,8 +374,14 @@ class LearnedDose:
         self.dsmall = torch.empty(self.n, dtype=torch.float32, device=self.small.device)
         self.ddose = torch.empty(self.n, dtype=torch.float32, device=self.small.device)
         self.fell_back = False
+        self.generation = 0
 
     def forward(self, lv, jw, mu):
+        """The dose of (lv, jw, mu) as a new tensor.  The network keeps this call's
+        activations (and the fallback decision) for `backward`, which therefore
+        always differentiates the most recent forward; `self.generation` numbers
+        the forwards so a caller can check the pairing (backward(..., generation=g))."""
+        self.generation += 1
         lib, s = _lib(), torch.cuda.current_stream().cuda_stream
         self.small.forward(lv, jw, mu, out=self.dsmall.view(*self.shape))
         pred, resid = self.net.forward(self.dsmall, self.small.rho.reshape(-1))
@@ -389,10 +395,15 @@ class LearnedDose:
         if self.fell_back:
             return self.large.forward(lv, jw, mu)
         _ck(lib.pdrt_scale_by(self.n, _p(pred), _p(self.net.scale), 1, _p(self.out), s), "scale")
-        return self.out.view(*self.shape)
+        return self.out.view(*self.shape).clone()
 
-    def backward(self, lv, jw, mu, g):
-        """Gradient of L with dL/d dose = g through the path the forward took."""
+    def backward(self, lv, jw, mu, g, generation=None):
+        """Gradient of L with dL/d dose = g through the path the most recent forward
+        took (the network's activations are that forward's); with `generation` given,
+        raises if a later forward has replaced them."""
+        if generation is not None and generation != self.generation:
+            raise RuntimeError("LearnedDose.backward: forward %d was followed by forward %d; the network holds "
+                               "the activations of the latest one only" % (generation, self.generation))
         if self.fell_back:
             return self.large.backward(lv, jw, mu, g)
         lib, s = _lib(), torch.cuda.current_stream().cuda_stream

@@ -144,7 +144,7 @@ class PlanOptimizer:
     def run(self, steps: int):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        losses = [float(self.step()) for _ in range(steps)]
+        losses = [float(self.step().detach()) for _ in range(steps)]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         return losses, dt / max(steps, 1)

@@ -70,14 +70,35 @@ def test_profile_half_value_at_field_edge():
     1 -> 1/2 -> 0 there.  A kernel symmetric in u then gives exactly half of the
     central value at the edge (the taps left and right of the edge column weigh the
     same), up to the slight lateral variation of the primary at the isocentre plane."""
+    from paper_2512_18863_amd import calibration
     case, (ix, j, iz, w), dose, _ = _oracle_reference()
+    x, prof = calibration.lateral_profile(dose, case, 100.0)
     row = (1 - w) * dose[iz, j, :] + w * dose[iz, j + 1, :]
-    x = case.origin[0] + np.arange(row.size) * SP
-    prof = row / row[ix]
+    np.testing.assert_allclose(prof, row / row[ix], rtol=1e-14, atol=0)
+    assert x[ix] == pytest.approx(0.0)
     for edge in (-50.0, 50.0):
         assert np.interp(edge, x, prof) == pytest.approx(0.5, abs=2e-3)
     assert prof[np.abs(x) <= 20].min() > 0.99          # flat inside the field
     assert np.all(prof[np.abs(x) >= 50 + 0.5 * TAPS * SP + SP] == 0.0)   # beyond the jaws and the kernel
+
+
+def test_central_axis_pdd():
+    """The PDD helper on the oracle's reference dose: normalised to 1 at its maximum,
+    depths measured from the entrance face, its value at 100 mm is the reference
+    dose over the central-axis maximum (the same linear interpolation in depth), the
+    maximum lies in the build-up region of the depth-dose table (d_max about 23 mm
+    in water, within a voxel and the inverse square's pull) and beyond it the curve
+    falls monotonically to the phantom's exit."""
+    from paper_2512_18863_amd import calibration
+    case, ref, dose, d_ref = _oracle_reference()
+    depth, pdd = calibration.central_axis_pdd(dose, case)
+    assert pdd.max() == 1.0 and depth[0] == pytest.approx(0.5 * SP)
+    ix, j, iz, w = ref
+    axis = dose[iz, :, ix]
+    assert np.interp(100.0, depth, pdd) == pytest.approx(d_ref / axis.max(), rel=1e-12)
+    k = int(np.argmax(pdd))
+    assert 10.0 <= depth[k] <= 35.0
+    assert np.all(np.diff(pdd[k + 1:]) < 0)
 
 
 @pytest.mark.gpu

@@ -133,6 +133,31 @@ def test_c1_gradient_parity():
     _check("mu", gm, rm)
 
 
+def test_full_plan_c4bench_backward_in_bench_configuration():
+    """The 180-control-point 128^3 plan with the 61 x 61 kernel, backward in the
+    launch configuration the benchmark times (whole plan in one batch, the
+    benchmark's loss weights); the gradients of six control points spread over both
+    arcs against the oracle's backward of those control points (gradients are per
+    control point, so the oracle needs only those six).  FP32 <= 1e-4 of max|g| per
+    group; the BF16 convolution <= 2^-8 (its arithmetic bound), stated per group."""
+    from paper_2512_18863_amd.engine import DoseEngine
+    c = inputs.config_c4_plan(2000, bench=True)
+    w = np.random.default_rng(4001).uniform(0.0, 1.0, size=c.shape)
+    idx = np.array([3, 60, 91, 122, 150, 177])
+    _say("C4-bench full-plan backward (180 CPs, n=61); oracle on CPs %s" % list(idx))
+    rl, rj, rm = _grads_oracle(subset(c, idx), w)
+    for conv, tol in (("fp32", TOL_GRAD), ("bf16", 2.0 ** -8)):
+        eng = DoseEngine(c, conv=conv)
+        g = [t.cpu().numpy() for t in eng.backward(_t(c.leaves), _t(c.jaws), _t(c.mu), _t(w))]
+        del eng
+        torch.cuda.empty_cache()
+        assert all(np.isfinite(x).all() for x in g)
+        for name, got, ref in zip(("leaves", "jaws", "mu"), g, (rl, rj, rm)):
+            e = np.abs(got[idx] - ref).max() / np.abs(ref).max()
+            _say("%s full plan, %s: max|dg|/max|g| = %.3e" % (conv, name, e))
+            assert e <= tol, (conv, name)
+
+
 def test_c4bench_gradient_parity_subset():
     _say("C4-bench gradients n=61, 3 CPs")
     c = subset(inputs.config_c4_plan(2000, bench=True), np.array([10, 80, 140]))
@@ -175,10 +200,14 @@ def _fd_edges(case, n_edges, seed, h):
     return out[:n_edges]
 
 
-def test_c2_fd_fp64_vs_adjoint_vs_oracle():
+def test_c2_fd_fp64_vs_adjoints_vs_oracle():
     """64 leaf edges of the two-arc C2 plan (16 control points drawn by seed 2004):
     GPU FP64 central differences (h = 0.01 mm) vs the oracle gradient vs the GPU FP32
-    adjoint."""
+    and BF16 adjoints.  The BF16 bar is derived from its arithmetic: the adjoint
+    convolution multiplies BF16-rounded operands (relative error <= 2 * 2^-9 per
+    product) with non-negative taps and a non-negative dose gradient, so every H,
+    A and leaf / jaw / MU gradient carries at most 2^-8 relative error (FP32
+    accumulation adds far less); the error is stated per group."""
     from paper_2512_18863_amd.engine import DoseEngine
     h = 0.01
     full = inputs.config_c2()
@@ -195,6 +224,13 @@ def test_c2_fd_fp64_vs_adjoint_vs_oracle():
     rl, rj, rm = oracle.backward(m, rho, c.gantry, c.leaves, c.jaws, c.mu, w)
     gl, _, _ = eng.backward(_t(c.leaves), _t(c.jaws), _t(c.mu), _t(w))
     gl = gl.cpu().numpy()
+    e16 = DoseEngine(c, conv="bf16")
+    b16 = [x.cpu().numpy() for x in e16.backward(_t(c.leaves), _t(c.jaws), _t(c.mu), _t(w))]
+    del e16
+    for name, got, ref in zip(("leaves", "jaws", "mu"), b16, (rl, rj, rm)):
+        e = np.abs(got - ref).max() / np.abs(ref).max()
+        _say("C2 bf16 adjoint vs oracle, %s: max|dg|/max|g| = %.3e" % (name, e))
+        assert e <= 2.0 ** -8, name
     lv = _t(c.leaves, torch.float64)
     jw = _t(c.jaws, torch.float64)
     mu = _t(c.mu, torch.float64)

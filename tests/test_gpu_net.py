@@ -309,3 +309,35 @@ def test_learned_dose_gradient_matches_torch_autograd():
     lhs = float((got.double() * ds_h.double()).sum())
     rhs = float((g_h.double() * out.cpu().double()).sum())
     assert abs(lhs - rhs) <= 1e-4 * float((g_h.abs().double() * out.cpu().abs().double()).sum())
+
+
+def test_learned_held_out_plans_vs_plain_61():
+    """Ten held-out plans (indices 2000-2009, never trained on: training used 0-1999)
+    with their own randomised 128^3 pelvis, 60-180 control points and jaws 20-50 mm:
+    the learned dose (9 x 9 engine + network, fallback rule live) against the plain
+    61 x 61 FP32 dose, the judge of its error.  Bar: 1 %/1 mm global gamma >= 99.5 %
+    (10 % threshold); the maximum error, the network's own error estimate and the
+    fallback decision are stated per plan."""
+    import os
+    from paper_2512_18863_amd import engine as E
+    from paper_2512_18863_amd import gamma, inputs, learned
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2512_18863_amd", "data",
+                        "learned_c4.npz")
+    net = learned.Net3D.from_file(path, (128, 128, 128))
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    for p in range(2000, 2010):
+        case = inputs.config_c4_plan(p, n_taps=61)
+        lv, jw, mu = t(case.leaves), t(case.jaws), t(case.mu)
+        ld = learned.LearnedDose(net, case, mode="auto")
+        out = ld.forward(lv, jw, mu).cpu().numpy().astype(np.float64)
+        st = net.stats.cpu().numpy()
+        plain = E.DoseEngine(case, n_taps=61).forward(lv, jw, mu).cpu().numpy().astype(np.float64)
+        err = float(np.abs(out - plain).max() / plain.max())
+        gp = gamma.pass_rate(plain, out, case.spacing, 1.0, 1.0)
+        _say("held-out plan %d (%d CPs, jaws %.0f x %.0f mm): fallback %s, estimate %.2e, max|dD|/maxD %.3e, "
+             "gamma(1%%/1mm) %.4f %%" % (p, case.n_cp, 2 * case.jaws[0, 1], 2 * case.jaws[0, 3], ld.fell_back,
+                                         st[1] / st[0], err, 100 * gp))
+        assert gp >= 0.995, p
+        assert err <= 0.02, p
+        del ld
+        torch.cuda.empty_cache()

@@ -4,8 +4,8 @@ the paper's weighted L1 objective (coarse-to-fine kernel sizes on geometry
 caches, weight selection by isodose Dice).  Also checks the projection layer
 against the oracle's projection (seeded inputs) and its Jacobian against finite
 differences.  The optimised plans are checked by properties (objective decrease,
-feasibility, Dice); the dose path's parity with the oracle is covered on seeded
-inputs elsewhere."""
+feasibility, Dice), and the 200-step plan's final dose and objective against the
+oracle's recomputation from the same projected parameters."""
 import numpy as np
 import pytest
 import torch
@@ -73,6 +73,22 @@ def test_c3_optimisation_200_steps():
     for a, b in zip(again, (lv, jw, mu)):
         np.testing.assert_allclose(a.cpu().numpy(), b, rtol=0, atol=2e-5)
     assert (lv[:, 1] - lv[:, 0] >= opt.limits["w_min"] - 1e-4).all() and (mu >= opt.limits["mu_min"] - 1e-6).all()
+    # the final plan's dose and objective recomputed by the oracle from the projected
+    # parameters (plain inputs to both paths: the oracle takes nothing else from the
+    # GPU).  Dose bar: 1e-5 of max dose.  Objective: with delta = max|D_gpu - D_oracle|
+    # each of the three terms T (a mean of squares) moves by at most 2 delta sqrt(T) +
+    # delta^2, so |dL| <= 2 delta sqrt(3 L) + 3 delta^2 (Cauchy-Schwarz over the terms).
+    _say("C3: oracle recomputes the final dose of all %d control points" % case.n_cp)
+    m = oracle.Model(case)
+    ref = oracle.forward(m, oracle.density(m), case.gantry, lv, jw, mu)
+    got = dose.cpu().numpy().astype(np.float64)
+    delta = float(np.abs(got - ref).max())
+    L_ref = float(optimize.objective(torch.tensor(ref), {k: torch.tensor(v) for k, v in masks.items()}))
+    bound = 2.0 * delta * np.sqrt(3.0 * L_ref) + 3.0 * delta ** 2 + 1e-6 * L_ref
+    _say("C3 final: max|dD|/maxD = %.3e, L(gpu) = %.6f, L(oracle dose) = %.6f, |dL| = %.2e (bound %.2e)"
+         % (delta / ref.max(), L_end, L_ref, abs(L_end - L_ref), bound))
+    assert delta <= 1e-5 * ref.max()
+    assert abs(L_end - L_ref) <= bound
 
 
 def test_c3_l1_objective_coarse_to_fine_with_cache():
