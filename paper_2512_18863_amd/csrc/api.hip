@@ -310,11 +310,11 @@ hipError_t run_conv<float>(const Geo<float>& g, int conv_mode, int nb, const flo
 }
 
 template <typename T>
-const char* conv_name(const Geo<T>& g, int conv_mode);
+const char* conv_name(const Geo<T>& g, int conv_mode, int adjoint);
 
 template <>
-const char* conv_name<double>(const Geo<double>&, int) {
-  return "conv_direct_f64";
+const char* conv_name<double>(const Geo<double>&, int, int adjoint) {
+  return adjoint ? "conv_direct_f64_adj" : "conv_direct_f64";
 }
 
 // The matrix-core convolutions honour the aperture box (inputs read, outputs
@@ -325,10 +325,11 @@ bool conv_uses_box(const Geo<T>& g, int conv_mode) {
 }
 
 template <>
-const char* conv_name<float>(const Geo<float>& g, int conv_mode) {
-  if (conv_mode == PDRT_CONV_BF16) return "conv_mfma_bf16";
-  if (g.n_taps >= kMfmaMinTaps) return "conv_mfma_f32";
-  return conv_small_supported(g) ? "conv_small_f32" : "conv_direct_f32";
+const char* conv_name<float>(const Geo<float>& g, int conv_mode, int adjoint) {
+  if (conv_mode == PDRT_CONV_BF16) return adjoint ? "conv_mfma_bf16_adj" : "conv_mfma_bf16";
+  if (g.n_taps >= kMfmaMinTaps) return adjoint ? "conv_mfma_f32_adj" : "conv_mfma_f32";
+  if (conv_small_supported(g)) return adjoint ? "conv_small_f32_adj" : "conv_small_f32";
+  return adjoint ? "conv_direct_f32_adj" : "conv_direct_f32";
 }
 
 // Plan-level geometry cache: z [n_cp][Nk] float at offset 0, then G [n_cp][Nk][Nu][Nv]
@@ -444,7 +445,7 @@ int forward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, con
       LAUNCH("ca_depth", launch_ca_depth<T>(g, nb, fr, rho_t, z, s));
       LAUNCH("march", launch_march<T>(g, nb, fr, rho_t, Fb, z, dd, vol0, s, ray_box));
     }
-    LAUNCH(conv_name<T>(g, spec->conv_mode),
+    LAUNCH(conv_name<T>(g, spec->conv_mode, 0),
            run_conv<T>(g, spec->conv_mode, nb, zb, vol0, vol1, s, box, CONV_IN_BOX));
     LAUNCH("gather", launch_gather<T>(g, nb, cp0 == 0, cp0 + nb == n_cp, fr, mu + cp0, vol1, dose, comp, s));
   }
@@ -503,7 +504,7 @@ int backward_impl(const pdrt_grid* grid, const T* rho, const pdrt_beam* beam, co
     LAUNCH("aperture_box", launch_aperture_box<T>(g, nb, jaws + (size_t)4 * cp0, box_du, box_dv, box, s));
     if (rot) LAUNCH("collimator", launch_collimator_box<T>(g, nb, cframe + 2 * cp0, box, s));
     LAUNCH("backproject_adj", launch_backproject_adj<T>(g, nb, fr, g_t, vol0, s));
-    LAUNCH(conv_name<T>(g, spec->conv_mode),
+    LAUNCH(conv_name<T>(g, spec->conv_mode, 1),
            run_conv<T>(g, spec->conv_mode, nb, zb, vol0, vol1, s, box, CONV_OUT_BOX));
     if constexpr (std::is_same<T, float>::value) {
       if (gc)

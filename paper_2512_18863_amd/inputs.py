@@ -275,6 +275,21 @@ def config_c2(n_cp: int = 180) -> Case:
                 mu, 31, (40.0, 40.0), m, loss_w=w)
 
 
+def config_p0() -> Case:
+    """The paper's timing shape (Table 6: a 105 x 224 x 224 dose grid, 180 control
+    points, kernel 55; the voxel size is not printed and is taken as 2 mm): a pelvis
+    224 x 224 x 105 at 2 mm, two arcs of 180 control points, 60 leaf pairs of 5 mm,
+    jaws +-40 mm, 55 x 55 kernel."""
+    m = Machine(n_leaf=60, leaf_width=5.0)
+    hu, sp, origin = pelvis_phantom((105, 224, 224), 2.0, seed=5001)
+    gantry = arc_angles(180, two_arcs=True)
+    leaves = random_apertures(180, 60, 40.0, seed=5002)
+    mu = random_mu(180, seed=5003)
+    w = np.random.default_rng(5004).uniform(0.0, 1.0, size=hu.shape)
+    return Case("P0", hu, sp, origin, (0.0, 0.0, 0.0), gantry, leaves, jaws_square(180, 40.0, 40.0),
+                mu, 55, (40.0, 40.0), m, loss_w=w)
+
+
 def config_c4_plan(p: int, n_taps: int = 61, bench: bool = False) -> Case:
     """Randomised pelvis 128^3 at 3 mm with a random VMAT plan (plan index p, seed
     4000 + p).  bench=True forces 180 control points on two arcs and jaws +-40 mm."""
