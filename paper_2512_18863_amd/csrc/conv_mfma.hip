@@ -1,5 +1,5 @@
 // conv_mfma.hip — the per-plane lateral convolution (arXiv:2512.18863 §2.2.6,
-// Eq. 8) on the CDNA4 matrix cores.
+// Eq. 8) in FP32 on the CDNA4 matrix cores (the BF16 variant is conv_bf16.hip).
 //
 // For one plane, out[i][j] = sum_{p,q} K[p][q] in[i+p][j+q] (zero padded).  Fixing
 // the tap row p, the sum over q is a product with a banded Toeplitz matrix:
@@ -16,20 +16,14 @@
 // of step t+1 are loaded from LDS before the matrix instructions of step t are
 // issued.
 //
-//   FP32: v_mfma_f32_16x16x4_f32.  Tap rows p and -p are equal (the kernel is
-//         radially symmetric), so rows i+p and i-p are added before the product
-//         and only h+1 tap rows are multiplied (row 0 with halved taps).
-//   BF16: v_mfma_f32_32x32x16_bf16, operands rounded to BF16 (round to nearest
-//         even), FP32 accumulation; all n tap rows (see the BF16 section).  Each
-//         lane's eight Toeplitz entries are one aligned 16-byte LDS read from one
-//         of eight copies of the tap row, shifted so that every lane's run starts
-//         on a 16-byte boundary.
+// v_mfma_f32_16x16x4_f32.  Tap rows p and -p are equal (the kernel is radially
+// symmetric), so rows i+p and i-p are added before the product and only h+1 tap
+// rows are multiplied (row 0 with halved taps).
 #include "conv_common.hpp"
 
 namespace pdrt {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int MT = 16;      // MFMA output tile edge
 constexpr int RMAX = 6;     // region edge in tiles
@@ -717,349 +711,6 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32_adj(Geo<float> g, Reg
   }
 }
 
-// ------------------------------------------------------------------ BF16
-//
-// v_mfma_f32_32x32x16_bf16 on 32 x 32 output tiles.  A wavefront owns one strip
-// of RJ tiles side by side (32 rows x 32 RJ columns) and a quarter of the tap
-// rows p; its four partial sums are added in LDS at the end (fixed order).  For
-// tile t at K-step s the input column block is a = 2 t + s (16 columns each), so
-// per tap row the strip loads 2 RJ + S - 2 distinct A fragments and S Toeplitz
-// fragments and issues RJ * S matrix instructions: each 1 KB A fragment feeds up
-// to RJ instructions.
-
-constexpr int BQ = 4;  // wavefronts sharing one strip (tap rows split in quarters)
-
-struct BF16Shape {
-  int S;       // K-steps of 16 input columns: ceil((32 + 2h) / 16)
-  int CL;      // length of one shifted tap-row copy: 16 S + 40 (a multiple of 8)
-  int rows, pitch;
-  int RI, RJ;  // strips per region, 32-wide tiles per strip
-  int regions_i, regions_j;
-};
-
-static BF16Shape bf16_shape(int Nu, int Nv, int h, int rmax) {
-  BF16Shape s;
-  int ti = (Nu + 31) / 32, tj = (Nv + 31) / 32;
-  s.S = (32 + 2 * h + 15) / 16;
-  const int rj_max = s.S <= 6 ? 3 : 2;  // three tiles per strip only while the registers hold them
-  s.RI = ti < rmax ? ti : rmax;
-  s.RJ = tj < rj_max ? tj : rj_max;
-  s.regions_i = (ti + s.RI - 1) / s.RI;
-  s.regions_j = (tj + s.RJ - 1) / s.RJ;
-  s.CL = 16 * s.S + 40;
-  s.rows = 32 * s.RI + 2 * h;
-  s.pitch = 16 * (2 * s.RJ + s.S - 2) + 8;
-  return s;
-}
-
-__host__ __device__ static size_t bf16_tile_bytes(const BF16Shape& bs) {
-  return ((size_t)bs.rows * bs.pitch * 2 + 15) & ~(size_t)15;
-}
-__host__ __device__ static size_t bf16_copy_bytes(int h, const BF16Shape& bs) { return (size_t)(h + 1) * 8 * bs.CL * 2; }
-// One padded BF16 tap row per p: positions x = -8 .. CL + 7 of the extended row
-// (x = q + h + 31) at index x + 8, zero outside |q| <= h; the shifted copies are
-// cut from it.
-__host__ __device__ static int bf16_ext_len(const BF16Shape& bs) { return bs.CL + 16; }
-__host__ __device__ static size_t bf16_kq_end(int h, const BF16Shape& bs) {
-  return (bf16_copy_bytes(h, bs) + sizeof(float) * (size_t)(h + 1) * (h + 1) + 15) & ~(size_t)15;
-}
-__host__ __device__ static size_t bf16_taps_bytes(int h, const BF16Shape& bs) {
-  return bf16_kq_end(h, bs) + (size_t)(h + 1) * bf16_ext_len(bs) * 2;
-}
-// one quarter's partial sums (all strips and tiles of the region)
-__host__ __device__ static size_t bf16_part_bytes(const BF16Shape& bs) {
-  return sizeof(float) * (size_t)bs.RI * bs.RJ * 1024;
-}
-static size_t bf16_lds(int h, const BF16Shape& bs) {
-  size_t a = bf16_taps_bytes(h, bs), b = bf16_part_bytes(bs);
-  return bf16_tile_bytes(bs) + (a > b ? a : b);
-}
-
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-// Items as in the FP32 kernel.  LDS: the region's BF16 input image (zero halo
-// written once), then the tap copies, which the quarters' partial sums reuse
-// after the matrix loop (one quarter at a time, added in a fixed order).
-// With a support box (see the FP32 kernel): CONV_IN_BOX stages only the box and
-// each strip splits just the tap rows that reach it over its four wavefronts,
-// skipping the A fragments outside the box's columns; CONV_OUT_BOX skips the
-// strips and tiles that do not meet the box (their outputs are stored as 0).
-template <int RJ, int SMAX, int SUP>
-__global__ void __launch_bounds__(256 * 3) k_conv_mfma_bf16(Geo<float> g, BF16Shape bs, int n_items,
-                                                            const int4* __restrict__ box,
-                                                            const float* __restrict__ zca,
-                                                            const float* __restrict__ in, float* __restrict__ out) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int NW = BQ * bs.RI, NT = 64 * NW;
-  const int h = g.h;
-  const int rows = bs.rows, pitch = bs.pitch, CL = bs.CL, S = bs.S;
-  __bf16* tile = reinterpret_cast<__bf16*>(smem_raw);
-  unsigned char* taps_area = smem_raw + bf16_tile_bytes(bs);
-  __bf16* bcopy = reinterpret_cast<__bf16*>(taps_area);  // [h+1][8][CL]
-  float* kq = reinterpret_cast<float*>(taps_area + bf16_copy_bytes(h, bs));
-  unsigned short* ext = reinterpret_cast<unsigned short*>(taps_area + bf16_kq_end(h, bs));  // [h+1][CL+16]
-  float* part = reinterpret_cast<float*>(taps_area);
-  const int nreg = bs.regions_i * bs.regions_j;
-  const int region = blockIdx.x % nreg;
-  const int I0 = (region / bs.regions_j) * bs.RI * 32;
-  const int J0 = (region % bs.regions_j) * RJ * 32;
-  const size_t plane = (size_t)g.Nu * g.Nv;
-  const int tid = threadIdx.x;
-  const DataRect dr = data_rect(g, I0, J0, 32 * bs.RI, 32 * RJ);
-
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int strip = wave / BQ, quarter = wave - strip * BQ;
-  const int m = lane & 31, hi = lane >> 5;  // A: row m, K 8 hi .. 8 hi + 7; B: column m
-  const __bf16* abase = tile + (32 * strip + m + h) * pitch + 8 * hi;
-  // B[kk][n] = K[p][16 s - h + kk - n]: lane (n = m, kk = 8 hi + e) needs extended
-  // entries x0 + e, x0 = 16 s + 8 hi + 31 - m, residue r = (31 - m) % 8.
-  const int rr = (31 - m) & 7;
-  const __bf16* bbase = bcopy + rr * CL + 8 * hi + 31 - m + ((8 - rr) & 7);
-  constexpr int NA = 2 * RJ + SMAX - 2;
-  const int na = 2 * RJ + S - 2;
-  float* my_part = part + (size_t)strip * RJ * 1024;
-  const int I = I0 + 32 * strip;  // first output row of this wavefront's strip
-  auto rect_of = [&](int item) {
-    if (SUP == CONV_IN_BOX) return clip_rect(dr, box[(item / nreg) / g.Nk]);
-    return dr;
-  };
-
-  zero_lds(tile, rows * pitch, tid, NT);
-  float buf[PF];
-  int it = blockIdx.x;
-  DataRect cur = rect_of(it < n_items ? it : 0);
-  DataRect prev = cur;
-  prev.nr = 0;
-  prev.nc = 1;
-  if (it < n_items) fetch_rect<PF>(in + (size_t)(it / nreg) * plane, g.Nv, cur, tid, NT, buf);
-  __syncthreads();
-  for (; it < n_items; it += gridDim.x) {
-    const int bk = it / nreg;
-    const int k = bk % g.Nk;
-    const float* src = in + (size_t)bk * plane;
-    put_rect<PF>(src, g.Nv, cur, pitch, tid, NT, buf, tile);
-    if (SUP == CONV_IN_BOX) {
-      for (RectWalk w(tid, NT, prev.nc); w.r < prev.nr; w.next(prev.nc)) {
-        const int lr = prev.lr0 + w.r, lc = prev.lc0 + w.c;
-        const bool in_cur = lr >= cur.lr0 && lr < cur.lr0 + cur.nr && lc >= cur.lc0 && lc < cur.lc0 + cur.nc;
-        if (!in_cur) tile[lr * pitch + lc] = (__bf16)0.f;
-      }
-    }
-    // this wavefront's tap rows [p_begin, p_end), A fragments [a_lo, a_hi], tiles [t_lo, t_hi]
-    int p_lo = -h, p_hi = h, a_lo = 0, a_hi = na - 1, t_lo = 0, t_hi = RJ - 1;
-    if (SUP == CONV_IN_BOX) {
-      const int r0 = cur.r0, r1 = cur.r0 + cur.nr;
-      p_lo = max(-h, r0 - I - 31);
-      p_hi = min(h, r1 - I - 1);
-      if (cur.nr == 0) p_hi = p_lo - 1;
-      a_lo = max(0, floor_div16(cur.c0 - (J0 - h)));
-      a_hi = min(na - 1, floor_div16(cur.c0 + cur.nc - 1 - (J0 - h)));
-    }
-    const int n_need = p_hi >= p_lo ? p_hi - p_lo + 1 : 0, per = (n_need + BQ - 1) / BQ;
-    int p_begin = p_lo + quarter * per, p_end = min(p_lo + n_need, p_begin + per);
-    // CONV_OUT_BOX: nS strips of 32 rows placed at the box's top row (Iw) and nJ
-    // tiles at its left column rounded down to a multiple of 8 (Jw, so the 16-byte
-    // fragment reads stay aligned); the NW wavefronts split as nS strips x C chunks
-    // of the tap rows, whose partial sums are added in a fixed binary tree.
-    const __bf16* a_base = abase;
-    int C = BQ, chunk = quarter, s_idx = strip, nS = 0, out_I = I, out_J = J0;
-    if (SUP == CONV_OUT_BOX) {
-      const int4 bx = box[bk / g.Nk];
-      const int Ie = min(g.Nu, I0 + 32 * bs.RI), Je = min(g.Nv, J0 + 32 * RJ);
-      const int u0 = max(bx.x, I0), u1 = min(bx.y, Ie), v0 = max(bx.z, J0), v1 = min(bx.w, Je);
-      int nJ = 0, Iw = I0, Jw = J0;
-      if (u1 > u0 && v1 > v0) {
-        nS = (u1 - u0 + 31) / 32;
-        Iw = min(u0, I0 + 32 * bs.RI - 32 * nS);
-        const int ja = v0 - ((v0 - J0) & 7);
-        nJ = (v1 - ja + 31) / 32;
-        Jw = min(ja, J0 + 32 * RJ - 32 * nJ);
-      }
-      C = nS > 0 ? NW / nS : NW;
-      s_idx = wave / C;
-      chunk = wave - s_idx * C;
-      a_base = tile + (Iw - I0 + 32 * s_idx + m + h) * pitch + (Jw - J0) + 8 * hi;
-      out_I = Iw + 32 * s_idx;
-      out_J = Jw;
-      t_lo = 0;
-      t_hi = nJ - 1;
-      a_lo = 0;
-      a_hi = min(na - 1, 2 * (nJ - 1) + S - 1);
-      const int n_p = 2 * h + 1;
-      p_begin = -h + (n_p * chunk) / C;
-      p_end = -h + (n_p * (chunk + 1)) / C;
-      if (s_idx >= nS || nJ == 0) p_end = p_begin;
-    }
-    unique_taps(g, k, zca[bk], kq, tid, NT);
-    __syncthreads();
-    // the padded BF16 row of each tap row (bf16 pairs)
-    {
-      const int XE = bf16_ext_len(bs), XE2 = XE / 2;
-      for (int d = tid; d < (h + 1) * XE2; d += NT) {
-        const int p = d / XE2, e2 = d - p * XE2;
-        unsigned packed = 0;
-#pragma unroll
-        for (int hlf = 0; hlf < 2; ++hlf) {
-          const int x = 2 * e2 + hlf - 8;
-          const int q = x - (h + 31);
-          const float v = (x >= 0 && q >= -h && q <= h) ? kq[p * (h + 1) + (q < 0 ? -q : q)] : 0.f;
-          const __bf16 bv = (__bf16)v;
-          packed |= (unsigned)(*reinterpret_cast<const unsigned short*>(&bv)) << (16 * hlf);
-        }
-        reinterpret_cast<unsigned*>(ext)[d] = packed;
-      }
-    }
-    __syncthreads();
-    // Extended tap row x stored in copy r at position x + sigma_r, sigma_r =
-    // (8 - r) % 8, so that a run starting at x with x % 8 == r is aligned.  A lane
-    // writes 8 positions (16 bytes) of one copy: padded-row entries e0 .. e0 + 7,
-    // e0 = 8 g - sigma_r + 8, funnel-shifted out of five aligned pairs.
-    {
-      const int XE = bf16_ext_len(bs);
-      const int lpr = CL / 8, rpi = 64 / lpr;  // lanes per copy row, copy rows per wavefront pass
-      const int rsub = lane / lpr, g8 = lane - rsub * lpr;
-      for (int row0 = wave * rpi; row0 < (h + 1) * 8; row0 += NW * rpi) {
-        const int row = row0 + rsub;
-        if (rsub < rpi && row < (h + 1) * 8) {
-          const int p = row >> 3, r = row & 7;
-          const int e0 = 8 * g8 - ((8 - r) & 7) + 8;
-          const unsigned* w = reinterpret_cast<const unsigned*>(ext + (size_t)p * XE) + (e0 >> 1);
-          const unsigned sh = 2u * (unsigned)(e0 & 1);
-          unsigned v[5];
-#pragma unroll
-          for (int c = 0; c < 5; ++c) v[c] = w[c];
-          uint4 o;
-          o.x = __builtin_amdgcn_alignbyte(v[1], v[0], sh);
-          o.y = __builtin_amdgcn_alignbyte(v[2], v[1], sh);
-          o.z = __builtin_amdgcn_alignbyte(v[3], v[2], sh);
-          o.w = __builtin_amdgcn_alignbyte(v[4], v[3], sh);
-          *reinterpret_cast<uint4*>(bcopy + (size_t)row * CL + 8 * g8) = o;
-        }
-      }
-    }
-    __syncthreads();
-    const int nx = it + gridDim.x;
-    DataRect nxt = cur;
-    if (nx < n_items) {
-      nxt = rect_of(nx);
-      fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, nxt, tid, NT, buf);
-    }
-
-    f32x16 acc[RJ];
-#pragma unroll
-    for (int t = 0; t < RJ; ++t)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
-    for (int p = p_begin; p < p_end; ++p) {
-      const int ap = p < 0 ? -p : p;
-      const __bf16* brow = bbase + ap * 8 * CL;
-      const __bf16* arow = a_base + p * pitch;
-      bf16x8 Bf[SMAX];
-#pragma unroll
-      for (int s2 = 0; s2 < SMAX; ++s2)
-        if (s2 < S) Bf[s2] = *reinterpret_cast<const bf16x8*>(brow + 16 * s2);
-      // walk the A fragments: fragment a feeds tile t at K-step a - 2 t
-#pragma unroll
-      for (int a = 0; a < NA; ++a) {
-        if (a < na && a >= a_lo && a <= a_hi) {
-          const bf16x8 Af = *reinterpret_cast<const bf16x8*>(arow + 16 * a);
-#pragma unroll
-          for (int t = 0; t < RJ; ++t) {
-            const int s2 = a - 2 * t;
-            if (s2 >= 0 && s2 < SMAX && s2 < S && t >= t_lo && t <= t_hi)
-              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Af, Bf[s2], acc[t], 0, 0, 0);
-          }
-        }
-      }
-    }
-    if (SUP == CONV_OUT_BOX) {
-      // binary tree over the chunks of each strip (the taps are dead now): in round
-      // d, chunk c = 2 d m + d parks its sums in slot m and chunk 2 d m adds them
-      const int spp = C / 2;  // slots per strip (C is even)
-      for (int d = 1; d < C; d <<= 1) {
-        __syncthreads();
-        if (s_idx < nS && chunk % (2 * d) == d) {
-          float* slot = part + (size_t)(s_idx * spp + chunk / (2 * d)) * RJ * 1024;
-#pragma unroll
-          for (int t = 0; t < RJ; ++t)
-#pragma unroll
-            for (int r4 = 0; r4 < 4; ++r4)
-              *reinterpret_cast<f32x4*>(slot + t * 1024 + r4 * 256 + 4 * lane) =
-                  f32x4{acc[t][4 * r4], acc[t][4 * r4 + 1], acc[t][4 * r4 + 2], acc[t][4 * r4 + 3]};
-        }
-        __syncthreads();
-        if (s_idx < nS && chunk % (2 * d) == 0 && chunk + d < C) {
-          const float* slot = part + (size_t)(s_idx * spp + chunk / (2 * d)) * RJ * 1024;
-#pragma unroll
-          for (int t = 0; t < RJ; ++t)
-#pragma unroll
-            for (int r4 = 0; r4 < 4; ++r4) {
-              const f32x4 v = *reinterpret_cast<const f32x4*>(slot + t * 1024 + r4 * 256 + 4 * lane);
-#pragma unroll
-              for (int e = 0; e < 4; ++e) acc[t][4 * r4 + e] += v[e];
-            }
-        }
-      }
-      if (s_idx < nS && chunk == 0) {
-        float* dst = out + (size_t)bk * plane;
-#pragma unroll
-        for (int t = 0; t < RJ; ++t) {
-          if (t > t_hi) break;
-          const int j = out_J + 32 * t + m;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int i = out_I + 8 * (r >> 2) + 4 * hi + (r & 3);
-            if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[t][r];
-          }
-        }
-      }
-      prev = cur;
-      cur = nxt;
-      __syncthreads();  // the partial sums alias the next item's taps
-      continue;
-    }
-    // add the quarters 1..3 into quarter 0 through LDS (the taps are dead now)
-    for (int qd = 1; qd < BQ; ++qd) {
-      __syncthreads();
-      // layout [t][r / 4][lane][r % 4]: each lane moves 16-byte runs, lanes contiguous
-      if (quarter == qd) {
-#pragma unroll
-        for (int t = 0; t < RJ; ++t)
-#pragma unroll
-          for (int r4 = 0; r4 < 4; ++r4)
-            *reinterpret_cast<f32x4*>(my_part + t * 1024 + r4 * 256 + 4 * lane) =
-                f32x4{acc[t][4 * r4], acc[t][4 * r4 + 1], acc[t][4 * r4 + 2], acc[t][4 * r4 + 3]};
-      }
-      __syncthreads();
-      if (quarter == 0) {
-#pragma unroll
-        for (int t = 0; t < RJ; ++t)
-#pragma unroll
-          for (int r4 = 0; r4 < 4; ++r4) {
-            const f32x4 v = *reinterpret_cast<const f32x4*>(my_part + t * 1024 + r4 * 256 + 4 * lane);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc[t][4 * r4 + e] += v[e];
-          }
-      }
-    }
-    if (quarter == 0) {
-      float* dst = out + (size_t)bk * plane;
-#pragma unroll
-      for (int t = 0; t < RJ; ++t) {
-        const int j = J0 + 32 * t + m;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int i = I0 + 32 * strip + 8 * (r >> 2) + 4 * hi + (r & 3);
-          if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[t][r];
-        }
-      }
-    }
-    prev = cur;
-    cur = nxt;
-    __syncthreads();  // the partial sums alias the next item's taps
-  }
-}
-
 // ------------------------------------------------------------------ launch
 
 // Persistent grid: as many workgroups as fit on the device at once (a multiple of
@@ -1156,62 +807,6 @@ hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, con
   if (adj) return launch_f32_adj(g, rs, fs, nb, bx, z, in, out, s);
   if (!bx || support == CONV_DENSE) return launch_f32_sup<CONV_DENSE>(g, rs, fs, lds, nb, bx, z, in, out, s);
   return launch_f32_sup<CONV_IN_BOX>(g, rs, fs, lds, nb, bx, z, in, out, s);
-}
-
-template <int RJ, int SMAX, int SUP>
-static hipError_t launch_bf16_cfg(const Geo<float>& g, const BF16Shape& bs, size_t lds, int nb, const int4* box,
-                                  const float* z, const float* in, float* out, hipStream_t s) {
-  const void* kern = (const void*)k_conv_mfma_bf16<RJ, SMAX, SUP>;
-  if (SUP == CONV_OUT_BOX) {  // the tree's slots: NW / 2 of RJ tiles each
-    const size_t slots = bf16_tile_bytes(bs) + (size_t)(BQ * bs.RI / 2) * RJ * 1024 * sizeof(float);
-    if (slots > lds) lds = slots;
-  }
-  {
-    hipError_t e = ensure_lds_limit(kern, (int)LDS_MAX);
-    if (e != hipSuccess) return e;
-  }
-  if (lds > LDS_MAX) return hipErrorInvalidConfiguration;
-  const int nreg = bs.regions_i * bs.regions_j;
-  const long n_items = (long)nreg * g.Nk * nb;
-  if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;
-  const int threads = 64 * BQ * bs.RI;
-  const int grid = persistent_grid(kern, threads, lds, nreg, n_items);
-  hipLaunchKernelGGL((k_conv_mfma_bf16<RJ, SMAX, SUP>), dim3(grid), dim3(threads), lds, s, g, bs, (int)n_items, box,
-                     z, in, out);
-  return hipGetLastError();
-}
-
-template <int RJ, int SUP>
-static hipError_t launch_bf16_rj(const Geo<float>& g, const BF16Shape& bs, size_t lds, int nb, const int4* box,
-                                 const float* z, const float* in, float* out, hipStream_t s) {
-  if (bs.S <= 4) return launch_bf16_cfg<RJ, 4, SUP>(g, bs, lds, nb, box, z, in, out, s);
-  if (bs.S <= 6) return launch_bf16_cfg<RJ, 6, SUP>(g, bs, lds, nb, box, z, in, out, s);
-  if (bs.S <= 8) return launch_bf16_cfg<RJ, 8, SUP>(g, bs, lds, nb, box, z, in, out, s);
-  return launch_bf16_cfg<RJ, 10, SUP>(g, bs, lds, nb, box, z, in, out, s);
-}
-
-template <int SUP>
-static hipError_t launch_bf16_sup(const Geo<float>& g, const BF16Shape& bs, size_t lds, int nb, const int4* box,
-                                  const float* z, const float* in, float* out, hipStream_t s) {
-  if (bs.RJ == 1) return launch_bf16_rj<1, SUP>(g, bs, lds, nb, box, z, in, out, s);
-  if (bs.RJ == 2) return launch_bf16_rj<2, SUP>(g, bs, lds, nb, box, z, in, out, s);
-  return launch_bf16_cfg<3, 6, SUP>(g, bs, lds, nb, box, z, in, out, s);
-}
-
-hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
-                                 hipStream_t s, const int* box, int support) {
-  BF16Shape bs;
-  size_t lds = 0;
-  for (int rmax = 3; rmax >= 1; --rmax) {  // strips per region, while the LDS image fits
-    bs = bf16_shape(g.Nu, g.Nv, g.h, rmax);
-    lds = bf16_lds(g.h, bs);
-    if (lds <= LDS_MAX) break;
-  }
-  if (bs.S > 10) return hipErrorInvalidConfiguration;
-  const int4* bx = reinterpret_cast<const int4*>(box);
-  if (!bx || support == CONV_DENSE) return launch_bf16_sup<CONV_DENSE>(g, bs, lds, nb, bx, z, in, out, s);
-  if (support == CONV_IN_BOX) return launch_bf16_sup<CONV_IN_BOX>(g, bs, lds, nb, bx, z, in, out, s);
-  return launch_bf16_sup<CONV_OUT_BOX>(g, bs, lds, nb, bx, z, in, out, s);
 }
 
 }  // namespace pdrt
