@@ -11,15 +11,17 @@
 //   forward  input support = the box, outputs = the box's reach (box +- h),
 //   adjoint  outputs = the box, input support = its reach.
 //
-// One wavefront owns one (control point, plane) item: it evaluates the plane's
+// One workgroup owns one (control point, plane) item: it evaluates the plane's
 // taps, writes them as padded BF16 tap rows, stages the input support as a BF16
-// image in LDS, and accumulates 16 x 16 output tiles, a block of up to BR x BC
-// tiles at a time in registers.  For tap row p and K-step s (32 input columns
-// starting at c0), a row tile at i0 reads the A fragment in[i0+p+m][c0+8kq ..]
-// (one 16-byte LDS read per lane) only if its 16 input rows meet the support;
-// a column tile at n0 reads the B fragment K[p][c0+8kq+e-n0-m], e = 0..7, only
-// if the K-step lies within its reach; each A fragment feeds every column tile
-// of the block and each B fragment every row tile.  The B fragment of a lane is
+// image in LDS, and accumulates 16 x 16 output tiles in register blocks.  For tap
+// row p and K-step s (32 input columns starting at c0), a row tile at i0 reads
+// the A fragment in[i0+p+m][c0+8kq ..] (one 16-byte LDS read per lane) and runs
+// its matrix instructions only if its 16 input rows meet the support; a column
+// tile at n0 reads the B fragment K[p][c0+8kq+e-n0-m], e = 0..7; each A fragment
+// feeds every column tile of the block and each B fragment every row tile.  The
+// forward's two wavefronts take one block each (their columns split the reach);
+// the adjoint's four share its one small block, each a quarter of the tap rows,
+// and their sums are added in LDS in a fixed order.  The B fragment of a lane is
 // eight consecutive entries of one padded tap row at an arbitrary offset: two
 // copies of each row, the second shifted by one element, make every run start on
 // a 4-byte boundary (four 4-byte LDS reads); lanes whose run lies wholly outside
@@ -27,8 +29,10 @@
 //
 // Rounding: inputs and taps are rounded to BF16 (nearest even), every product is
 // exact in FP32 and accumulated in FP32 (matrix instructions, then tap rows and
-// K-steps in a fixed order): deterministic.  Work items are independent, so
-// several wavefronts share a compute unit and hide each other's set-up.
+// K-steps in a fixed order, the parts' sums in part order): deterministic.  Work
+// items are independent, so several workgroups share a compute unit and hide
+// each other's set-up; the first global loads of the input are issued before the
+// taps are evaluated.
 #include "conv_common.hpp"
 
 namespace pdrt {
@@ -58,19 +62,25 @@ __device__ __forceinline__ unsigned bf16_pair(float lo, float hi) {
 }
 
 // NK: K-steps (32 input columns each) of one column chunk; BR x BC: output tiles
-// of one register block; SUP: CONV_IN_BOX (forward) or CONV_OUT_BOX (adjoint).
-template <int NK, int BR, int BC, int SUP>
-__global__ void __launch_bounds__(64) k_conv_bf16(Geo<float> g, Bf16Plan q, const int4* __restrict__ box,
-                                                  const float* __restrict__ zca, const float* __restrict__ in,
-                                                  float* __restrict__ out) {
+// of one register block; NWB x NWP wavefronts: NWB blocks at a time, each block's
+// tap rows split in NWP parts whose sums are added in LDS in a fixed order;
+// SUP: CONV_IN_BOX (forward) or CONV_OUT_BOX (adjoint).
+template <int NK, int BR, int BC, int NWB, int NWP, int SUP>
+__global__ void __launch_bounds__(64 * NWB * NWP) __attribute__((amdgpu_waves_per_eu(1, 2)))
+k_conv_bf16(Geo<float> g, Bf16Plan q, const int4* __restrict__ box,
+                                                              const float* __restrict__ zca,
+                                                              const float* __restrict__ in, float* __restrict__ out) {
+  constexpr int NT = 64 * NWB * NWP;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int h = g.h, L = q.L;
+  const int h = g.h, L = q.L, L2 = L / 2;
   unsigned* T0 = reinterpret_cast<unsigned*>(smem_raw);  // [h+1][L/2] dword pairs, run start even
-  unsigned* T1 = T0 + (h + 1) * (L / 2);                 // the same rows shifted by one element
-  (void)T1;                                              // (reached through T0 + (h+1) L/2)
+  unsigned* T1 = T0 + (h + 1) * L2;                      // the same rows shifted by one element
   __bf16* img = reinterpret_cast<__bf16*>(smem_raw + cb_tap_bytes(h, q));
   float* kq = reinterpret_cast<float*>(img);             // unique taps, before the image is staged
-  const int lane = threadIdx.x;
+  f32x4c* red = reinterpret_cast<f32x4c*>(img);          // the parts' sums, after the last chunk
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wb = wave / NWP, wp = wave - wb * NWP;
   const int item = blockIdx.x;
   const int b = item / g.Nk, k = item - b * g.Nk;
   const size_t plane = (size_t)g.Nu * g.Nv;
@@ -89,9 +99,9 @@ __global__ void __launch_bounds__(64) k_conv_bf16(Geo<float> g, Bf16Plan q, cons
     // (whole rows above and below it, the columns left and right of it between)
     if (empty) or0 = or1 = 0, oc0 = oc1 = 0;
     const int top = or0 * g.Nv, bottom = (g.Nu - or1) * g.Nv;
-    for (int d = lane; d < top + bottom; d += 64) dst[d < top ? d : (size_t)or1 * g.Nv + (d - top)] = 0.f;
+    for (int d = tid; d < top + bottom; d += NT) dst[d < top ? d : (size_t)or1 * g.Nv + (d - top)] = 0.f;
     const int side = oc0 + (g.Nv - oc1), mid = (or1 - or0) * side;
-    for (int d = lane; d < mid; d += 64) {
+    for (int d = tid; d < mid; d += NT) {
       const int rr = d / side, cc = d - rr * side;
       dst[(size_t)(or0 + rr) * g.Nv + (cc < oc0 ? cc : oc1 + (cc - oc0))] = 0.f;
     }
@@ -102,12 +112,54 @@ __global__ void __launch_bounds__(64) k_conv_bf16(Geo<float> g, Bf16Plan q, cons
     ir0 = max(0, u0 - h), ir1 = min(g.Nu, u1 + h), ic0 = max(0, v0 - h), ic1 = min(g.Nv, v1 + h);
   }
 
+  const int m = lane & 15, kqd = lane >> 4;  // A: row m, K entries 8 kqd ..; B: column m
+  const int TR = (or1 - or0 + 15) / 16, TC = (oc1 - oc0 + 15) / 16;
+  const int KCOLS = 32 * NK, W2 = KCOLS / 2;
+  // input chunks: rows [cr0, cr1) of at most rch rows, columns [cc0, cc0 + KCOLS);
+  // the image holds rows [IR0, IR1): the chunk's rows with 15 zero rows above and
+  // below, clipped to the rows that the output tiles' tap rows reach
+  const int rows_all = min(ir1 - ir0 + 30, 16 * TR + 2 * h);
+  const int rch = rows_all <= q.img_rows ? ir1 - ir0 : q.img_rows - 30;
+  struct Chunk {
+    int cr0, cr1, cc0, cc1, IR0, nrows;
+  };
+  auto chunk_at = [&](int cr0, int cc0) {
+    Chunk c;
+    c.cr0 = cr0, c.cr1 = min(ir1, cr0 + rch), c.cc0 = cc0, c.cc1 = min(ic1, cc0 + KCOLS);
+    c.IR0 = max(cr0 - 15, or0 - h);
+    c.nrows = min(c.cr1 + 15, or0 + 16 * TR + h) - c.IR0;
+    return c;
+  };
+  auto load_pair = [&](const Chunk& c, int d, float& x0, float& x1) {
+    const int rr = d / W2, c2 = d - rr * W2;
+    const int i = c.IR0 + rr, j = c.cc0 + 2 * c2;
+    const bool rin = d < c.nrows * W2 && i >= c.cr0 && i < c.cr1;
+    const size_t o = (size_t)i * g.Nv + j;
+    x0 = rin && j < c.cc1 ? src[o] : 0.f;
+    x1 = rin && j + 1 < c.cc1 ? src[o + 1] : 0.f;
+  };
+  auto put_pair = [&](const Chunk& c, int d, float x0, float x1) {
+    if (d < c.nrows * W2) {
+      const int rr = d / W2, c2 = d - rr * W2;
+      reinterpret_cast<unsigned*>(img + rr * q.pitch)[c2] = bf16_pair(x0, x1);
+    }
+  };
+
+  // the first chunk (for an aperture inside the field limits, the only one): its
+  // first PB pairs per thread are loaded before the taps are evaluated, so the
+  // loads' latency overlaps that work
+  constexpr int PB = 8, SB = 4;
+  const Chunk first = chunk_at(ir0, ic0);
+  float p0[PB], p1[PB];
+#pragma unroll
+  for (int e = 0; e < PB; ++e) load_pair(first, tid + NT * e, p0[e], p1[e]);
+
   // ---- taps: unique FP32 values, then two padded BF16 copies of each row
-  unique_taps(g, k, zca[item], kq, lane, 64);
+  unique_taps(g, k, zca[item], kq, tid, NT);
   __syncthreads();
   {
-    const int L2 = L / 2, n2 = (h + 1) * L2;
-    for (int d = lane; d < n2; d += 64) {
+    const int n2 = (h + 1) * L2;
+    for (int d = tid; d < n2; d += NT) {
       const int a = d / L2, j = d - a * L2;
       float v[3];
 #pragma unroll
@@ -120,139 +172,138 @@ __global__ void __launch_bounds__(64) k_conv_bf16(Geo<float> g, Bf16Plan q, cons
       T1[d] = bf16_pair(v[1], v[2]);
     }
   }
-  __syncthreads();
 
-  const int m = lane & 15, kqd = lane >> 4;  // A: row m, K entries 8 kqd ..; B: column m
-  const int TR = (or1 - or0 + 15) / 16, TC = (oc1 - oc0 + 15) / 16;
-  const int KCOLS = 32 * NK, L2 = L / 2;
-  for (int rb = 0; rb < TR; rb += BR) {
-    for (int cb = 0; cb < TC; cb += BC) {
-      const int nr = min(BR, TR - rb), nc = min(BC, TC - cb);
-      const int OI0 = or0 + 16 * rb, OJ0 = oc0 + 16 * cb;
-      f32x4c acc[BR][BC];
+  const int nbc = (TC + BC - 1) / BC, nblocks = ((TR + BR - 1) / BR) * nbc;
+  for (int slot = 0; slot * NWB < nblocks; ++slot) {
+    const int blk = slot * NWB + wb;
+    const bool active = blk < nblocks;
+    const int rb = active ? (blk / nbc) * BR : 0, cb = active ? (blk % nbc) * BC : 0;
+    const int nr = active ? min(BR, TR - rb) : 0, nc = active ? min(BC, TC - cb) : 0;
+    const int OI0 = or0 + 16 * rb, OJ0 = oc0 + 16 * cb;
+    f32x4c acc[BR][BC];
 #pragma unroll
-      for (int r = 0; r < BR; ++r)
+    for (int r = 0; r < BR; ++r)
 #pragma unroll
-        for (int t = 0; t < BC; ++t) acc[r][t] = f32x4c{0.f, 0.f, 0.f, 0.f};
-      // input rows and columns this block can reach: i0 + p + m for |p| <= h
-      const int br0 = max(ir0, OI0 - h), br1 = min(ir1, OI0 + 16 * nr + h);
-      const int bc0 = max(ic0, OJ0 - h), bc1 = min(ic1, OJ0 + 16 * nc + h);
-      if (br1 > br0 && bc1 > bc0) {
-        // row chunks: the image holds chunk rows plus 15 zero rows above and below,
-        // clipped to what the block's tap rows reach
-        const int rows_all = min(br1 - br0 + 30, 16 * nr + 2 * h);
-        const int rch = rows_all <= q.img_rows ? br1 - br0 : q.img_rows - 30;
-        for (int cr0 = br0; cr0 < br1; cr0 += rch) {
-          const int cr1 = min(br1, cr0 + rch);
-          for (int cc0 = bc0; cc0 < bc1; cc0 += KCOLS) {
-            const int cc1 = min(bc1, cc0 + KCOLS);
-            const int IR0 = max(cr0 - 15, OI0 - h);
-            const int nrows = min(cr1 + 15, OI0 + 16 * nr + h) - IR0;
-            // stage rows [IR0, IR0 + nrows) x columns [cc0, cc0 + KCOLS): data in
-            // [cr0, cr1) x [cc0, cc1), zero elsewhere; SB pairs per lane in flight
-            __syncthreads();
-            {
-              constexpr int SB = 2;
-              const int W2 = KCOLS / 2, total = nrows * W2;
-              for (int d0 = 0; d0 < total; d0 += 64 * SB) {
-                float x0[SB], x1[SB];
+      for (int t = 0; t < BC; ++t) acc[r][t] = f32x4c{0.f, 0.f, 0.f, 0.f};
+    for (int cr0 = ir0; cr0 < ir1; cr0 += rch) {
+      for (int cc0 = ic0; cc0 < ic1; cc0 += KCOLS) {
+        const Chunk c = chunk_at(cr0, cc0);
+        // stage the chunk's image (all threads; SB pairs per thread in flight)
+        __syncthreads();
+        int d0 = 0;
+        if (slot == 0 && cr0 == ir0 && cc0 == ic0) {
 #pragma unroll
-                for (int e = 0; e < SB; ++e) {
-                  const int d = d0 + lane + 64 * e;
-                  const int rr = d / W2, c2 = d - rr * W2;
-                  const int i = IR0 + rr, j = cc0 + 2 * c2;
-                  const bool rin = d < total && i >= cr0 && i < cr1;
-                  const size_t o = (size_t)i * g.Nv + j;
-                  x0[e] = rin && j < cc1 ? src[o] : 0.f;
-                  x1[e] = rin && j + 1 < cc1 ? src[o + 1] : 0.f;
-                }
+          for (int e = 0; e < PB; ++e) put_pair(c, tid + NT * e, p0[e], p1[e]);
+          d0 = NT * PB;
+        }
+        for (; d0 < c.nrows * W2; d0 += NT * SB) {
+          float x0[SB], x1[SB];
 #pragma unroll
-                for (int e = 0; e < SB; ++e) {
-                  const int d = d0 + lane + 64 * e;
-                  if (d < total) {
-                    const int rr = d / W2, c2 = d - rr * W2;
-                    reinterpret_cast<unsigned*>(img + rr * q.pitch)[c2] = bf16_pair(x0[e], x1[e]);
-                  }
-                }
-              }
+          for (int e = 0; e < SB; ++e) load_pair(c, d0 + tid + NT * e, x0[e], x1[e]);
+#pragma unroll
+          for (int e = 0; e < SB; ++e) put_pair(c, d0 + tid + NT * e, x0[e], x1[e]);
+        }
+        __syncthreads();
+        if (!active) continue;
+        // tap rows reaching the chunk from any row tile of the block, this wave's part
+        const int p_lo = max(-h, c.cr0 - (OI0 + 16 * nr - 1)), p_hi = min(h, c.cr1 - 1 - OI0);
+        const int np = p_hi - p_lo + 1;
+        if (np <= 0) continue;
+        const int pa = p_lo + (np * wp) / NWP, pz = p_lo + (np * (wp + 1)) / NWP;
+        // per lane and (column tile, K-step): where its B run starts in a padded
+        // tap row (copy by parity), and whether it meets the band at all
+        int boff[BC][NK];
+        unsigned bmask[BC][NK];
+#pragma unroll
+        for (int t = 0; t < BC; ++t) {
+          const int n0 = OJ0 + 16 * t;
+#pragma unroll
+          for (int s2 = 0; s2 < NK; ++s2) {
+            const int c0 = cc0 + 32 * s2;
+            const int x = c0 + 8 * kqd - n0 - m + q.X0;
+            const bool live = t < nc && c0 < c.cc1 && x + 7 >= q.X0 - h && x <= q.X0 + h;
+            const int xs = live ? x : q.X0;
+            boff[t][s2] = ((xs & 1) ? (h + 1) * L2 : 0) + (xs >> 1);
+            bmask[t][s2] = live ? 0xffffffffu : 0u;
+          }
+        }
+        const __bf16* abase = img + (m - c.IR0) * q.pitch + 8 * kqd;
+        for (int p = pa; p < pz; ++p) {
+          const int ap = p < 0 ? -p : p;
+          // all of this tap row's operands first (unconditional loads, kept as
+          // 32-bit words until the matrix instructions: branch-free code waits only
+          // for the operands each instruction needs), then the instructions of the
+          // row tiles whose 16 input rows [i0 + p, i0 + p + 16) meet the chunk
+          u32x4c Bw[BC][NK];
+#pragma unroll
+          for (int t = 0; t < BC; ++t)
+#pragma unroll
+            for (int s2 = 0; s2 < NK; ++s2) {
+              const unsigned* row = T0 + ap * L2 + boff[t][s2];
+              const unsigned mk = bmask[t][s2];
+              Bw[t][s2] = u32x4c{row[0] & mk, row[1] & mk, row[2] & mk, row[3] & mk};
             }
-            __syncthreads();
-            // per lane and (column tile, K-step): where its B run starts in a padded
-            // tap row (copy by parity), and whether it meets the band at all
-            int boff[BC][NK];
-            unsigned bmask[BC][NK];
+          u32x4c Aw[BR][NK];
+          bool rval[BR];
 #pragma unroll
-            for (int t = 0; t < BC; ++t) {
-              const int n0 = OJ0 + 16 * t;
+          for (int r = 0; r < BR; ++r) {
+            const int i0 = OI0 + 16 * r;
+            rval[r] = r < nr && i0 + p + 15 >= c.cr0 && i0 + p < c.cr1;
+            // other tiles read the chunk's first image row (in bounds), unused
+            const int arow = rval[r] ? i0 + p : c.IR0;
 #pragma unroll
-              for (int s2 = 0; s2 < NK; ++s2) {
-                const int c0 = cc0 + 32 * s2;
-                const int x = c0 + 8 * kqd - n0 - m + q.X0;
-                const bool live = t < nc && c0 < cc1 && x + 7 >= q.X0 - h && x <= q.X0 + h;
-                const int xs = live ? x : q.X0;
-                boff[t][s2] = ((xs & 1) ? (h + 1) * L2 : 0) + (xs >> 1);
-                bmask[t][s2] = live ? 0xffffffffu : 0u;
-              }
-            }
-            const __bf16* abase = img + (m - IR0) * q.pitch + 8 * kqd;
-            // tap rows reaching the chunk from any row tile of the block
-            const int p_lo = max(-h, cr0 - (OI0 + 16 * nr - 1)), p_hi = min(h, cr1 - 1 - OI0);
-            for (int p = p_lo; p <= p_hi; ++p) {
-              const int ap = p < 0 ? -p : p;
-              // all of this tap row's operands first (unconditional loads, kept as
-              // 32-bit words until the matrix instructions), then the instructions
-              u32x4c Bw[BC][NK];
+            for (int s2 = 0; s2 < NK; ++s2)
+              Aw[r][s2] = *reinterpret_cast<const u32x4c*>(abase + arow * q.pitch + 32 * s2);
+          }
+#pragma unroll
+          for (int r = 0; r < BR; ++r) {
+            if (!rval[r]) continue;
+#pragma unroll
+            for (int s2 = 0; s2 < NK; ++s2)
 #pragma unroll
               for (int t = 0; t < BC; ++t)
-#pragma unroll
-                for (int s2 = 0; s2 < NK; ++s2) {
-                  const unsigned* row = T0 + ap * L2 + boff[t][s2];
-                  const unsigned mk = bmask[t][s2];
-                  Bw[t][s2] = u32x4c{row[0] & mk, row[1] & mk, row[2] & mk, row[3] & mk};
-                }
-              u32x4c Aw[BR][NK];
-              bool rval[BR];
-#pragma unroll
-              for (int r = 0; r < BR; ++r) {
-                const int i0 = OI0 + 16 * r;
-                // the tile's 16 input rows [i0 + p, i0 + p + 16) must meet the chunk;
-                // other tiles read image row 0 (in bounds) and skip their instructions
-                rval[r] = r < nr && i0 + p + 15 >= cr0 && i0 + p < cr1;
-                const int arow = rval[r] ? i0 + p : IR0;
-#pragma unroll
-                for (int s2 = 0; s2 < NK; ++s2)
-                  Aw[r][s2] = *reinterpret_cast<const u32x4c*>(abase + arow * q.pitch + 32 * s2);
-              }
-#pragma unroll
-              for (int r = 0; r < BR; ++r) {
-                if (!rval[r]) continue;
-#pragma unroll
-                for (int s2 = 0; s2 < NK; ++s2)
-#pragma unroll
-                  for (int t = 0; t < BC; ++t)
-                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, Aw[r][s2]),
-                                                                         __builtin_bit_cast(bf16x8c, Bw[t][s2]),
-                                                                         acc[r][t], 0, 0, 0);
-              }
-            }
+                acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, Aw[r][s2]),
+                                                                     __builtin_bit_cast(bf16x8c, Bw[t][s2]),
+                                                                     acc[r][t], 0, 0, 0);
           }
         }
       }
-      // lane (m, kqd) holds rows 4 kqd + e, column m of each tile
+    }
+    if (NWP > 1) {
+      // parts 1 .. NWP-1 park their sums, part 0 adds them in that order
+      __syncthreads();
+      if (active && wp > 0) {
 #pragma unroll
-      for (int r = 0; r < BR; ++r) {
-        if (r >= nr) break;
+        for (int r = 0; r < BR; ++r)
+#pragma unroll
+          for (int t = 0; t < BC; ++t)
+            red[(((wb * (NWP - 1) + wp - 1) * BR + r) * BC + t) * 64 + lane] = acc[r][t];
+      }
+      __syncthreads();
+      if (active && wp == 0) {
+        for (int pp = 1; pp < NWP; ++pp)
+#pragma unroll
+          for (int r = 0; r < BR; ++r)
+#pragma unroll
+            for (int t = 0; t < BC; ++t)
+              acc[r][t] += red[(((wb * (NWP - 1) + pp - 1) * BR + r) * BC + t) * 64 + lane];
+      }
+    }
+    // lane (m, kqd) holds rows 4 kqd + e, column m of each tile
+    if (active && wp == 0) {
+      // (conditions rather than early exits: the loops stay fully unrolled and the
+      // accumulators in registers)
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
 #pragma unroll
         for (int t = 0; t < BC; ++t) {
-          if (t >= nc) break;
           const int j = OJ0 + 16 * t + m;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int i = OI0 + 16 * r + 4 * kqd + e;
-            if (i < or1 && j < oc1) dst[(size_t)i * g.Nv + j] = acc[r][t][e];
+            if (r < nr && t < nc && i < or1 && j < oc1) dst[(size_t)i * g.Nv + j] = acc[r][t][e];
           }
         }
-      }
     }
   }
 }
@@ -272,7 +323,7 @@ static int box_extent(double F, double D, double c, int N) {
 // distinct 16-byte slots of a 128-byte window (no bank conflicts).
 static int pitch_bf16(int cols) { return cols + 8; }
 
-template <int NK, int BR, int BC, int SUP>
+template <int NK, int BR, int BC, int NWB, int NWP, int SUP>
 static hipError_t launch_bf16_nk(const Geo<float>& g, int nb, const int4* box, const float* z, const float* in,
                                  float* out, hipStream_t s, int box_rows) {
   Bf16Plan q;
@@ -280,30 +331,32 @@ static hipError_t launch_bf16_nk(const Geo<float>& g, int nb, const int4* box, c
   q.L = 2 * g.h + 16;
   const int out_rows = SUP == CONV_IN_BOX ? (box_rows + 2 * g.h < g.Nu ? box_rows + 2 * g.h : g.Nu) : box_rows;
   const int tr = (out_rows + 15) / 16;
-  const int tr_blk = tr < BR ? tr : BR;
   const int in_rows = SUP == CONV_IN_BOX ? box_rows : (box_rows + 2 * g.h < g.Nu ? box_rows + 2 * g.h : g.Nu);
   int rows = in_rows + 30;
-  if (rows > 16 * tr_blk + 2 * g.h) rows = 16 * tr_blk + 2 * g.h;
+  if (rows > 16 * tr + 2 * g.h) rows = 16 * tr + 2 * g.h;
   if (rows < 31) rows = 31;  // at least one row of data per chunk
-  q.img_rows = rows;
   q.pitch = pitch_bf16(32 * NK);
+  // the image area also holds the unique FP32 taps and the parts' sums
+  const int red_rows = (NWB * (NWP - 1) * BR * BC * 1024 + 2 * q.pitch - 1) / (2 * q.pitch);
+  q.img_rows = rows > red_rows ? rows : red_rows;
   q.kq_floats = (g.h + 1) * (g.h + 1);
   const size_t lds = cb_tap_bytes(g.h, q) + cb_img_bytes(q);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  const void* kern = (const void*)k_conv_bf16<NK, BR, BC, SUP>;
+  const void* kern = (const void*)k_conv_bf16<NK, BR, BC, NWB, NWP, SUP>;
   {
     hipError_t e = ensure_lds_limit(kern, (int)lds);
     if (e != hipSuccess) return e;
   }
   const long n_items = (long)nb * g.Nk;
   if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_conv_bf16<NK, BR, BC, SUP>), dim3((unsigned)n_items), dim3(64), lds, s, g, q, box, z, in,
-                     out);
+  hipLaunchKernelGGL((k_conv_bf16<NK, BR, BC, NWB, NWP, SUP>), dim3((unsigned)n_items), dim3(64 * NWB * NWP), lds, s,
+                     g, q, box, z, in, out);
   return hipGetLastError();
 }
 
-// Forward: one register block of up to 6 x 6 tiles covers the reach of a rectangle
-// inside the field limits; adjoint: 2 x 2 tiles cover the rectangle itself.
+// Forward: two wavefronts, each a block of 6 x 3 tiles (together the reach of a
+// rectangle inside the field limits); adjoint: four wavefronts sharing one block
+// of 2 x 2 tiles (the rectangle itself), each a quarter of the tap rows.
 template <int SUP>
 static hipError_t launch_bf16_sup(const Geo<float>& g, int nb, const int4* box, const float* z, const float* in,
                                   float* out, hipStream_t s) {
@@ -314,10 +367,11 @@ static hipError_t launch_bf16_sup(const Geo<float>& g, int nb, const int4* box, 
   const int bc = box ? box_extent(Fv, D, 0.5 * (g.Nv - 1), g.Nv) : g.Nv;
   const int in_cols = SUP == CONV_IN_BOX ? bc : (bc + 2 * g.h < g.Nv ? bc + 2 * g.h : g.Nv);
   const int nk = (in_cols + 31) / 32;
-  constexpr int BR = SUP == CONV_IN_BOX ? 6 : 2, BC = SUP == CONV_IN_BOX ? 3 : 2;
-  if (nk <= 1) return launch_bf16_nk<1, BR, BC, SUP>(g, nb, box, z, in, out, s, br);
-  if (nk == 2) return launch_bf16_nk<2, BR, BC, SUP>(g, nb, box, z, in, out, s, br);
-  return launch_bf16_nk<3, BR, BC, SUP>(g, nb, box, z, in, out, s, br);
+  constexpr bool F = SUP == CONV_IN_BOX;
+  constexpr int BR = F ? 6 : 2, BC = F ? 3 : 2, NWB = F ? 2 : 1, NWP = F ? 1 : 4;
+  if (nk <= 1) return launch_bf16_nk<1, BR, BC, NWB, NWP, SUP>(g, nb, box, z, in, out, s, br);
+  if (nk == 2) return launch_bf16_nk<2, BR, BC, NWB, NWP, SUP>(g, nb, box, z, in, out, s, br);
+  return launch_bf16_nk<3, BR, BC, NWB, NWP, SUP>(g, nb, box, z, in, out, s, br);
 }
 
 hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
