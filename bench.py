@@ -226,12 +226,12 @@ def per_step(kernels, steps):
     return {k: round(v[1] / steps, 4) for k, v in sorted(kernels.items())}
 
 
-def run_gpu(case, conv, steps, warmup, w, cache=None, forward_only=False):
+def run_gpu(case, conv, steps, warmup, w, cache=None, forward_only=False, march_scan=False):
     """Forward + backward (or forward only) timed over `steps`; with cache = "fp32" /
     "bf16" the plan's geometry cache is built first (once per plan, not timed)."""
     import torch
     from paper_2512_18863_amd import engine as E
-    eng = E.DoseEngine(case, conv=conv)
+    eng = E.DoseEngine(case, conv=conv, march_scan=march_scan)
     dev = eng.device
     if cache:
         torch.cuda.synchronize()
@@ -565,6 +565,18 @@ def main():
     del f32
     engines = {"fp32": eng}
     variants = {}
+    print("[bench] fp32 with the segmented-scan ray march", file=sys.stderr, flush=True)
+    rs = run_gpu(case, "fp32", K, W, w, march_scan=True)
+    variants["fp32_march_scan"] = {
+        "value": round(n_cp / (rs["median_ms"] / 1e3), 3), "ms_per_step": round(rs["median_ms"], 4),
+        "march": "depth integral as a segmented scan over the wavefronts of a workgroup (spec.march_scan = 1); "
+                 "the default is one thread per ray",
+        "max_abs_err_vs_default_over_max": float(np.abs(rs["dose"].astype(np.float64) - d32).max()
+                                                 / np.abs(d32).max()),
+        "roofline_kernels": {k: roofline_entry(k, rs["kernels"], K, work) for k in ("march", "march_adj")},
+        "kernels_ms_per_step": per_step(rs["kernels"], K)}
+    del rs
+    torch.cuda.empty_cache()
     if not args.no_bf16:
         print("[bench] bf16 variant", file=sys.stderr, flush=True)
         r16 = run_gpu(case, "bf16", K, W, w)

@@ -122,6 +122,13 @@ typedef struct {
   double pen_fwhm_mm[2];
   double hs_amp, hs_sigma_mm;
   double oar[2];
+  /* Form of the ray march that evaluates the depth integral of Eq. 7 (the same
+   * arithmetic, a different order of the compensated sums, so results agree to
+   * rounding): 0 = one thread per ray walks its planes in order (default, the
+   * faster on the MI355X); 1 = the planes of 64 rays are split over the wavefronts
+   * of a workgroup, each scanning its segment and adding the sums of the segments
+   * before it, exchanged through LDS. */
+  int32_t march_scan;
 } pdrt_kernel_spec;
 
 /* Beam-frame grid of a problem (§2.2.3): Nu x Nv rays, Nk planes, first plane at
@@ -225,8 +232,8 @@ int pdrt_dose_forward_f64(const pdrt_grid* grid, const double* rho, const pdrt_b
  *   z float [n_cp][Nk] at byte 0, then G [n_cp][Nk][Nu][Nv] (float for
  *   PDRT_CACHE_F32, bf16 for PDRT_CACHE_BF16) at the next 256-byte boundary.
  * A cache is valid for the grid, density, beam (gantry angles, isocentre, SAD,
- * field limit) and the spec fields n_taps, wepl_mode, lateral/depth steps and the
- * depth-dose table it was built with; the caller keeps those fixed (they are not
+ * field limit) and the spec fields n_taps, wepl_mode, lateral/depth steps, the
+ * depth-dose table and march_scan it was built with; the caller keeps those fixed (they are not
  * checked).  The spec's conv_mode, calib, transmission, kernel polynomials and
  * fluence corrections may change between builds and uses.  With PDRT_CACHE_F32
  * the cached calls return exactly what pdrt_dose_forward / _backward return.

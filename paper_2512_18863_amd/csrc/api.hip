@@ -111,6 +111,7 @@ int validate(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_spe
       if (!std::isfinite(spec->kpoly[a][b])) return PDRT_E_INVALID;
   if (!(spec->kz_max_mm >= 0.0) || !std::isfinite(spec->kz_max_mm)) return PDRT_E_INVALID;
   if (spec->max_cp_batch < 0) return PDRT_E_INVALID;
+  if (spec->march_scan != 0 && spec->march_scan != 1) return PDRT_E_INVALID;
   if (spec->fluence_corr != 0 && spec->fluence_corr != 1) return PDRT_E_INVALID;
   if (spec->fluence_corr) {
     const double sig[3] = {spec->pen_fwhm_mm[0] / kFwhmPerSigma, spec->pen_fwhm_mm[1] / kFwhmPerSigma,
@@ -259,6 +260,7 @@ void make_geo(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel_sp
   g->hs_amp = (T)spec->hs_amp;
   g->oar0 = (T)spec->oar[0];
   g->oar1 = (T)spec->oar[1];
+  g->march_scan = spec->march_scan;
 }
 
 // The three Gaussians of the fluence corrections: penumbra along u and v, head scatter.

@@ -209,22 +209,25 @@ hipError_t launch_ca_depth(const Geo<T>& g, int nb, const T* frame, const T* rho
 
 // ------------------------------------------------------------------ ray march
 
-// One thread per divergent ray (i, j): ray (u_i, v_j) meets plane k at
+// Ray (u_i, v_j) meets plane k at
 //   q - iso = (d_k - SAD) b + (d_k / SAD)(u e_u + v e_v);
-// the density is sampled trilinearly there and integrated with a compensated
-// running sum (step Dd sqrt(1 + (u^2 + v^2)/SAD^2)), giving W_k; the primary is
-// P_k = F (SAD / d_k)^2 DD(W_k).  Lanes run along v, i.e. along patient z, so the
-// z-fastest density copy is read almost contiguously.  MARCH_ADJOINT instead
-// accumulates A = sum_k H_k (SAD / d_k)^2 DD(W_k) (the adjoint of the primary
-// w.r.t. F); MARCH_GEOMETRY stores the aperture-independent factor
-// G_k = (SAD / d_k)^2 DD(W_k) itself (rounded to E), so that P = F G later.
+// the density is sampled trilinearly there, and the water-equivalent depth of
+// Eq. 7 is the inclusive sum W_k = sum_{k' <= k} rho(q_k') ds, ds = Dd sqrt(1 +
+// (u^2 + v^2)/SAD^2); the primary is P_k = F (SAD / d_k)^2 DD(W_k).
+// MARCH_ADJOINT instead accumulates A = sum_k H_k (SAD / d_k)^2 DD(W_k) (the
+// adjoint of the primary w.r.t. F); MARCH_GEOMETRY stores the aperture-independent
+// factor G_k = (SAD / d_k)^2 DD(W_k) itself (rounded to E), so that P = F G later.
 enum { MARCH_PRIMARY = 0, MARCH_ADJOINT = 1, MARCH_GEOMETRY = 2 };
 
+// ---- serial form (the default)
 //
-// With a box (the aperture rectangle of each control point, given when the
-// convolution honours it) rays outside it are skipped: the convolution never
-// reads P there, and the adjoint's A there is written as 0 (the parameter
-// gradients only read it inside).
+// One thread per divergent ray (i, j) walks its Nk planes in order with a
+// compensated running sum; eight planes' density loads are in flight at a time.
+// Lanes run along v, i.e. along patient z, so the z-fastest density copy is read
+// almost contiguously.  With a box (the aperture rectangle of each control point,
+// given when the convolution honours it) rays outside it are skipped: the
+// convolution never reads P there, and the adjoint's A there is written as 0
+// (the parameter gradients only read it inside).
 // One ray (i, j) of control point b.
 template <typename T, int MODE, typename E>
 __device__ __forceinline__ void march_ray(const Geo<T>& g, int b, int i, int j, const T* __restrict__ frame,
@@ -287,7 +290,7 @@ __device__ __forceinline__ void march_ray(const Geo<T>& g, int b, int i, int j, 
 // so no lanes idle on rays outside it.  (In adjoint mode A outside the box is
 // cleared beforehand.)
 template <typename T, int MODE, typename E>
-__global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ frame, const T* __restrict__ rho_t,
+__global__ void __launch_bounds__(256) k_march_serial(Geo<T> g, const T* __restrict__ frame, const T* __restrict__ rho_t,
                                                const T* __restrict__ F, const T* __restrict__ zca,
                                                const T* __restrict__ dd, E* __restrict__ vol, T* __restrict__ A,
                                                const int* __restrict__ box) {
@@ -309,38 +312,212 @@ __global__ void __launch_bounds__(256) k_march(Geo<T> g, const T* __restrict__ f
   }
 }
 
+// ---- segmented scan (spec->march_scan)
+//
+// The inclusive sum as a segmented scan across the wavefronts of a workgroup.
+// The workgroup takes 64 rays (lanes along v, so that neighbouring lanes read
+// neighbouring z of the z-fastest density copy) and its NW wavefronts take
+// consecutive segments of the Nk planes: each wavefront samples its segment
+// (samples kept in registers, MARCH_SEG planes per pass) and forms the segment's
+// compensated sum; the segment sums go through LDS and each wavefront adds those
+// of the segments before its own in plane order (its carry); it then rescans its
+// segment from the carry, giving W_k for its planes, and applies the depth dose.
+// In adjoint mode the wavefronts' partial sums of H_k (SAD/d_k)^2 DD(W_k) are
+// added in LDS in segment order.  Every sum runs in a fixed order.
+//
+// With a box (the aperture rectangle of each control point, given when the
+// convolution honours it) only the rays inside it are marched: the convolution
+// never reads P outside it, and the adjoint's A there is written as 0 beforehand
+// (the parameter gradients only read it inside).
+constexpr int MARCH_SEG = kMarchSeg;           // planes per wavefront and pass
+constexpr int MARCH_MAXW = kMarchMaxSegments;  // wavefronts per workgroup
+
+template <typename T>
+__device__ __forceinline__ void kahan_add(T& S, T& c, T x) {
+  const T y = x - c;
+  const T t = S + y;
+  c = (t - S) - y;
+  S = t;
+}
+
+template <typename T, int MODE, typename E>
+__global__ void __launch_bounds__(64 * MARCH_MAXW) k_march_scan(Geo<T> g, const T* __restrict__ frame,
+                                                           const T* __restrict__ rho_t, const T* __restrict__ F,
+                                                           const T* __restrict__ zca, const T* __restrict__ dd,
+                                                           E* __restrict__ vol, T* __restrict__ A,
+                                                           const int* __restrict__ box) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* seg = reinterpret_cast<T*>(smem_raw);  // [2][MARCH_MAXW][64]: segment sums and compensations
+  T* tab = seg + 2 * MARCH_MAXW * 64;       // depth-dose table [n_dd]
+  const int nw = blockDim.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int q = tid; q < g.n_dd; q += blockDim.x) tab[q] = dd[q];
+  __syncthreads();
+  const int b = blockIdx.y;
+  const int plane = g.Nu * g.Nv;
+  int u0 = 0, nu = g.Nu, v0 = 0, nv = g.Nv;
+  if (box) {
+    const int* bx = box + 4 * b;
+    u0 = bx[0], v0 = bx[2];
+    nu = max(0, bx[1] - bx[0]), nv = max(0, bx[3] - bx[2]);
+  }
+  const int area = nu * nv;
+  const int kb = (g.Nk * w) / nw, ke = (g.Nk * (w + 1)) / nw;  // this wavefront's planes
+  const bool per_ray = g.wepl_mode == PDRT_WEPL_PER_RAY;
+  const bool keep = ke - kb <= MARCH_SEG;  // one pass holds the whole segment
+  const T sn = frame[2 * b], cs = frame[2 * b + 1];
+  const T* zb = zca + (size_t)b * g.Nk;
+  for (int grp = blockIdx.x; grp * 64 < area; grp += gridDim.x) {
+    const int rr = grp * 64 + lane;
+    const bool valid = rr < area;
+    const int li = valid ? rr / nv : 0;
+    const int i = u0 + li, j = v0 + (valid ? rr - li * nv : 0);
+    const int r = i * g.Nv + j;
+    const T u = (T(i) - g.cu) * g.lat, v = (T(j) - g.cv) * g.lat;
+    const T ucs = u * cs, usn = u * sn;
+    const T ds = g.dstep * dsqrt(T(1) + (u * u + v * v) * (g.inv_sad * g.inv_sad));
+    // samples rho ds of planes k0 .. k0 + MARCH_SEG - 1 (zero past the segment),
+    // four planes' corner loads issued together before they are combined
+    T y[MARCH_SEG];
+    auto sample_pass = [&](int k0) {
+#pragma unroll
+      for (int s0 = 0; s0 < MARCH_SEG; s0 += 4) {
+        RhoFetch<T> fr[4];
+#pragma unroll
+        for (int s1 = 0; s1 < 4; ++s1) {
+          const int k = min(k0 + s0 + s1, g.Nk - 1);
+          const T e = g.e0 + T(k) * g.dstep;
+          const T gk = T(1) + e * g.inv_sad;
+          const T X = g.iso_ix + (-e * sn + gk * ucs) * g.inv_sx;
+          const T Y = g.iso_iy + (e * cs + gk * usn) * g.inv_sy;
+          const T Z = g.iso_iz + (gk * v) * g.inv_sz;
+          fr[s1] = rho_fetch(rho_t, g.nx, g.ny, g.nz, X, Y, Z);
+        }
+#pragma unroll
+        for (int s1 = 0; s1 < 4; ++s1)
+          y[s0 + s1] = k0 + s0 + s1 < ke ? rho_combine(fr[s1]) * ds : T(0);
+      }
+    };
+    T S = T(0), cS = T(0);
+    if (per_ray) {
+      for (int k0 = kb; k0 < ke; k0 += MARCH_SEG) {
+        sample_pass(k0);
+#pragma unroll
+        for (int s2 = 0; s2 < MARCH_SEG; ++s2)
+          if (k0 + s2 < ke) kahan_add(S, cS, y[s2]);
+      }
+      seg[w * 64 + lane] = S;
+      seg[(MARCH_MAXW + w) * 64 + lane] = cS;
+    }
+    __syncthreads();
+    // carry: the sums of the segments before this one, in plane order
+    T W = T(0), cW = T(0);
+    if (per_ray)
+      for (int w2 = 0; w2 < w; ++w2) kahan_add(W, cW, seg[w2 * 64 + lane] - seg[(MARCH_MAXW + w2) * 64 + lane]);
+    T Fv = T(1);
+    if (MODE == MARCH_PRIMARY && valid) Fv = F[(size_t)b * plane + r];
+    E* vb = vol + (size_t)b * g.Nk * plane + r;
+    T acc = T(0);
+    for (int k0 = kb; k0 < ke; k0 += MARCH_SEG) {
+      if (per_ray && !keep) sample_pass(k0);
+#pragma unroll
+      for (int s2 = 0; s2 < MARCH_SEG; ++s2) {
+        const int k = k0 + s2;
+        if (k < ke) {
+          T Wk;
+          if (per_ray) {
+            kahan_add(W, cW, y[s2]);
+            Wk = W;
+          } else {
+            Wk = zb[k];
+          }
+          const T e = g.e0 + T(k) * g.dstep;
+          const T gk = T(1) + e * g.inv_sad;
+          const T geo = dd_lookup(tab, g.n_dd, g.inv_dd_step, Wk) / (gk * gk);
+          if (valid) {
+            if (MODE == MARCH_ADJOINT)
+              acc = fma(T(vb[(size_t)k * plane]), geo, acc);
+            else if (MODE == MARCH_PRIMARY)
+              vb[(size_t)k * plane] = Fv * geo;
+            else
+              vb[(size_t)k * plane] = E(geo);
+          }
+        }
+      }
+    }
+    if (MODE == MARCH_ADJOINT) {
+      __syncthreads();
+      seg[w * 64 + lane] = acc;
+      __syncthreads();
+      if (w == 0 && valid) {
+        T a = T(0);
+        for (int w2 = 0; w2 < nw; ++w2) a += seg[w2 * 64 + lane];
+        A[(size_t)b * plane + r] = a;
+      }
+    }
+    __syncthreads();  // the segment sums are reused by the next group
+  }
+}
+
 template <typename T>
 __global__ void k_fill_zero(size_t n, T* __restrict__ p) {
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
     p[q] = T(0);
 }
 
-// Blocks per control point for a box-restricted march: enough for the largest
-// jaw rectangle the field limit allows (the plane minus the kernel halo, plus the
-// rectangle's margins); the walk is grid-stride, so a larger box (fluence
-// corrections, jaws beyond the field limit) is still covered.
+// Workgroups per control point: enough for the 64-ray groups of the largest jaw
+// rectangle the field limit allows (the plane minus the kernel halo, plus the
+// rectangle's margins); the groups are walked grid-stride, so a larger rectangle
+// (fluence corrections, collimator rotation, jaws beyond the field limit) is
+// still covered.  Without a box, the groups of the whole plane.
+template <typename T>
+int march_groups(const Geo<T>& g, const int* box) {
+  if (!box) return (g.Nu * g.Nv + 63) / 64;
+  const int bu = min(g.Nu, g.Nu - 2 * g.h + 6), bv = min(g.Nv, g.Nv - 2 * g.h + 6);
+  return max(1, (bu * bv + 63) / 64);
+}
+
+// Blocks per control point for the serial form with a box: enough for the
+// largest jaw rectangle the field limit allows (the walk is grid-stride, so a
+// larger box is still covered).
 template <typename T>
 int march_box_blocks(const Geo<T>& g) {
   const int bu = min(g.Nu, g.Nu - 2 * g.h + 6), bv = min(g.Nv, g.Nv - 2 * g.h + 6);
   return max(1, (bu * bv + 255) / 256);
 }
 
+// The scan's wavefronts per workgroup: segments of at most MARCH_SEG planes where
+// eight wavefronts suffice (Nk <= 256), else eight segments of several passes.
+template <typename T, int MODE, typename E>
+hipError_t launch_march_mode(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* F, const T* z,
+                             const T* dd, E* vol, T* A, hipStream_t s, const int* box) {
+  if (!g.march_scan) {
+    dim3 grid(box ? march_box_blocks(g) : (g.Nu * g.Nv + 255) / 256, nb);
+    hipLaunchKernelGGL((k_march_serial<T, MODE, E>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t, F, z,
+                       dd, vol, A, box);
+    return hipGetLastError();
+  }
+  const int nw = march_segments(g.Nk);
+  const size_t lds = sizeof(T) * (2 * MARCH_MAXW * 64 + (size_t)g.n_dd);
+  if (lds > 64 * 1024) return hipErrorInvalidConfiguration;
+  dim3 grid(march_groups(g, box), nb);
+  hipLaunchKernelGGL((k_march_scan<T, MODE, E>), grid, dim3(64 * nw), lds, s, g, frame, rho_t, F, z, dd, vol, A,
+                     box);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_march(const Geo<T>& g, int nb, const T* frame, const T* rho_t, const T* F, const T* z, const T* dd,
                         T* P, hipStream_t s, const int* box) {
-  dim3 grid(box ? march_box_blocks(g) : (g.Nu * g.Nv + 255) / 256, nb);
-  hipLaunchKernelGGL((k_march<T, MARCH_PRIMARY, T>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t, F, z,
-                     dd, P, (T*)nullptr, box);
-  return hipGetLastError();
+  return launch_march_mode<T, MARCH_PRIMARY, T>(g, nb, frame, rho_t, F, z, dd, P, (T*)nullptr, s, box);
 }
 
 template <typename E>
 hipError_t launch_march_geometry(const Geo<float>& g, int nb, const float* frame, const float* rho_t, const float* z,
                                  const float* dd, E* G, hipStream_t s) {
-  dim3 grid((g.Nu * g.Nv + 255) / 256, nb);
-  hipLaunchKernelGGL((k_march<float, MARCH_GEOMETRY, E>), grid, dim3(256), g.n_dd * sizeof(float), s, g, frame,
-                     rho_t, (const float*)nullptr, z, dd, G, (float*)nullptr, (const int*)nullptr);
-  return hipGetLastError();
+  return launch_march_mode<float, MARCH_GEOMETRY, E>(g, nb, frame, rho_t, (const float*)nullptr, z, dd, G,
+                                                     (float*)nullptr, s, (const int*)nullptr);
 }
 template hipError_t launch_march_geometry<float>(const Geo<float>&, int, const float*, const float*, const float*,
                                                  const float*, float*, hipStream_t);
@@ -356,10 +533,8 @@ hipError_t launch_march_adj(const Geo<T>& g, int nb, const T* frame, const T* rh
                        s, n, A);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
   }
-  dim3 grid(box ? march_box_blocks(g) : (g.Nu * g.Nv + 255) / 256, nb);
-  hipLaunchKernelGGL((k_march<T, MARCH_ADJOINT, T>), grid, dim3(256), g.n_dd * sizeof(T), s, g, frame, rho_t,
-                     (const T*)nullptr, z, dd, const_cast<T*>(H), A, box);
-  return hipGetLastError();
+  return launch_march_mode<T, MARCH_ADJOINT, T>(g, nb, frame, rho_t, (const T*)nullptr, z, dd, const_cast<T*>(H), A,
+                                                s, box);
 }
 
 // ------------------------------------------------------------------ kernel taps

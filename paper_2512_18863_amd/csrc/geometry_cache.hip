@@ -10,7 +10,7 @@
 // HBM for all control points.  Each forward then replaces the march by
 //   k_apply_geometry   P[b][k] = F[b] G[b][k]
 // and each backward replaces the adjoint march by
-//   k_geometry_adjoint A[b] = sum_k H[b][k] G[b][k]   (k ascending, fused multiply-add)
+//   k_geometry_adjoint A[b] = sum_k H[b][k] G[b][k]   (the march's segments and order)
 // With an FP32 cache both produce exactly the values of the march (the same
 // products and the same sum order); a BF16 cache halves the bytes read and
 // rounds G to 8 significant bits.
@@ -48,7 +48,8 @@ __global__ void __launch_bounds__(256) k_apply_geometry(int Nk, int Nv, int plan
 }
 
 template <typename E>
-__global__ void __launch_bounds__(256) k_geometry_adjoint(int Nk, int Nv, int plane, const float* __restrict__ H,
+__global__ void __launch_bounds__(256) k_geometry_adjoint(int Nk, int nseg, int Nv, int plane,
+                                                          const float* __restrict__ H,
                                                           const E* __restrict__ G, float* __restrict__ A,
                                                           const int* __restrict__ box) {
   const int b = blockIdx.y;
@@ -60,10 +61,17 @@ __global__ void __launch_bounds__(256) k_geometry_adjoint(int Nk, int Nv, int pl
   }
   const E* gb = G + (size_t)b * Nk * plane + r;
   const float* hb = H + (size_t)b * Nk * plane + r;
-  float acc = 0.f;
+  // the march's order: each segment's fused multiply-adds in plane order, then the
+  // segments' sums in segment order
+  float a = 0.f;
+  for (int w = 0; w < nseg; ++w) {
+    float acc = 0.f;
 #pragma unroll 4
-  for (int k = 0; k < Nk; ++k) acc = fmaf(hb[(size_t)k * plane], (float)gb[(size_t)k * plane], acc);
-  A[(size_t)b * plane + r] = acc;
+    for (int k = (Nk * w) / nseg; k < (Nk * (w + 1)) / nseg; ++k)
+      acc = fmaf(hb[(size_t)k * plane], (float)gb[(size_t)k * plane], acc);
+    a += acc;
+  }
+  A[(size_t)b * plane + r] = a;
 }
 
 }  // namespace
@@ -81,8 +89,9 @@ template <typename E>
 hipError_t launch_geometry_adjoint(const Geo<float>& g, int nb, const float* H, const E* G, float* A, hipStream_t s,
                                    const int* box) {
   const int plane = g.Nu * g.Nv;
-  hipLaunchKernelGGL(k_geometry_adjoint<E>, dim3((plane + 255) / 256, nb), dim3(256), 0, s, g.Nk, g.Nv, plane, H, G,
-                     A, box);
+  const int nseg = g.march_scan ? march_segments(g.Nk) : 1;
+  hipLaunchKernelGGL(k_geometry_adjoint<E>, dim3((plane + 255) / 256, nb), dim3(256), 0, s, g.Nk, nseg, g.Nv, plane,
+                     H, G, A, box);
   return hipGetLastError();
 }
 

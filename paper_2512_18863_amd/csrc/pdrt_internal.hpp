@@ -45,6 +45,8 @@ struct Geo {
   // fluence corrections (off when fcorr == 0); the blur taps travel separately
   int fcorr;
   T hs_amp, oar0, oar1;
+  // ray march: 0 = one thread per ray (serial), 1 = segmented scan across wavefronts
+  int march_scan;
 };
 
 // Unit-sum taps of one Gaussian blur, radius R <= PDRT_MAX_BLUR_RADIUS.
@@ -59,6 +61,18 @@ struct Layout {
   size_t frame, rho_t, fluence, depth, vol0, vol1, adj, comp, fc_tmp, box, cframe, rot, total;
   int batch;
 };
+
+// The scan form of the ray march splits the Nk planes of a ray into segments
+// scanned by separate wavefronts (segment w = planes [Nk w / n, Nk (w + 1) / n) of
+// n = march_segments segments); its adjoint sums each segment in plane order and
+// adds the segments' sums in segment order (the serial form: one segment).  The
+// cached geometry adjoint follows the same order so that both give the same bits.
+constexpr int kMarchSeg = 32;  // planes per segment and sampling pass
+constexpr int kMarchMaxSegments = 8;
+__host__ __device__ inline int march_segments(int Nk) {
+  const int n = (Nk + kMarchSeg - 1) / kMarchSeg;
+  return n < 1 ? 1 : (n > kMarchMaxSegments ? kMarchMaxSegments : n);
+}
 
 // Raises a kernel's dynamic-LDS limit to at least `bytes` on the current device.
 // Each (device, kernel) pair is set once, or again when a larger limit is asked

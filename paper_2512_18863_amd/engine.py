@@ -49,7 +49,8 @@ class Spec(ctypes.Structure):
                 ("kpoly", (ctypes.c_double * 4) * 4), ("kz_max_mm", ctypes.c_double),
                 ("max_cp_batch", ctypes.c_int32),
                 ("fluence_corr", ctypes.c_int32), ("pen_fwhm_mm", ctypes.c_double * 2),
-                ("hs_amp", ctypes.c_double), ("hs_sigma_mm", ctypes.c_double), ("oar", ctypes.c_double * 2)]
+                ("hs_amp", ctypes.c_double), ("hs_sigma_mm", ctypes.c_double), ("oar", ctypes.c_double * 2),
+                ("march_scan", ctypes.c_int32)]
 
 
 def set_fluence_corrections(s: "Spec", m) -> None:
@@ -165,7 +166,7 @@ class DoseEngine:
 
     def __init__(self, case: "_inputs.Case", *, n_taps: Optional[int] = None, conv: str = "fp32",
                  wepl_mode: Optional[int] = None, device="cuda", max_cp_batch: int = 0,
-                 calib: Optional[float] = None, with_f64: bool = False):
+                 calib: Optional[float] = None, with_f64: bool = False, march_scan: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("DoseEngine needs a GPU")
         lib()
@@ -215,6 +216,7 @@ class DoseEngine:
                 s.kpoly[a][c] = float(m.kpoly[a][c])
         s.kz_max_mm = m.kz_max
         s.max_cp_batch = max_cp_batch
+        s.march_scan = 1 if march_scan else 0
         set_fluence_corrections(s, m)
         self.spec = s
         dims = (ctypes.c_int32 * 3)()
