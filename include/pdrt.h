@@ -371,12 +371,15 @@ int pdrt_net_head(int32_t n, int32_t c, const void* x, const float* hw, const fl
 size_t pdrt_net_head_ws_bytes(int32_t n, int32_t c);
 int pdrt_net_head_backward(int32_t n, int32_t c, const void* x, const float* hw, const float* gp, const float* gr,
                            void* dx, float* ws, size_t ws_bytes, float* dhead, void* stream);
-/* Training loss L = inv_count sum mask [(pred - t s)^2 + lam (resid - |pred - t s|)^2]
- * (t = target, s = tscale[0]) and its gradients gp, gr; loss[0] = L. */
+/* Training loss L = inv_count sum mask [(pred - t s)^2 + lam R] (t = target, s =
+ * tscale[0], e = pred - t s) with R = (resid - |e|)^2 for quantile == 0, or, for
+ * 0 < quantile < 1, the pinball loss R = u (quantile - [u < 0]), u = |e| - resid,
+ * whose minimiser is the quantile of |e| (an upper bound of the local error for a
+ * quantile near 1); its gradients gp (of the first term only) and gr; loss[0] = L. */
 size_t pdrt_net_loss_ws_bytes(int32_t n);
 int pdrt_net_train_loss(int32_t n, const float* pred, const float* resid, const float* target, const float* tscale,
-                        const float* mask, float inv_count, float lam, float* gp, float* gr, float* ws,
-                        size_t ws_bytes, float* loss, void* stream);
+                        const float* mask, float inv_count, float lam, float quantile, float* gp, float* gr,
+                        float* ws, size_t ws_bytes, float* loss, void* stream);
 /* stats[0] = max pred, stats[1] = max resid over pred >= frac * max pred (device);
  * ws: device, at least pdrt_net_reduce_ws_bytes(n). */
 int pdrt_net_fallback_stats(int32_t n, const float* pred, const float* resid, float frac, float* stats, void* ws,

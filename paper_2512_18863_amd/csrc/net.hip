@@ -451,7 +451,7 @@ __global__ void __launch_bounds__(256) k_head_bwd(int P, int C, const __bf16* __
 __global__ void __launch_bounds__(256) k_train_loss(int P, const float* __restrict__ pred,
                                                     const float* __restrict__ resid, const float* __restrict__ target,
                                                     const float* __restrict__ tscale, const float* __restrict__ mask,
-                                                    float inv_count, float lam, float* __restrict__ gp,
+                                                    float inv_count, float lam, float tau, float* __restrict__ gp,
                                                     float* __restrict__ gr, float* __restrict__ part) {
   __shared__ float red[256];
   int p = blockIdx.x * 256 + threadIdx.x;
@@ -461,9 +461,16 @@ __global__ void __launch_bounds__(256) k_train_loss(int P, const float* __restri
     float e = pred[p] - target[p] * tscale[0];
     float ae = fabsf(e);
     float er = resid[p] - ae;
-    l = m * (e * e + lam * er * er) * inv_count;
+    if (tau > 0.f) {
+      // pinball loss of the tau-quantile of |e|: u (tau - [u < 0]), u = |e| - resid
+      const float below = er > 0.f ? 1.f : 0.f;  // u < 0
+      l = m * (e * e - lam * er * (tau - below)) * inv_count;
+      gr[p] = m * lam * (below - tau) * inv_count;
+    } else {
+      l = m * (e * e + lam * er * er) * inv_count;
+      gr[p] = m * 2.f * lam * er * inv_count;
+    }
     gp[p] = m * 2.f * e * inv_count;
-    gr[p] = m * 2.f * lam * er * inv_count;
   }
   red[threadIdx.x] = l;
   __syncthreads();
@@ -735,10 +742,10 @@ hipError_t launch_head_bwd(int P, int C, const __bf16* X, const float* hw, const
 }
 
 hipError_t launch_train_loss(int P, const float* pred, const float* resid, const float* target, const float* tscale,
-                             const float* mask, float inv_count, float lam, float* gp, float* gr, float* part,
-                             hipStream_t s) {
+                             const float* mask, float inv_count, float lam, float tau, float* gp, float* gr,
+                             float* part, hipStream_t s) {
   hipLaunchKernelGGL(k_train_loss, dim3(nblk(P)), dim3(256), 0, s, P, pred, resid, target, tscale, mask, inv_count,
-                     lam, gp, gr, part);
+                     lam, tau, gp, gr, part);
   return hipGetLastError();
 }
 

@@ -156,13 +156,14 @@ int pdrt_net_head_backward(int32_t n, int32_t c, const void* x, const float* hw,
 size_t pdrt_net_loss_ws_bytes(int32_t n) { return n < 1 ? 0 : sizeof(float) * (size_t)((n + 255) / 256); }
 
 int pdrt_net_train_loss(int32_t n, const float* pred, const float* resid, const float* target, const float* tscale,
-                        const float* mask, float inv_count, float lam, float* gp, float* gr, float* ws,
-                        size_t ws_bytes, float* loss, void* stream) {
+                        const float* mask, float inv_count, float lam, float quantile, float* gp, float* gr,
+                        float* ws, size_t ws_bytes, float* loss, void* stream) {
   if (n < 1 || !pred || !resid || !target || !tscale || !mask || !gp || !gr || !loss) return PDRT_E_INVALID;
   if (!std::isfinite(inv_count) || !std::isfinite(lam)) return PDRT_E_INVALID;
+  if (!(quantile >= 0.f && quantile < 1.f)) return PDRT_E_INVALID;
   if (!ws || ws_bytes < pdrt_net_loss_ws_bytes(n)) return PDRT_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  PDRT_TIMED("train_loss", s, launch_train_loss(n, pred, resid, target, tscale, mask, inv_count, lam, gp, gr, ws, s));
+  PDRT_TIMED("train_loss", s, launch_train_loss(n, pred, resid, target, tscale, mask, inv_count, lam, quantile, gp, gr, ws, s));
   PDRT_TIMED("reduce_splits", s, launch_reduce_splits((n + 255) / 256, 1, ws, loss, s));
   return PDRT_OK;
 }

@@ -171,8 +171,8 @@ hipError_t launch_head(int P, int C, const __bf16* X, const float* hw, const flo
 hipError_t launch_head_bwd(int P, int C, const __bf16* X, const float* hw, const float* gp, const float* gr,
                            __bf16* dX, float* part, hipStream_t s);
 hipError_t launch_train_loss(int P, const float* pred, const float* resid, const float* target, const float* tscale,
-                             const float* mask, float inv_count, float lam, float* gp, float* gr, float* part,
-                             hipStream_t s);
+                             const float* mask, float inv_count, float lam, float tau, float* gp, float* gr,
+                             float* part, hipStream_t s);
 hipError_t launch_reduce_splits(int nsplit, size_t n, const float* part, float* out, hipStream_t s);
 hipError_t launch_fallback_stats(int P, const float* pred, const float* resid, float frac, float* stats, void* ws,
                                  hipStream_t s);

@@ -16,6 +16,7 @@ fastest ([nz][ny][nx]); the isocentre sits at the grid centre, voxel centres at
 """
 from __future__ import annotations
 
+import copy
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -309,6 +310,33 @@ def config_c4_plan(p: int, n_taps: int = 61, bench: bool = False) -> Case:
     limit = (40.0, 40.0) if bench else (50.0, 50.0)
     return Case(name, hu, sp, origin, (0.0, 0.0, 0.0), gantry, leaves, jaws_square(n_cp, jx, jy), mu,
                 n_taps, limit, m)
+
+
+C4_OOD_KINDS = ("bone_air_slabs", "lung_body", "bone_body", "water")
+
+
+def config_c4_ood(kind: str, p: int = 2000) -> Case:
+    """Held-out plan p of the randomised pelvis workload on an anatomy unlike any
+    training phantom, for the learned correction's error estimate: "bone_air_slabs"
+    (the whole grid alternates 24 mm slabs of 1500 HU and -1000 HU along z),
+    "lung_body" / "bone_body" (soft tissue of the phantom set to -700 / 900 HU), or
+    "water" (0 HU everywhere)."""
+    base = config_c4_plan(p)
+    c = copy.copy(base)
+    h = base.hu
+    if kind == "bone_air_slabs":
+        z = np.arange(h.shape[0])[:, None, None]
+        c.hu = (np.where((z // 8) % 2 == 0, 1500.0, -1000.0) * np.ones_like(h)).astype(np.float32)
+    elif kind in ("lung_body", "bone_body"):
+        h = h.copy()
+        h[(h > -900) & (h < 500)] = -700.0 if kind == "lung_body" else 900.0
+        c.hu = h
+    elif kind == "water":
+        c.hu = np.zeros_like(h)
+    else:
+        raise ValueError("unknown anatomy %r" % kind)
+    c.name = "C4-%d-%s" % (p, kind)
+    return c
 
 
 def tiny_case(seed: int = 7, n_cp: int = 2, n_taps: int = 3, shape=(6, 6, 6), spacing: float = 10.0,

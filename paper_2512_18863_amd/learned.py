@@ -20,6 +20,7 @@ with s = 1 / max(small-kernel dose).  All 3x3x3 convolutions are ReLU'd.
 from __future__ import annotations
 
 import ctypes
+import math
 import time
 
 import numpy as np
@@ -64,8 +65,8 @@ def _lib():
             "pdrt_net_head_ws_bytes": (ctypes.c_size_t, [I32, I32]),
             "pdrt_net_head_backward": (ctypes.c_int, [I32, I32, V, V, V, V, V, V, ctypes.c_size_t, V, V]),
             "pdrt_net_loss_ws_bytes": (ctypes.c_size_t, [I32]),
-            "pdrt_net_train_loss": (ctypes.c_int, [I32, V, V, V, V, V, ctypes.c_float, ctypes.c_float, V, V, V,
-                                                   ctypes.c_size_t, V, V]),
+            "pdrt_net_train_loss": (ctypes.c_int, [I32, V, V, V, V, V, ctypes.c_float, ctypes.c_float,
+                                                   ctypes.c_float, V, V, V, ctypes.c_size_t, V, V]),
             "pdrt_net_fallback_stats": (ctypes.c_int, [I32, V, V, ctypes.c_float, V, V, ctypes.c_size_t, V]),
             "pdrt_adam_step": (ctypes.c_int, [ctypes.c_size_t, V, V, V, V, ctypes.c_float, ctypes.c_float,
                                               ctypes.c_float, ctypes.c_float, I32, V]),
@@ -281,14 +282,27 @@ class Net3D:
                                   b1, b2, eps, self.t, self._s()), "adam")
         self.prepare()
 
-    def train_loss(self, target, mask, count, lam=1.0):
+    def train_loss(self, target, mask, count, lam=1.0, quantile=0.0):
         lib, s = _lib(), self._s()
         n0 = self.npos[0]
         inv = 1.0 / max(1.0, float(count))
         _ck(lib.pdrt_net_train_loss(n0, _p(self.pred), _p(self.resid), _p(target), _p(self.scale), _p(mask), inv,
-                                    lam, _p(self.gp), _p(self.gr), _p(self.ws), self.ws_bytes, _p(self.loss), s),
-            "loss")
+                                    lam, quantile, _p(self.gp), _p(self.gr), _p(self.ws), self.ws_bytes,
+                                    _p(self.loss), s), "loss")
         return self.loss
+
+    def resid_head_slices(self):
+        """Index ranges of the error head's parameters (its weights and bias)."""
+        o = self.head_off
+        return (o + HEAD_C, o + 2 * HEAD_C), (o + 2 * HEAD_C + 1, o + 2 * HEAD_C + 2)
+
+    def scale_error_head(self, k):
+        """Multiply the error estimate by k > 0 (the head is linear in its weights)."""
+        if not (k > 0.0 and math.isfinite(k)):
+            raise ValueError("error-head scale must be positive and finite")
+        for a, b in self.resid_head_slices():
+            self.params[a:b] *= k
+        self.prepare()
 
     def state(self):
         return {"params": self.params.cpu().numpy(), "m": self.m.cpu().numpy(), "v": self.v.cpu().numpy(),
@@ -337,15 +351,23 @@ def pair(plan_index, small=9, large=61, device="cuda"):
     return ds, dl, e_small.rho.reshape(-1), case
 
 
-def train(net: Net3D, plans, steps, lr=1e-3, log_every=50, lam=1.0, log=print):
-    """Train on precomputed pairs [(ds, dl, rho, mask)], cycling through them."""
+def train(net: Net3D, plans, steps, lr=1e-3, log_every=50, lam=1.0, log=print, quantile=0.0, error_head_only=False):
+    """Train on precomputed pairs [(ds, dl, rho, mask)], cycling through them.  With
+    error_head_only the gradients of every parameter but the error head's are
+    cleared before each update (the prediction is left as it is)."""
     t0 = time.perf_counter()
     hist = []
+    keep = net.resid_head_slices() if error_head_only else None
     for it in range(steps):
         ds, dl, rho, mask, count = plans[it % len(plans)]
         net.forward(ds, rho)
-        loss = net.train_loss(dl, mask, count, lam)
+        loss = net.train_loss(dl, mask, count, lam, quantile)
         net.backward(net.gp, net.gr, weights=True)
+        if keep:
+            (a0, a1), (b0, b1) = keep
+            net.grads[:a0].zero_()
+            net.grads[a1:b0].zero_()
+            net.grads[b1:].zero_()
         net.adam(lr)
         if (it + 1) % log_every == 0 or it == 0:
             lv = float(loss)

@@ -174,6 +174,60 @@ def test_pool_upsample_head_loss_adam():
     assert torch.allclose(wgpu.cpu(), wref.detach(), rtol=1e-5, atol=1e-6)
 
 
+@pytest.mark.parametrize("quantile", [0.0, 0.9])
+def test_train_loss_against_autograd(quantile):
+    """The training loss and its gradients against torch autograd on the CPU (FP64):
+    squared error of the prediction plus lam times either the squared error of the
+    error estimate (quantile 0) or the pinball loss of the quantile of |error|;
+    the second term's gradient reaches the error estimate only."""
+    from paper_2512_18863_amd.learned import _lib
+    _say("train loss, quantile %.2f" % quantile)
+    lib = _lib()
+    dev = "cuda"
+    s = torch.cuda.current_stream().cuda_stream
+    rng = np.random.default_rng(21)
+    n = 3000                                  # several blocks of 256 and a ragged tail
+    pred_h = torch.tensor(rng.normal(size=n), dtype=torch.float64)
+    resid_h = torch.tensor(rng.uniform(0.0, 2.0, size=n), dtype=torch.float64)
+    target_h = torch.tensor(rng.normal(size=n), dtype=torch.float64)
+    mask_h = torch.tensor(rng.uniform(size=n) < 0.7, dtype=torch.float64)
+    tscale, lam, count = 1.3, 0.7, float(mask_h.sum())
+    f32 = lambda a: a.to(torch.float32).to(dev)
+    pred, resid, target, mask = f32(pred_h), f32(resid_h), f32(target_h), f32(mask_h)
+    ts = torch.tensor([tscale], dtype=torch.float32, device=dev)
+    gp = torch.empty(n, dtype=torch.float32, device=dev)
+    gr = torch.empty(n, dtype=torch.float32, device=dev)
+    wsb = lib.pdrt_net_loss_ws_bytes(n)
+    ws = torch.empty(wsb // 4, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    assert lib.pdrt_net_train_loss(n, pred.data_ptr(), resid.data_ptr(), target.data_ptr(), ts.data_ptr(),
+                                   mask.data_ptr(), 1.0 / count, lam, quantile, gp.data_ptr(), gr.data_ptr(),
+                                   ws.data_ptr(), wsb, loss.data_ptr(), s) == 0
+    torch.cuda.synchronize()
+    # the reference sees the FP32 inputs
+    p = pred.double().cpu().requires_grad_()
+    r = resid.double().cpu().requires_grad_()
+    e = p - target.double().cpu() * float(ts.item())
+    m = mask.double().cpu()
+    # the error estimate's term does not reach the prediction (its |e| is a constant)
+    ae = e.detach().abs()
+    if quantile == 0.0:
+        term = (r - ae) ** 2
+    else:
+        u = ae - r
+        term = u * (quantile - (u < 0).double())
+    ref = (m * (e ** 2 + lam * term)).sum() / count
+    ref.backward()
+    assert abs(loss.item() - ref.item()) <= 1e-5 * abs(ref.item())
+    assert torch.allclose(gp.double().cpu(), p.grad, rtol=1e-5, atol=1e-7)
+    assert torch.allclose(gr.double().cpu(), r.grad, rtol=1e-5, atol=1e-7)
+    # the quantile must lie in [0, 1)
+    for bad in (-0.1, 1.0, float("nan")):
+        assert lib.pdrt_net_train_loss(n, pred.data_ptr(), resid.data_ptr(), target.data_ptr(), ts.data_ptr(),
+                                       mask.data_ptr(), 1.0 / count, lam, bad, gp.data_ptr(), gr.data_ptr(),
+                                       ws.data_ptr(), wsb, loss.data_ptr(), s) == -1
+
+
 def test_learned_training_reduces_loss_and_fallback_is_plain():
     """A few hundred steps on a handful of 64^3 plans reduce the training loss;
     forced to fall back, the learned path and returns the plain
@@ -340,4 +394,39 @@ def test_learned_held_out_plans_vs_plain_61():
         assert gp >= 0.995, p
         assert err <= 0.02, p
         del ld
+        torch.cuda.empty_cache()
+
+
+def test_learned_error_estimate_flags_unfamiliar_anatomy():
+    """The error head's estimate as a failure detector, on held-out plan 2000: on its
+    own pelvis and on anatomies whose learned-dose error stays in the usual range
+    (soft tissue set to lung or bone density, all water) the largest estimate stays
+    below 1 % of the largest dose and the learned dose is used; on a grid of
+    alternating 24 mm slabs of bone and air (no training phantom is like it) the
+    learned dose is off by more than 1 %, the estimate says so and the path falls
+    back to the plain 61 x 61 dose, bit for bit."""
+    import os
+    from paper_2512_18863_amd import engine as E
+    from paper_2512_18863_amd import inputs, learned
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2512_18863_amd", "data",
+                        "learned_c4.npz")
+    net = learned.Net3D.from_file(path, (128, 128, 128))
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    cases = [("pelvis", inputs.config_c4_plan(2000))] + [(k, inputs.config_c4_ood(k)) for k in inputs.C4_OOD_KINDS]
+    for kind, case in cases:
+        lv, jw, mu = t(case.leaves), t(case.jaws), t(case.mu)
+        plain = E.DoseEngine(case, n_taps=61).forward(lv, jw, mu)
+        raw = learned.LearnedDose(net, case, mode="never").forward(lv, jw, mu)
+        err = float((raw - plain).abs().max() / plain.max())
+        ld = learned.LearnedDose(net, case, mode="auto")
+        out = ld.forward(lv, jw, mu)
+        st = net.stats.cpu().numpy()
+        est = float(st[1] / st[0])
+        _say("plan 2000, %s: learned-dose max error %.3e, estimate %.3e, fallback %s" % (kind, err, est, ld.fell_back))
+        if kind == "bone_air_slabs":
+            assert err > 0.01 and est > ld.threshold and ld.fell_back
+            assert torch.equal(out, plain)
+        else:
+            assert err < 0.01 and est < ld.threshold and not ld.fell_back
+        del ld, raw, plain, out
         torch.cuda.empty_cache()
