@@ -16,6 +16,7 @@ python bench.py [--gpus 1] [--steps K] [--warmup W]
 from __future__ import annotations
 
 import argparse
+import fnmatch
 import hashlib
 import json
 import os
@@ -29,18 +30,28 @@ PEAK_HBM_GBS = 8000.0
 
 
 # kernels whose HBM counters are recorded in profiles/traffic.json: the library's
-# profile name -> (symbol prefixes in the kernel trace, sources the kernel is built from)
+# profile name -> (patterns of the kernel-trace symbol with blanks removed, sources
+# the kernel is built from)
 _CONV = ["conv_mfma.hip", "conv_common.hpp", "taps.hpp", "device_math.hpp", "pdrt_internal.hpp"]
+_CONV16 = ["conv_bf16.hip", "conv_common.hpp", "taps.hpp", "device_math.hpp", "pdrt_internal.hpp"]
 _FWD = ["dose_fwd.hip", "taps.hpp", "device_math.hpp", "pdrt_internal.hpp"]
 _BWD = ["dose_bwd.hip", "device_math.hpp", "pdrt_internal.hpp"]
 KERNELS = {
     "conv_mfma_f32": (("k_conv_mfma_f32<",), _CONV),
     "conv_mfma_f32_adj": (("k_conv_mfma_f32_adj<",), _CONV),
-    "march": (("k_march<float,0,",), _FWD),
-    "march_adj": (("k_march<float,1,",), _FWD),
+    # template arguments <NK, BR, BC, NWB, NWP, SUP>: forward 6 x 3 tiles in two
+    # wavefronts, adjoint 2 x 2 tiles in four
+    "conv_mfma_bf16": (("k_conv_bf16<*,6,3,2,1,*",), _CONV16),
+    "conv_mfma_bf16_adj": (("k_conv_bf16<*,2,2,1,4,*",), _CONV16),
+    "march": (("k_march_serial<float,0,",), _FWD),
+    "march_adj": (("k_march_serial<float,1,",), _FWD),
     "gather": (("k_gather<float",), _FWD),
     "backproject_adj": (("k_backproject_reg<float", "k_backproject_adj<float"), _BWD),
 }
+
+
+def _symbol_match(name, pattern):
+    return fnmatch.fnmatchcase(name.replace(" ", ""), "*" + pattern + "*")
 
 
 def kernel_source_hash(kernel: str) -> str:
@@ -71,7 +82,7 @@ def measured_traffic(kernel: str, workload: str):
 COPY_BYTES = 1 << 30   # the counter run's calibration copy
 
 
-def traffic_from_counters(fetch_csv, write_csv, workload="c4bench_fp32"):
+def traffic_from_counters(fetch_csv, write_csv, workload="c4bench"):
     """Write profiles/traffic.json from two rocprofv3 --pmc runs of `bench.py
     --counter-run` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Each counter is
     scaled by what it reads for the run's 1 GiB copy, so that the copy counts as
@@ -111,7 +122,7 @@ def traffic_from_counters(fetch_csv, write_csv, workload="c4bench_fp32"):
         rec["all_kernels_" + workload][k] = {"dispatches": cnt, "fetch_bytes_per_launch": fb / cnt,
                                              "write_bytes_per_launch": wb / cnt}
     for name, (syms, _src) in KERNELS.items():
-        hits = [(n, v, v2) for (n, v), (_, v2) in zip(fetch, write) if any(sy in n.replace(" ", "") for sy in syms)]
+        hits = [(n, v, v2) for (n, v), (_, v2) in zip(fetch, write) if any(_symbol_match(n, sy) for sy in syms)]
         if hits:
             fb = sum(h[1] for h in hits) * 1024.0 * kf / len(hits)
             wb = sum(h[2] for h in hits) * 1024.0 * kw / len(hits)
@@ -185,10 +196,12 @@ def roofline_entry(kernel, kernels, steps, work, traffic=None):
     if unit == "TFLOP/s":
         out["flops_per_launch"] = units
         out["dense_equivalent_TFLOPs"] = round(ach * work.dense_conv_flops / work.conv_flops, 3)
+        # the FP32 planes it must move once: the aperture nodes on one side, every node on the other
+        out["algorithmic_bytes_per_launch"] = 4 * work.ap_nodes + 4 * work.nodes
     else:
         out["algorithmic_bytes_per_launch"] = units
-    if traffic and unit == "GB/s":
-        out["traffic_over_algorithmic"] = round(traffic / units, 3)
+    if traffic:
+        out["traffic_over_algorithmic"] = round(traffic / out["algorithmic_bytes_per_launch"], 3)
     return out
 
 
@@ -458,7 +471,8 @@ def cpu_baseline(case, w, runs=3, cps=8):
 
 def counter_run(case, w):
     """A copy kernel of known size (1 GiB read + 1 GiB written) followed by one
-    FP32 forward and one backward of the benchmark plan."""
+    forward and one backward of the benchmark plan with the FP32 convolution, then
+    one of each with the BF16 convolution."""
     import torch
     from paper_2512_18863_amd import engine as E
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -466,12 +480,15 @@ def counter_run(case, w):
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
-    eng = E.DoseEngine(case, conv="fp32")
-    dev = eng.device
-    lv, jw, mu = _tensors(case, dev)
-    eng.forward(lv, jw, mu)
-    eng.backward(lv, jw, mu, torch.tensor(w, dtype=torch.float32, device=dev))
-    torch.cuda.synchronize()
+    for conv in ("fp32", "bf16"):
+        eng = E.DoseEngine(case, conv=conv)
+        dev = eng.device
+        lv, jw, mu = _tensors(case, dev)
+        eng.forward(lv, jw, mu)
+        eng.backward(lv, jw, mu, torch.tensor(w, dtype=torch.float32, device=dev))
+        torch.cuda.synchronize()
+        del eng
+        torch.cuda.empty_cache()
     print("counter run done", flush=True)
 
 
@@ -521,7 +538,7 @@ def main():
     d32 = r32["dose"]
     rl = {}
     for k in sorted(kernels):
-        e = roofline_entry(k, kernels, K, work, measured_traffic(k, "c4bench_fp32"))
+        e = roofline_entry(k, kernels, K, work, measured_traffic(k, "c4bench"))
         if e:
             rl[k] = e
     # the dominant kernel of the step: the one with the largest time per step
@@ -589,8 +606,8 @@ def main():
             "value": round(n_cp / (r16["median_ms"] / 1e3), 3), "ms_per_step": round(r16["median_ms"], 4),
             "forward_only": {"value": round(n_cp / (f16["median_ms"] / 1e3), 3), "ms": round(f16["median_ms"], 4)},
             "max_abs_err_vs_fp32_over_max": err, "gamma_1pct_1mm_vs_fp32": round(gp, 6),
-            "roofline_kernels": {k: roofline_entry(k, r16["kernels"], K, work) for k in r16["kernels"]
-                                 if k.startswith("conv_mfma_bf16")},
+            "roofline_kernels": {k: roofline_entry(k, r16["kernels"], K, work, measured_traffic(k, "c4bench"))
+                                 for k in r16["kernels"] if k.startswith("conv_mfma_bf16")},
             "kernels_ms_per_step": per_step(r16["kernels"], K)}
         engines["bf16"] = r16["eng"]
         del f16

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdrt.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build", "pdrt")
-SOURCES = ["api.hip", "dose_fwd.hip", "dose_bwd.hip", "conv_mfma.hip", "conv_bf16.hip", "conv_small.hip", "geometry_cache.hip",
+SOURCES = ["api.hip", "dose_fwd.hip", "dose_bwd.hip", "conv_mfma.hip", "conv_fwd_reg.hip", "conv_bf16.hip", "conv_small.hip", "geometry_cache.hip",
            "fluence_corr.hip", "collimator.hip", "plan_eval.hip", "net.hip", "net_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

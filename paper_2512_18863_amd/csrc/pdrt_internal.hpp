@@ -128,6 +128,10 @@ hipError_t launch_conv_small(const Geo<float>& g, int nb, const float* z, const 
                              hipStream_t s);
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                 hipStream_t s, const int* box = nullptr, int support = 0);
+// forward convolution with the aperture rectangle in registers (FP32, h <= 31)
+bool conv_fwd_reg_supported(const Geo<float>& g);
+hipError_t launch_conv_fwd_reg(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
+                               hipStream_t s, const int* box);
 hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                  hipStream_t s, const int* box = nullptr, int support = 0);
 template <typename T>

@@ -1,0 +1,153 @@
+"""CPU model of the register-resident forward convolution's indexing
+(paper_2512_18863_amd/csrc/conv_fwd_reg.hip): box chunks, K-step ranges, the
+clamped tap-row addresses, the matrix instructions' lane layout and the DPP row
+shifts that move each product p rows up and down, emulated lane by lane in FP64
+and compared with the direct convolution of the masked input
+(§2.2.6, Eq. 8: out[i][j] = sum_{p,q} K[p][q] in[i+p][j+q]).  The DPP shifts are
+modelled as row_shl:S (lane i takes lane i + S of its 16-lane row) and row_shr:S
+(lane i takes lane i - S), zero where the source lies outside the row; the GPU
+parity tests check the hardware against the oracle."""
+import numpy as np
+import pytest
+
+QB = 2          # output blocks above and below a row chunk
+NW_LANES = 64
+
+
+def mfma_16x16x4(a_lane, b_lane):
+    """D = A B for v_mfma_f32_16x16x4_f32: lane l gives A[l & 15][l >> 4] and
+    B[l >> 4][l & 15]; lane l holds D[4 (l >> 4) + e][l & 15], e = 0..3."""
+    A = np.zeros((16, 4))
+    B = np.zeros((4, 16))
+    for l in range(64):
+        A[l & 15, l >> 4] = a_lane[l]
+        B[l >> 4, l & 15] = b_lane[l]
+    D = A @ B
+    out = np.zeros((64, 4))
+    for l in range(64):
+        for e in range(4):
+            out[l, e] = D[4 * (l >> 4) + e, l & 15]
+    return out
+
+
+def row_shl(v, s):
+    out = np.zeros_like(v)
+    for l in range(64):
+        if (l & 15) + s < 16:
+            out[l] = v[l + s]
+    return out
+
+
+def row_shr(v, s):
+    out = np.zeros_like(v)
+    for l in range(64):
+        if (l & 15) - s >= 0:
+            out[l] = v[l - s]
+    return out
+
+
+def model(inp, box, h, kq, T, SU):
+    Nu, Nv = inp.shape
+    E, off = 2 * h + 37, h + 18
+    kx = np.zeros((h + 1, E))
+    for p in range(h + 1):
+        for x in range(E):
+            q = abs(x - off)
+            kx[p, x] = kq[p, q] if q <= h else 0.0
+    r0, r1, c0, c1 = max(box[0], 0), min(box[1], Nu), max(box[2], 0), min(box[3], Nv)
+    plane = np.zeros((Nu, Nv))
+    if r1 <= r0 or c1 <= c0:
+        return plane
+    NKS, NB = 4 * SU, T + 2 * QB
+    lanes = np.arange(64)
+    n, kk = lanes & 15, lanes >> 4
+    cw0, cw1 = max(0, c0 - h), min(Nv, c1 + h)
+    njt = (cw1 - cw0 + 15) // 16
+    nrc = (r1 - r0 + 16 * T - 1) // (16 * T)
+    ncc = (c1 - c0 + 16 * SU - 1) // (16 * SU)
+    wpitch = 16 * ((Nv + 15) // 16) + 4
+    win = np.zeros((Nu, wpitch))
+    for jt in range(njt):
+        J = cw0 + 16 * jt
+        assert J - cw0 + 16 <= wpitch
+        for rc in range(nrc):
+            R = r0 + 16 * T * rc
+            O = np.zeros((NB, 64, 4))
+            for cc in range(ncc):
+                C = c0 + 16 * SU * cc
+                B = np.zeros((T, NKS, 64))
+                for t in range(T):
+                    for ks in range(NKS):
+                        r, c = R + 16 * t + n, C + 4 * ks + kk
+                        ok = (r < r1) & (c < c1)
+                        B[t, ks, ok] = inp[r[ok], c[ok]]
+                nks = min(NKS, (c1 - C + 3) // 4)
+                lo, hi = J - h - C - 3, J + 15 + h - C
+                ka = 0 if lo <= 0 else (lo + 3) // 4
+                kb = min(nks - 1, hi // 4 if hi >= 0 else -1)
+                if ka > kb:
+                    continue
+                for p in range(h + 1):
+                    S, Q = p & 15, p >> 4
+                    A = np.zeros((NKS, 64))
+                    for ks in range(NKS):
+                        kc = min(max(ks, ka), kb)
+                        x = C + 4 * kc + kk - J - n + off
+                        assert x.min() >= 0 and x.max() < E, (x.min(), x.max(), E)
+                        A[ks] = kx[p, x]
+                    for t in range(T):
+                        y = np.zeros((64, 4))
+                        for ks in range(ka, kb + 1):
+                            y += mfma_16x16x4(A[ks], B[t, ks])
+                        c = QB
+                        if p == 0:
+                            O[c + t] += y
+                        elif S == 0:
+                            O[c + t - Q] += y
+                            O[c + t + Q] += y
+                        else:
+                            O[c + t - Q] += row_shl(y, S)
+                            O[c + t - Q - 1] += row_shr(y, 16 - S)
+                            O[c + t + Q] += row_shr(y, S)
+                            O[c + t + Q + 1] += row_shl(y, 16 - S)
+            for q in range(NB):
+                row = R - 16 * QB + 16 * q + n
+                for l in range(64):
+                    if 0 <= row[l] < Nu:
+                        col = J - cw0 + 4 * kk[l]
+                        win[row[l], col:col + 4] += O[q, l]
+    for j in range(cw0, min(Nv, cw0 + 16 * njt)):
+        plane[:, j] = win[:, j - cw0]
+    return plane
+
+
+def direct(inp, box, h, kq):
+    Nu, Nv = inp.shape
+    m = np.zeros_like(inp)
+    r0, r1, c0, c1 = max(box[0], 0), min(box[1], Nu), max(box[2], 0), min(box[3], Nv)
+    m[r0:r1, c0:c1] = inp[r0:r1, c0:c1]
+    out = np.zeros_like(inp)
+    pad = np.zeros((Nu + 2 * h, Nv + 2 * h))
+    pad[h:h + Nu, h:h + Nv] = m
+    for p in range(-h, h + 1):
+        for q in range(-h, h + 1):
+            out += kq[abs(p), abs(q)] * pad[h + p:h + p + Nu, h + q:h + q + Nv]
+    return out
+
+
+@pytest.mark.parametrize("Nu,Nv,h,box,T,SU", [
+    (89, 89, 30, (30, 59, 31, 58), 2, 2),      # the benchmark plane: 61 taps, a 29 x 27 rectangle
+    (89, 89, 30, (0, 89, 0, 89), 2, 2),        # the whole plane: several chunks each way
+    (40, 37, 6, (3, 38, 0, 21), 1, 1),         # small kernel, rectangle at the left edge, 3 x 2 chunks
+    (50, 47, 16, (20, 21, 46, 47), 2, 2),      # one pixel in the last column, tap rows 16 = 16 + 0
+    (45, 60, 17, (10, 40, 5, 55), 3, 3),       # one chunk each way with T = SU = 3
+    (70, 66, 31, (25, 46, 20, 41), 1, 2),      # the largest half-width, 2 x 1 chunks
+    (30, 30, 8, (12, 12, 3, 20), 2, 2),        # empty rectangle
+])
+def test_register_forward_matches_direct_convolution(Nu, Nv, h, box, T, SU):
+    rng = np.random.default_rng(Nu * 7 + h)
+    inp = rng.normal(size=(Nu, Nv))
+    kq = rng.uniform(0.1, 1.0, size=(h + 1, h + 1))   # any table with K[p][q] = kq[|p|][|q|]
+    got = model(inp, box, h, kq, T, SU)
+    ref = direct(inp, box, h, kq)
+    assert np.abs(got - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
