@@ -21,8 +21,9 @@
 // all tap rows, then adds them into an LDS copy of the plane; the plane goes out
 // with row-contiguous stores, zeros outside the reach included.
 //
-// Work skipped: K-steps (4 box columns) of which no column lies within h of the
-// strip.  The products of skipped steps are exact zeros.  The sum of every output
+// Work skipped: groups of 16 box columns of which no column lies within h of the
+// strip (one uniform branch per group and tap row; inside a group the band's zero
+// taps are multiplied).  The products of skipped groups are exact zeros.  The sum of every output
 // runs over p = 0, 1, ..., h in order, within a tap row over the box's row blocks,
 // and within a product over the box columns in order (deterministic; the rounding
 // differs from a direct sum only in order).
@@ -37,9 +38,10 @@ constexpr int kRegQB = 2;    // output blocks of 16 rows above and below a row c
 constexpr int kRegMaxH = 16 * (kRegQB - 1) + 15;  // largest half-width the blocks reach
 
 // Extended tap row: kx[p][x] = K[p][|x - off|] for |x - off| <= h, else 0, with
-// off = h + 18 and length 2h + 37 (every executed K-step reads |c - j| <= h + 18).
-__host__ __device__ inline int reg_tap_len(int h) { return 2 * h + 37; }
-__host__ __device__ inline int reg_tap_off(int h) { return h + 18; }
+// off = h + 34 and length 2h + 65: a column group in reach reads |c - j| <= h + 30
+// (x in [4, 2h + 64]); a group out of reach reads x in [0, 30], all zero.
+__host__ __device__ inline int reg_tap_len(int h) { return 2 * h + 65; }
+__host__ __device__ inline int reg_tap_off(int h) { return h + 34; }
 
 // Lane i takes lane i + S (LEFT) or i - S of its 16-lane row; 0 where that lane lies
 // outside the row.  1 <= S <= 15.  (Each component is copied to a scalar before its
@@ -59,23 +61,36 @@ __device__ __forceinline__ f32x4r row_shift(const f32x4r& v) {
 
 // One tap row P: the products of the box's T row blocks with the band of tap row P
 // and their shifted sums into the strip's output blocks O (block kRegQB + t holds
-// the rows of box block t).  A K-step ks is executed when ka <= ks <= kb.
-template <int P, int T, int NKS, int NB>
-__device__ __forceinline__ void reg_tap_row(const float* const (&aaddr)[NKS], int E, int ka, int kb,
-                                            const float (&B)[T][NKS], f32x4r (&O)[NB]) {
+// the rows of box block t).  Column group u > 0 (K-steps 4u .. 4u + 3) is executed when
+// bit u of umask (uniform) is set; group 0 always is.
+template <int P, int T, int SU, int NB>
+__device__ __forceinline__ void reg_tap_row(const float* const (&aaddr)[SU], int E, unsigned umask,
+                                            const float (&B)[T][4 * SU], f32x4r (&O)[NB]) {
   constexpr int S = P & 15, Q = P >> 4;
-  float A[NKS];
+  float A[4 * SU];
 #pragma unroll
-  for (int ks = 0; ks < NKS; ++ks) A[ks] = aaddr[ks][P * E];
-  // the T products share each A and are independent chains, issued in turn
+  for (int u = 0; u < SU; ++u)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) A[4 * u + s] = aaddr[u][P * E + 4 * s];
+  // the T products share each A and are independent chains, issued in turn; group 0
+  // always runs and starts the chains from zero (out of reach its A is zero), the
+  // others run when their bit of umask is set and accumulate in place
   f32x4r Y[T];
 #pragma unroll
-  for (int t = 0; t < T; ++t) Y[t] = f32x4r{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < T; ++t)
+    Y[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[0], B[t][0], f32x4r{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
 #pragma unroll
-  for (int ks = 0; ks < NKS; ++ks)
-    if (ks >= ka && ks <= kb) {
+  for (int s = 1; s < 4; ++s)
 #pragma unroll
-      for (int t = 0; t < T; ++t) Y[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks], B[t][ks], Y[t], 0, 0, 0);
+    for (int t = 0; t < T; ++t) Y[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[s], B[t][s], Y[t], 0, 0, 0);
+#pragma unroll
+  for (int u = 1; u < SU; ++u)
+    if (umask & (1u << u)) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+          Y[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[4 * u + s], B[t][4 * u + s], Y[t], 0, 0, 0);
     }
 #pragma unroll
   for (int t = 0; t < T; ++t) {
@@ -99,13 +114,13 @@ __device__ __forceinline__ void reg_tap_row(const float* const (&aaddr)[NKS], in
   }
 }
 
-template <int P, int T, int NKS, int NB>
-__device__ __forceinline__ void reg_tap_rows(int h, const float* const (&aaddr)[NKS], int E, int ka, int kb,
-                                             const float (&B)[T][NKS], f32x4r (&O)[NB]) {
+template <int P, int T, int SU, int NB>
+__device__ __forceinline__ void reg_tap_rows(int h, const float* const (&aaddr)[SU], int E, unsigned umask,
+                                             const float (&B)[T][4 * SU], f32x4r (&O)[NB]) {
   if constexpr (P <= kRegMaxH) {
     if (P > h) return;
-    reg_tap_row<P, T, NKS, NB>(aaddr, E, ka, kb, B, O);
-    reg_tap_rows<P + 1, T, NKS, NB>(h, aaddr, E, ka, kb, B, O);
+    reg_tap_row<P, T, SU, NB>(aaddr, E, umask, B, O);
+    reg_tap_rows<P + 1, T, SU, NB>(h, aaddr, E, umask, B, O);
   }
 }
 
@@ -159,20 +174,27 @@ __global__ void __launch_bounds__(64 * kRegNW) k_conv_fwd_reg(Geo<float> g, int 
       }
     }
   };
-  if (wave < njt) load_b(0, 0);  // in flight while the taps are built
+  const int jt0 = wave;  // this wavefront's first strip
+  if (jt0 < njt) load_b(0, 0);  // in flight while the taps are built
 
   unique_taps(g, k, zca[bk], kq, tid, NT);
   __syncthreads();
-  for (int idx = tid; idx < (h + 1) * E; idx += NT) {
-    const int p = idx / E, x = idx - p * E;
-    const int q = x < off ? off - x : x - off;
-    kx[idx] = q <= h ? kq[p * (h + 1) + q] : 0.f;
+  for (int p = wave; p <= h; p += kRegNW)
+    for (int x = lane; x < E; x += 64) {
+      const int q = x < off ? off - x : x - off;
+      kx[p * E + x] = q <= h ? kq[p * (h + 1) + q] : 0.f;
+    }
+  // with one chunk each strip writes its rows of the plane copy once (rows it does
+  // not cover are written as zeros at the end); with several chunks the strips add
+  // into a cleared copy
+  const bool single = nrc == 1 && ncc == 1;
+  __syncthreads();
+  if (!single) {
+    for (int idx = 4 * tid; idx < Nu * wpitch; idx += 4 * NT) *reinterpret_cast<f32x4r*>(win + idx) = f32x4r{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
   }
-  __syncthreads();
-  for (int idx = tid; idx < Nu * wpitch; idx += NT) win[idx] = 0.f;
-  __syncthreads();
 
-  for (int jt = wave; jt < njt; jt += kRegNW) {
+  for (int jt = jt0; jt < njt; jt += kRegNW) {
     const int J = cw0 + 16 * jt;  // the strip's first output column
     for (int rc = 0; rc < nrc; ++rc) {
       const int R = r0 + 16 * T * rc;
@@ -180,43 +202,46 @@ __global__ void __launch_bounds__(64 * kRegNW) k_conv_fwd_reg(Geo<float> g, int 
 #pragma unroll
       for (int q = 0; q < NB; ++q) O[q] = f32x4r{0.f, 0.f, 0.f, 0.f};
       for (int cc = 0; cc < ncc; ++cc) {
-        if (jt != wave || rc != 0 || cc != 0) load_b(rc, cc);
+        if (jt != jt0 || rc != 0 || cc != 0) load_b(rc, cc);
         const int C = c0 + 16 * SU * cc;
-        const int nks = min(NKS, (c1 - C + 3) / 4);
-        // K-steps with a column within h of the strip [J, J + 16)
-        const int lo = J - h - C - 3, hi = J + 15 + h - C;
-        const int ka = lo <= 0 ? 0 : (lo + 3) / 4;
-        const int kb = min(nks - 1, hi >= 0 ? hi / 4 : -1);
-        if (ka > kb) continue;
-        // A of K-step ks in tap row p: kx[p][C + 4 ks + kk - J - m + off]; steps outside
-        // [ka, kb] read step ka's or kb's entries (in range, not used)
-        const float* aaddr[NKS];
+        const int nsu = min(SU, (c1 - C + 15) / 16);
+        // column groups with a column within h of the strip [J, J + 16)
+        const int lo = J - h - C - 15, hi = J + 15 + h - C;
+        const int ua = lo <= 0 ? 0 : (lo + 15) / 16;
+        const int ub = min(nsu - 1, hi >= 0 ? hi / 16 : -1);
+        if (ua > ub) continue;
+        // A of K-step 4 u + s in tap row p: kx[p][C + 16 u + 4 s + kk - J - m + off];
+        // groups outside [ua, ub] read the zeros at the start of the row (group 0
+        // runs with them; the others are skipped)
+        const float* aaddr[SU];
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) {
-          const int kc = min(max(ks, ka), kb);
-          aaddr[ks] = kx + (C + 4 * kc + kk - J - n + off);
-        }
-        reg_tap_rows<0, T, NKS, NB>(h, aaddr, E, ka, kb, B, O);
+        for (int u = 0; u < SU; ++u)
+          aaddr[u] = kx + ((u >= ua && u <= ub) ? C + 16 * u + kk - J - n + off : 15 + kk - n);
+        const unsigned umask = __builtin_amdgcn_readfirstlane((2u << ub) - (1u << ua));  // bits ua .. ub
+        reg_tap_rows<0, T, SU, NB>(h, aaddr, E, umask, B, O);
       }
-      // add the strip's rows R - 16 kRegQB + 16 q + n (those in the plane), columns
-      // J + 4 kk .. J + 4 kk + 3, into the LDS plane; only this wavefront writes them
+      // the strip's rows R - 16 kRegQB + 16 q + n (those in the plane), columns
+      // J + 4 kk .. J + 4 kk + 3, into the LDS plane (written with one chunk, added
+      // with several); only this wavefront writes them
       float* wcol = win + (J - cw0) + 4 * kk;
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const int row = R - 16 * kRegQB + 16 * q + n;
         if (row >= 0 && row < Nu) {
           f32x4r* w = reinterpret_cast<f32x4r*>(wcol + row * wpitch);
-          *w += O[q];
+          if (single) *w = O[q];
+          else *w += O[q];
         }
       }
     }
   }
   __syncthreads();
-  // the plane, row by row: the LDS copy over the reach's columns, zero elsewhere
+  // the plane, row by row: the LDS copy over the strips' rows and columns, zero elsewhere
+  const int wr0 = single ? r0 - 16 * kRegQB : 0, wr1 = single ? r0 + 16 * (T + kRegQB) : Nu;
   RectWalk w(tid, NT, Nv);
   for (; w.r < Nu; w.next(Nv)) {
     const int j = w.c - cw0;
-    dst[(size_t)w.r * Nv + w.c] = (j >= 0 && j < 16 * njt) ? win[w.r * wpitch + j] : 0.f;
+    dst[(size_t)w.r * Nv + w.c] = (j >= 0 && j < 16 * njt && w.r >= wr0 && w.r < wr1) ? win[w.r * wpitch + j] : 0.f;
   }
 }
 

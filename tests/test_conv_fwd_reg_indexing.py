@@ -1,6 +1,7 @@
 """CPU model of the register-resident forward convolution's indexing
-(paper_2512_18863_amd/csrc/conv_fwd_reg.hip): box chunks, K-step ranges, the
-clamped tap-row addresses, the matrix instructions' lane layout and the DPP row
+(paper_2512_18863_amd/csrc/conv_fwd_reg.hip): box chunks, the column groups in
+reach of each output strip, the tap-row addresses (in range for every group, run
+or not), the matrix instructions' lane layout and the DPP row
 shifts that move each product p rows up and down, emulated lane by lane in FP64
 and compared with the direct convolution of the masked input
 (§2.2.6, Eq. 8: out[i][j] = sum_{p,q} K[p][q] in[i+p][j+q]).  The DPP shifts are
@@ -48,7 +49,7 @@ def row_shr(v, s):
 
 def model(inp, box, h, kq, T, SU):
     Nu, Nv = inp.shape
-    E, off = 2 * h + 37, h + 18
+    E, off = 2 * h + 65, h + 34
     kx = np.zeros((h + 1, E))
     for p in range(h + 1):
         for x in range(E):
@@ -81,23 +82,25 @@ def model(inp, box, h, kq, T, SU):
                         r, c = R + 16 * t + n, C + 4 * ks + kk
                         ok = (r < r1) & (c < c1)
                         B[t, ks, ok] = inp[r[ok], c[ok]]
-                nks = min(NKS, (c1 - C + 3) // 4)
-                lo, hi = J - h - C - 3, J + 15 + h - C
-                ka = 0 if lo <= 0 else (lo + 3) // 4
-                kb = min(nks - 1, hi // 4 if hi >= 0 else -1)
-                if ka > kb:
+                nsu = min(SU, (c1 - C + 15) // 16)
+                lo, hi = J - h - C - 15, J + 15 + h - C
+                ua = 0 if lo <= 0 else (lo + 15) // 16
+                ub = min(nsu - 1, hi // 16 if hi >= 0 else -1)
+                if ua > ub:
                     continue
                 for p in range(h + 1):
                     S, Q = p & 15, p >> 4
                     A = np.zeros((NKS, 64))
-                    for ks in range(NKS):
-                        kc = min(max(ks, ka), kb)
-                        x = C + 4 * kc + kk - J - n + off
-                        assert x.min() >= 0 and x.max() < E, (x.min(), x.max(), E)
-                        A[ks] = kx[p, x]
+                    for u in range(SU):
+                        base = C + 16 * u + kk - J - n + off if ua <= u <= ub else 15 + kk - n
+                        for s in range(4):
+                            x = base + 4 * s
+                            assert x.min() >= 0 and x.max() < E, (x.min(), x.max(), E)
+                            A[4 * u + s] = kx[p, x]
                     for t in range(T):
                         y = np.zeros((64, 4))
-                        for ks in range(ka, kb + 1):
+                        # group 0 always (zero A when out of reach), the others when in reach
+                        for ks in list(range(4)) + list(range(max(4, 4 * ua), 4 * ub + 4)):
                             y += mfma_16x16x4(A[ks], B[t, ks])
                         c = QB
                         if p == 0:
