@@ -669,31 +669,39 @@ __device__ __forceinline__ double uniform(double v) {
 }
 
 // dose(x, y, z) += sum_b MU_b trilinear(Dfan_b at the voxel's beam-frame position).
-// A block covers 64 consecutive z of four voxel columns (one wavefront per
-// column); the column terms of each control point are computed once per block
-// (into LDS) instead of once per voxel, and each lane does only the z-dependent
-// part: the lateral coordinate j, the eight loads and the interpolation.  The
-// arithmetic of every term is that of a direct per-voxel evaluation (same
-// operations in the same order), and the terms are summed in control-point order
-// with a compensated sum.
+// A block covers 64 consecutive z of a 4 x 4 patch of voxel columns (one
+// wavefront per column).  The beam-frame rows that a column reads are shared with
+// its neighbours in x and y, so a square patch reads about (4 + 1)^2 distinct rows
+// per control point for 16 columns, where a line of four columns reads about
+// 2 (4 + 1) for 4 (blocks drift apart over the control points, so rows shared
+// between blocks come from beyond L2 again).  The column terms of each control
+// point are computed once per block (into LDS) instead of once per voxel, and each
+// lane does only the z-dependent part: the lateral coordinate j, the eight loads
+// and the interpolation (the four (k, i) corners weighted first, in columns j and
+// j + 1, then the step along j).  The terms are summed in control-point order with
+// a compensated sum.
+constexpr int GATHER_P = 4;                  // patch edge (voxel columns)
+constexpr int GATHER_NW = GATHER_P * GATHER_P;  // wavefronts per block
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_gather(Geo<T> g, int nb, int first, int last, int zc, int xc,
-                                                const T* __restrict__ frame, const T* __restrict__ mu,
-                                                const T* __restrict__ Dfan, T* __restrict__ dose,
-                                                T* __restrict__ comp) {
-  __shared__ GatherCol<T> cols[4][GATHER_CHUNK];
-  const int nblk = zc * xc * g.ny;
+__global__ void __launch_bounds__(64 * GATHER_NW) k_gather(Geo<T> g, int nb, int first, int last, int zc, int xc,
+                                                           int yc, const T* __restrict__ frame,
+                                                           const T* __restrict__ mu, const T* __restrict__ Dfan,
+                                                           T* __restrict__ dose, T* __restrict__ comp) {
+  constexpr int NT = 64 * GATHER_NW;
+  __shared__ GatherCol<T> cols[GATHER_NW][GATHER_CHUNK];
+  const int nblk = zc * xc * yc;
   const int per_xcd = (nblk + 7) / 8;
   const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (w >= nblk) return;  // uniform over the block
-  const int zq = w % zc, xq = (w / zc) % xc;
+  const int zq = w % zc, xq = (w / zc) % xc, yq = w / (zc * xc);
   const int wave = threadIdx.x >> 6;
   const int z = zq * 64 + (threadIdx.x & 63);
-  const int x = xq * 4 + wave;
-  const int y = w / (zc * xc);
-  const bool active = z < g.nz && x < g.nx;
+  const int x = xq * GATHER_P + wave % GATHER_P;
+  const int y = yq * GATHER_P + wave / GATHER_P;
+  const bool active = z < g.nz && x < g.nx && y < g.ny;
   const size_t vox = ((size_t)z * g.ny + y) * g.nx + x;
-  const T tz = g.rel_oz + T(z) * g.sz, ty = g.rel_oy + T(y) * g.sy;
+  const T tz = g.rel_oz + T(z) * g.sz;
   T s = T(0), c = T(0);
   if (active && !first) {
     s = dose[vox];
@@ -704,9 +712,10 @@ __global__ void __launch_bounds__(256) k_gather(Geo<T> g, int nb, int first, int
   for (int b0 = 0; b0 < nb; b0 += GATHER_CHUNK) {
     const int nbc = min(GATHER_CHUNK, nb - b0);
     __syncthreads();  // the previous chunk's column terms are no longer read
-    for (int e = threadIdx.x; e < 4 * nbc; e += 256) {
+    for (int e = threadIdx.x; e < GATHER_NW * nbc; e += NT) {
       const int cw = e / nbc, bb = e - cw * nbc, b = b0 + bb;
-      const T tx = g.rel_ox + T(xq * 4 + cw) * g.sx;
+      const T tx = g.rel_ox + T(xq * GATHER_P + cw % GATHER_P) * g.sx;
+      const T ty = g.rel_oy + T(yq * GATHER_P + cw / GATHER_P) * g.sy;
       const T sn = frame[2 * b], cs = frame[2 * b + 1];
       // voxel_to_fan without the z part
       const T ev = -sn * tx + cs * ty;
@@ -762,13 +771,16 @@ __global__ void __launch_bounds__(256) k_gather(Geo<T> g, int nb, int first, int
       };
       auto add = [&](int bb, const Term& tm) {
         const GatherCol<T>& col = cols[wave][bb];
-        T acc = T(0);
+        // the (k, i) corners weighted first (columns j and j + 1), then the j step
+        T lo = T(0), hi = T(0);
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
-          const T a = tm.jin0 * tm.lo[cc];
-          const T bv = tm.jin1 * tm.hi[cc];
-          acc += uniform(col.w[cc]) * (a + tm.wj * (bv - a));
+          const T w = uniform(col.w[cc]);
+          lo += w * tm.lo[cc];
+          hi += w * tm.hi[cc];
         }
+        const T a = tm.jin0 * lo, bv = tm.jin1 * hi;
+        const T acc = a + tm.wj * (bv - a);
         // outside the beam-frame grid the term is +0, which leaves s and c unchanged
         const T val = tm.in_j * (mu[b0 + bb] * acc);
         const T t = s + val;
@@ -802,13 +814,13 @@ __global__ void __launch_bounds__(256) k_gather(Geo<T> g, int nb, int first, int
 template <typename T>
 hipError_t launch_gather(const Geo<T>& g, int nb, int first, int last, const T* frame, const T* mu, const T* Dfan,
                          T* dose, T* comp, hipStream_t s) {
-  const int zc = (g.nz + 63) / 64, xc = (g.nx + 3) / 4;
-  const long nblk = (long)zc * xc * g.ny;
+  const int zc = (g.nz + 63) / 64, xc = (g.nx + GATHER_P - 1) / GATHER_P, yc = (g.ny + GATHER_P - 1) / GATHER_P;
+  const long nblk = (long)zc * xc * yc;
   if (nblk > 0x7ffffff0L) return hipErrorInvalidConfiguration;
   if ((long)g.Nk * g.Nu * g.Nv > 0x7fffffffL) return hipErrorInvalidConfiguration;  // 32-bit corner offsets
   const int grid = (int)((nblk + 7) / 8 * 8);
-  hipLaunchKernelGGL(k_gather<T>, dim3(grid), dim3(256), 0, s, g, nb, first, last, zc, xc, frame, mu, Dfan, dose,
-                     comp);
+  hipLaunchKernelGGL(k_gather<T>, dim3(grid), dim3(64 * GATHER_NW), 0, s, g, nb, first, last, zc, xc, yc, frame, mu,
+                     Dfan, dose, comp);
   return hipGetLastError();
 }
 
