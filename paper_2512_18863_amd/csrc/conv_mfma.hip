@@ -793,7 +793,8 @@ static hipError_t launch_f32_adj(const Geo<float>& g, const RegionShape& rs, con
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                 hipStream_t s, const int* box, int support) {
   const int4* bx = reinterpret_cast<const int4*>(box);
-  if (bx && support == CONV_IN_BOX && conv_fwd_reg_supported(g)) return launch_conv_fwd_reg(g, nb, z, in, out, s, box);
+  if (bx && support == CONV_IN_BOX && conv_fwd_reg_supported(g, false))
+    return launch_conv_fwd_reg(g, nb, z, in, out, s, box, false);
   const bool adj = bx && support == CONV_OUT_BOX;
   RegionShape rs;
   F32Shape fs;

@@ -128,10 +128,11 @@ hipError_t launch_conv_small(const Geo<float>& g, int nb, const float* z, const 
                              hipStream_t s);
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                 hipStream_t s, const int* box = nullptr, int support = 0);
-// forward convolution with the aperture rectangle in registers (FP32, h <= 31)
-bool conv_fwd_reg_supported(const Geo<float>& g);
+// forward convolution with the aperture rectangle in registers (FP32 or BF16
+// operands, h <= 31)
+bool conv_fwd_reg_supported(const Geo<float>& g, bool bf16);
 hipError_t launch_conv_fwd_reg(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
-                               hipStream_t s, const int* box);
+                               hipStream_t s, const int* box, bool bf16);
 hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                  hipStream_t s, const int* box = nullptr, int support = 0);
 template <typename T>
