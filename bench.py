@@ -34,14 +34,16 @@ PEAK_HBM_GBS = 8000.0
 # the kernel is built from)
 _CONV = ["conv_mfma.hip", "conv_common.hpp", "taps.hpp", "device_math.hpp", "pdrt_internal.hpp"]
 _CONV16 = ["conv_bf16.hip", "conv_common.hpp", "taps.hpp", "device_math.hpp", "pdrt_internal.hpp"]
+_FWDREG = ["conv_fwd_reg.hip", "conv_mfma.hip", "conv_bf16.hip", "conv_common.hpp", "taps.hpp", "device_math.hpp",
+           "pdrt_internal.hpp"]
 _FWD = ["dose_fwd.hip", "taps.hpp", "device_math.hpp", "pdrt_internal.hpp"]
 _BWD = ["dose_bwd.hip", "device_math.hpp", "pdrt_internal.hpp"]
 KERNELS = {
-    "conv_mfma_f32": (("k_conv_mfma_f32<",), _CONV),
+    # forwards: the register-resident kernel <BF16?, T, SU>
+    "conv_mfma_f32": (("k_conv_fwd_reg<false,",), _FWDREG),
     "conv_mfma_f32_adj": (("k_conv_mfma_f32_adj<",), _CONV),
-    # template arguments <NK, BR, BC, NWB, NWP, SUP>: forward 6 x 3 tiles in two
-    # wavefronts, adjoint 2 x 2 tiles in four
-    "conv_mfma_bf16": (("k_conv_bf16<*,6,3,2,1,*",), _CONV16),
+    "conv_mfma_bf16": (("k_conv_fwd_reg<true,",), _FWDREG),
+    # template arguments <NK, BR, BC, NWB, NWP, SUP>: adjoint 2 x 2 tiles in four wavefronts
     "conv_mfma_bf16_adj": (("k_conv_bf16<*,2,2,1,4,*",), _CONV16),
     "march": (("k_march_serial<float,0,",), _FWD),
     "march_adj": (("k_march_serial<float,1,",), _FWD),
