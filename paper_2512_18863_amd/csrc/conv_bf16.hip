@@ -378,8 +378,9 @@ hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, co
                                  hipStream_t s, const int* box, int support) {
   const int4* bx = reinterpret_cast<const int4*>(box);
   if (support == CONV_OUT_BOX && bx) return launch_bf16_sup<CONV_OUT_BOX>(g, nb, bx, z, in, out, s);
-  // the forward with the rectangle in registers where its tap rows fit
-  if (support == CONV_IN_BOX && bx && conv_fwd_reg_supported(g, true))
+  // the forward with the rectangle in registers where its tap rows fit (not with
+  // the fluence corrections' widened rectangles, as for FP32)
+  if (support == CONV_IN_BOX && bx && !g.fcorr && conv_fwd_reg_supported(g, true))
     return launch_conv_fwd_reg(g, nb, z, in, out, s, box, true);
   // forward, or no box: the input support is the box (the whole plane without one)
   return launch_bf16_sup<CONV_IN_BOX>(g, nb, support == CONV_DENSE ? nullptr : bx, z, in, out, s);

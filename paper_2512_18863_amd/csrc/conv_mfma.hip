@@ -628,34 +628,71 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32_adj(Geo<float> g, Reg
   float* part = kq + (h + 1) * (h + 1);  // (NW - 1) x 256 partial sums, 16-byte aligned (see f32_adj_lds)
   part = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(part) + 15) & ~(uintptr_t)15);
   const int nreg = rs.regions_i * rs.regions_j;
-  const int region = blockIdx.x % nreg;
-  const int I0 = (region / rs.regions_j) * rs.TI * MT;
-  const int J0 = (region % rs.regions_j) * rs.TJ * MT;
-  const int Ie = min(g.Nu, I0 + MT * rs.TI), Je = min(g.Nv, J0 + MT * rs.TJ);  // region's outputs in the plane
   const size_t plane = (size_t)g.Nu * g.Nv;
   const int tid = threadIdx.x;
-  const DataRect dr = data_rect(g, I0, J0, MT * rs.TI, MT * rs.TJ);
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int m = lane & 15, kk = lane >> 4;
   const float* bbase = kx + 4 * kk + 15 - m;
   const int off = h + 15;
 
+  // Item it is (control point, plane) it / nreg in region it % nreg.  The grid is
+  // not a multiple of the region count, so a workgroup's items move over the
+  // regions (a plane wider than one region, e.g. the square grid of a rotated
+  // collimator, has its boxes in few regions: pinning workgroups to regions would
+  // idle the others).  The image is cleared again when the region changes.  An item
+  // whose box misses its region's outputs has nothing to compute or write and is
+  // skipped without staging.
+  struct Reg {
+    int region, I0, J0, Ie, Je;  // first output row / column; outputs in the plane end at Ie, Je
+    DataRect dr;
+  };
+  auto reg_of = [&](int item) {
+    Reg r;
+    r.region = item % nreg;
+    r.I0 = (r.region / rs.regions_j) * rs.TI * MT;
+    r.J0 = (r.region % rs.regions_j) * rs.TJ * MT;
+    r.Ie = min(g.Nu, r.I0 + MT * rs.TI);
+    r.Je = min(g.Nv, r.J0 + MT * rs.TJ);
+    r.dr = data_rect(g, r.I0, r.J0, MT * rs.TI, MT * rs.TJ);
+    return r;
+  };
+  auto live = [&](int item, const Reg& r) {
+    const int4 b4 = box[(item / nreg) / g.Nk];
+    return max(b4.x, r.I0) < min(b4.y, r.Ie) && max(b4.z, r.J0) < min(b4.w, r.Je);
+  };
   zero_lds(tile, rows * pitch, tid, NT);
   float buf[PF];
   int it = blockIdx.x;
-  if (it < n_items) fetch_rect<PF>(in + (size_t)(it / nreg) * plane, g.Nv, dr, tid, NT, buf);
+  int held = -1;  // the region whose data (and zero halo) the image holds
+  if (it < n_items) {
+    const Reg r = reg_of(it);
+    if (live(it, r)) fetch_rect<PF>(in + (size_t)(it / nreg) * plane, g.Nv, r.dr, tid, NT, buf);
+  }
   __syncthreads();
   for (; it < n_items; it += gridDim.x) {
     const int bk = it / nreg;
     const int k = bk % g.Nk;
     const float* src = in + (size_t)bk * plane;
-    put_rect<PF>(src, g.Nv, dr, pitch, tid, NT, buf, tile);
+    const Reg r = reg_of(it);
+    const int I0 = r.I0, J0 = r.J0, Ie = r.Ie, Je = r.Je;
+    const int nx = it + gridDim.x;
+    const Reg rn = reg_of(nx);
+    const bool next_live = nx < n_items && live(nx, rn);
+    if (!live(it, r)) {  // uniform over the workgroup; the LDS is not touched
+      if (next_live) fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, rn.dr, tid, NT, buf);
+      continue;
+    }
+    if (held >= 0 && held != r.region) {
+      zero_lds(tile, rows * pitch, tid, NT);
+      __syncthreads();
+    }
+    held = r.region;
+    put_rect<PF>(src, g.Nv, r.dr, pitch, tid, NT, buf, tile);
     unique_taps(g, k, zca[bk], kq, tid, NT);
     __syncthreads();
     build_kx(kq, kx, h, E, off, wave, lane, NW);
     __syncthreads();
-    const int nx = it + gridDim.x;
-    if (nx < n_items) fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, dr, tid, NT, buf);
+    if (next_live) fetch_rect<PF>(in + (size_t)(nx / nreg) * plane, g.Nv, rn.dr, tid, NT, buf);
     float* dst = out + (size_t)bk * plane;
 
     // the covered rectangle [Iw, Iw + 16 nI) x [Jw, Jw + 16 nJ)
@@ -774,9 +811,17 @@ static hipError_t launch_f32_adj_cfg(const Geo<float>& g, const RegionShape& rs,
   const int nreg = rs.regions_i * rs.regions_j;
   const long n_items = (long)nreg * g.Nk * nb;
   if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;
-  const int grid = persistent_grid(kern, 64 * NW, lds, nreg, n_items);
-  hipLaunchKernelGGL((k_conv_mfma_f32_adj<NW, TPW>), dim3(grid), dim3(64 * NW), lds, s, g, rs, fs, (int)n_items,
-                     box, z, in, out);
+  // as many workgroups as fit, the count prime to the region count (a workgroup's
+  // items then visit every region)
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * NW, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  long grid = (long)device_cus() * per_cu;
+  if (grid < 1) grid = 1;
+  auto gcd = [](long a, long b) { while (b) { const long t = a % b; a = b; b = t; } return a; };
+  while (grid > 1 && gcd(grid, nreg) != 1) --grid;
+  if (grid > n_items) grid = n_items;
+  hipLaunchKernelGGL((k_conv_mfma_f32_adj<NW, TPW>), dim3((unsigned)grid), dim3(64 * NW), lds, s, g, rs, fs,
+                     (int)n_items, box, z, in, out);
   return hipGetLastError();
 }
 
@@ -793,7 +838,10 @@ static hipError_t launch_f32_adj(const Geo<float>& g, const RegionShape& rs, con
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                 hipStream_t s, const int* box, int support) {
   const int4* bx = reinterpret_cast<const int4*>(box);
-  if (bx && support == CONV_IN_BOX && conv_fwd_reg_supported(g, false))
+  // the forward with the rectangle in registers, unless the fluence corrections
+  // widen the rectangles by their blur radii (then several chunks per plane would
+  // repeat the tap loop; the tiled kernel below is faster there)
+  if (bx && support == CONV_IN_BOX && !g.fcorr && conv_fwd_reg_supported(g, false))
     return launch_conv_fwd_reg(g, nb, z, in, out, s, box, false);
   const bool adj = bx && support == CONV_OUT_BOX;
   RegionShape rs;
