@@ -41,7 +41,8 @@ _BWD = ["dose_bwd.hip", "device_math.hpp", "pdrt_internal.hpp"]
 KERNELS = {
     # forwards: the register-resident kernel <BF16?, T, SU>
     "conv_mfma_f32": (("k_conv_fwd_reg<false,",), _FWDREG),
-    "conv_mfma_f32_adj": (("k_conv_mfma_f32_adj<",), _CONV),
+    # adjoint: the window kernel <NW, TPW> (the region kernel serves the fluence corrections)
+    "conv_mfma_f32_adj": (("k_conv_f32_adj_win<", "k_conv_mfma_f32_adj<"), _CONV),
     "conv_mfma_bf16": (("k_conv_fwd_reg<true,",), _FWDREG),
     # template arguments <NK, BR, BC, NWB, NWP, SUP>: adjoint 2 x 2 tiles in four wavefronts
     "conv_mfma_bf16_adj": (("k_conv_bf16<*,2,2,1,4,*",), _CONV16),

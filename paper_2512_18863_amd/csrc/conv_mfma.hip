@@ -128,43 +128,72 @@ constexpr int PF = 12;  // prefetched elements per thread
 
 // The matrix loop over tap rows p in [pa, pb] and super-steps u in [ua, ub] for
 // NA tiles that share the Toeplitz operand.  Two operand sets are loaded
-// alternately one step ahead of their use: the loop body covers two steps and
-// its loads are unconditional (the load past the last step reads the last step's
-// addresses again and is not used), so the body is straight-line code and each
-// matrix step waits only for its own operands, never for the loads in flight
-// for the next step.
+// alternately one step ahead of their use: the loop body covers two steps and the
+// last one or two steps are peeled, so every load is of a step that is computed
+// and each matrix step waits only for its own operands, never for the loads in
+// flight for the next step.  The LDS addresses advance by a running increment (16
+// along a row of super-steps, a jump to the next tap row at its end), so a step
+// costs a few scalar instructions besides its loads, adds and matrix work.
 // B[k][n] of instruction s in super-step u = K[p][16 u + 4 k + s - h - n]
 //                                           = kx[p][16 u + 4 k + s + 15 - n].
 // MODE 0 adds the two folded rows i + p and i - p; MODE 1 uses row i + p only and
 // MODE 2 row i - p only (tap rows whose other row lies outside the input's
 // support, where it would add exact zeros): half the operand loads, no adds.
+struct StepWalk {
+  int lu, last;          // super-step of the next load within its row, and the row's last one
+  int da, dm, db;        // address jumps at the end of a row (rows i + p, i - p, taps)
+  __device__ __forceinline__ StepWalk(int nu, int pitch, int E) {
+    lu = 0;
+    last = nu - 1;
+    const int span = 16 * (nu - 1);
+    da = pitch - span;
+    dm = -pitch - span;
+    db = E - span;
+  }
+  // the increments of the addresses after a load, and the walk's advance
+  __device__ __forceinline__ void next(int& ia, int& im, int& ib) {
+    const bool wrap = lu == last;
+    ia = wrap ? da : 16;
+    im = wrap ? dm : 16;
+    ib = wrap ? db : 16;
+    lu = wrap ? 0 : lu + 1;
+  }
+};
+
 template <int NA, int MODE = 0>
 __device__ __forceinline__ void f32_steps(const float* const* abase, const float* bbase, int pitch, int E, int pa,
                                           int pb, int ua, int ub, f32x4* acc) {
   const int nu = ub - ua + 1;
   const int total = (pb >= pa && nu > 0) ? (pb - pa + 1) * nu : 0;
   if (total <= 0) return;
-  const float* ab[NA];
+  const float* ap[NA];
+  const float* am[NA];
 #pragma unroll
-  for (int q = 0; q < NA; ++q) ab[q] = abase[q];
+  for (int q = 0; q < NA; ++q) {
+    ap[q] = abase[q] + pa * pitch + 16 * ua;
+    am[q] = abase[q] - pa * pitch + 16 * ua;
+  }
+  const float* bp = bbase + pa * E + 16 * ua;
+  StepWalk w(nu, pitch, E);
   f32x4 ac_[NA];
 #pragma unroll
   for (int q = 0; q < NA; ++q) ac_[q] = acc[q];
-  int lp = pa, lu = ua;  // next step to load: tap row lp, super-step lu
   auto load = [&](f32x4v (&a0)[NA], f32x4v (&a1)[NA], float (&bb)[4]) {
-    const int p = min(lp, pb);  // past the last step: reload the last tap row
-    const int op = p * pitch + 16 * lu, om = 16 * lu - p * pitch;
-    const float* br = bbase + p * E + 16 * lu;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bb[e] = br[e];
+    for (int e = 0; e < 4; ++e) bb[e] = bp[e];
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-      if (MODE != 2) a0[q] = *reinterpret_cast<const f32x4v*>(ab[q] + op);
-      if (MODE != 1) a1[q] = *reinterpret_cast<const f32x4v*>(ab[q] + om);
+      if (MODE != 2) a0[q] = *reinterpret_cast<const f32x4v*>(ap[q]);
+      if (MODE != 1) a1[q] = *reinterpret_cast<const f32x4v*>(am[q]);
     }
-    const bool wrap = lu >= ub;
-    lu = wrap ? ua : lu + 1;
-    lp += wrap ? 1 : 0;
+    int ia, im, ib;
+    w.next(ia, im, ib);
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      ap[q] += ia;
+      am[q] += im;
+    }
+    bp += ib;
   };
   auto compute = [&](const f32x4v (&a0)[NA], const f32x4v (&a1)[NA], const float (&bb)[4]) {
     f32x4v ac[NA];
@@ -177,17 +206,24 @@ __device__ __forceinline__ void f32_steps(const float* const* abase, const float
   };
   f32x4v x0[NA], x1[NA], y0[NA], y1[NA];
   float bx[4], by[4];
-  load(x0, x1, bx);
+  load(x0, x1, bx);  // step 0
   int st = 0;
-  for (; st + 1 < total; st += 2) {
+  for (; st + 2 < total; st += 2) {
     load(y0, y1, by);  // step st + 1
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the matrix work they overlap
     compute(x0, x1, bx);
-    load(x0, x1, bx);  // step st + 2 (a repeat of the last step when st + 2 == total)
+    load(x0, x1, bx);  // step st + 2
     __builtin_amdgcn_sched_barrier(0);
     compute(y0, y1, by);
   }
-  if (st < total) compute(x0, x1, bx);
+  if (st + 1 < total) {  // steps st and st + 1 remain
+    load(y0, y1, by);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(x0, x1, bx);
+    compute(y0, y1, by);
+  } else {
+    compute(x0, x1, bx);
+  }
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = ac_[q];
 }
@@ -205,22 +241,25 @@ __device__ __forceinline__ void f32_steps_hpair(const float* abase, const float*
   const int total = (pb >= pa && nu > 0) ? (pb - pa + 1) * nu : 0;
   if (total <= 0) return;
   f32x4 c0 = acc0, c1 = acc1;
-  int lp = pa, lu = ua;
+  const float* ap = abase + pa * pitch + 16 * ua;
+  const float* am = abase - pa * pitch + 16 * ua;
+  const float* bp0 = bbase0 + pa * E + 16 * ua;
+  const float* bp1 = bbase1 + pa * E + 16 * ua;
+  StepWalk w(nu, pitch, E);
   auto load = [&](f32x4v& a0, f32x4v& a1, float (&b0)[4], float (&b1)[4]) {
-    const int p = min(lp, pb);  // past the last step: reload the last tap row
-    const int op = p * pitch + 16 * lu, om = 16 * lu - p * pitch;
-    const float* r0 = bbase0 + p * E + 16 * lu;
-    const float* r1 = bbase1 + p * E + 16 * lu;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      b0[e] = r0[e];
-      b1[e] = r1[e];
+      b0[e] = bp0[e];
+      b1[e] = bp1[e];
     }
-    if (MODE != 2) a0 = *reinterpret_cast<const f32x4v*>(abase + op);
-    if (MODE != 1) a1 = *reinterpret_cast<const f32x4v*>(abase + om);
-    const bool wrap = lu >= ub;
-    lu = wrap ? ua : lu + 1;
-    lp += wrap ? 1 : 0;
+    if (MODE != 2) a0 = *reinterpret_cast<const f32x4v*>(ap);
+    if (MODE != 1) a1 = *reinterpret_cast<const f32x4v*>(am);
+    int ia, im, ib;
+    w.next(ia, im, ib);
+    ap += ia;
+    am += im;
+    bp0 += ib;
+    bp1 += ib;
   };
   auto compute = [&](const f32x4v& a0, const f32x4v& a1, const float (&b0)[4], const float (&b1)[4]) {
     const f32x4v a = MODE == 0 ? a0 + a1 : (MODE == 1 ? a0 : a1);
@@ -234,15 +273,22 @@ __device__ __forceinline__ void f32_steps_hpair(const float* abase, const float*
   float bx0[4], bx1[4], by0[4], by1[4];
   load(x0, x1, bx0, bx1);
   int st = 0;
-  for (; st + 1 < total; st += 2) {
+  for (; st + 2 < total; st += 2) {
     load(y0, y1, by0, by1);  // step st + 1
     __builtin_amdgcn_sched_barrier(0);
     compute(x0, x1, bx0, bx1);
-    load(x0, x1, bx0, bx1);  // step st + 2 (a repeat of the last step when st + 2 == total)
+    load(x0, x1, bx0, bx1);  // step st + 2
     __builtin_amdgcn_sched_barrier(0);
     compute(y0, y1, by0, by1);
   }
-  if (st < total) compute(x0, x1, bx0, bx1);
+  if (st + 1 < total) {
+    load(y0, y1, by0, by1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(x0, x1, bx0, bx1);
+    compute(y0, y1, by0, by1);
+  } else {
+    compute(x0, x1, bx0, bx1);
+  }
   acc0 = c0;
   acc1 = c1;
 }
@@ -748,6 +794,279 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32_adj(Geo<float> g, Reg
   }
 }
 
+
+// One wavefront's partial sums into the LDS, as a call of its own: with the store
+// inlined into the adjoint kernel below, the compiler's wait insertion makes the
+// first matrix step of every loop iteration wait for all LDS loads in flight (the
+// next step's included) instead of its own operands only.
+typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
+__device__ __attribute__((noinline)) void park_partial(lds_f32x4* p, f32x4 v) { *p = v; }
+
+// The adjoint (CONV_OUT_BOX) with an image of its output tiles' read window only.
+// Per item the box (clipped to the plane) is covered by nI x nJ output tiles at its
+// corner; they are taken in pieces of at most WI x WJ tiles, and each piece's
+// image holds rows [Ip - h, Ip + 16 nIp + h) and columns [Jp - h, Jp - h + 16 (nJp -
+// 1) + 16 SS) of the plane (zero outside it), which is all its tiles read, so the
+// image is a small fraction of a whole-plane one and two workgroups share a CU
+// (one's setup, staging and barriers under the other's matrix loop).  The tap rows,
+// the split of a tile's tap rows over wavefronts and the order of every sum are
+// those of the tiled kernel; outputs outside the covered rectangle are not written
+// (the adjoint ray march reads this volume only inside the box).
+struct AdjWin {
+  int WI, WJ;        // piece size in output tiles
+  int rows, pitch;   // image rows (16 WI + 2h) and row pitch
+  int E, SS;         // extended tap row length and column super-steps of a tile
+};
+
+// A piece's window: plane rows [r0, r0 + nr) and columns [c0, c0 + nc) go to image
+// rows and columns [0, nr) x [0, nc); plane positions outside the plane read zero.
+struct WinRect {
+  int r0, c0, nr, nc;
+};
+
+// Staging of a window in groups of four columns.  A thread keeps one column group
+// and walks rows with a stride of NT / (groups per row): its column tests are made
+// once per piece, and each group is one four-word load (any word address) and one
+// 16-byte LDS store.  Positions outside the plane read as zero.  A group partly
+// outside the plane's columns reads the words before column 0 or after column
+// Nv - 1 from the neighbouring row and clears them; only in the batch's first and
+// last planes could that leave the batch's data (before its first row, after its
+// last), so those planes are loaded word by word, the columns inside only.
+typedef float f32x4u_w __attribute__((ext_vector_type(4), aligned(4)));
+
+struct WinStage {
+  int cg, r0, step;  // the thread's column group and first window row; rows per pass
+  int pc;            // plane column of the group's first element
+  int cmask;         // bit e: column pc + e lies in the plane
+};
+
+__device__ __forceinline__ WinStage win_stage(const Geo<float>& g, const WinRect& w, int tid, int nt) {
+  WinStage st;
+  const int gw = w.nc >> 2;
+  st.r0 = opaque(tid) / gw;
+  st.cg = tid - st.r0 * gw;
+  st.step = nt / gw;
+  if (st.r0 >= st.step) st.r0 = w.nr;  // threads past the last whole row of groups stay idle
+  st.pc = w.c0 + 4 * st.cg;
+  st.cmask = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) st.cmask |= (st.pc + e >= 0 && st.pc + e < g.Nv) ? 1 << e : 0;
+  return st;
+}
+
+// Group r (window row) of the stage as loaded: positions outside the plane hold
+// whatever lies there (or zero) until mask_group clears them, so that a prefetch
+// does not wait for its loads.  SAFE (the batch's first and last planes) loads word
+// by word only the columns inside the plane; it is a uniform choice per plane, so
+// both forms keep every load of a thread in registers of its own.
+__device__ __forceinline__ bool group_row_ok(const Geo<float>& g, const WinRect& w, const WinStage& st, int r) {
+  const int pr = w.r0 + r;
+  return pr >= 0 && pr < g.Nu && st.cmask != 0;
+}
+
+template <bool SAFE>
+__device__ __forceinline__ f32x4 load_group(const float* __restrict__ src, const Geo<float>& g, const WinRect& w,
+                                            const WinStage& st, int r) {
+  const int pr = w.r0 + r;
+  const bool rok = group_row_ok(g, w, st, r);
+  const float* p = src + (rok ? pr * g.Nv + st.pc : 0);
+  f32x4 v;
+  if (SAFE) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = rok && ((st.cmask >> e) & 1) ? p[e] : 0.f;
+  } else {
+    const f32x4u_w x = *reinterpret_cast<const f32x4u_w*>(p);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = x[e];
+  }
+  return v;
+}
+
+__device__ __forceinline__ f32x4 mask_group(const Geo<float>& g, const WinRect& w, const WinStage& st, int r,
+                                            f32x4 v) {
+  const bool rok = group_row_ok(g, w, st, r);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = rok && ((st.cmask >> e) & 1) ? v[e] : 0.f;
+  return v;
+}
+
+template <int PG, bool SAFE>
+__device__ __forceinline__ void fetch_win_as(const float* __restrict__ src, const Geo<float>& g, const WinRect& w,
+                                             int tid, int nt, f32x4 (&buf)[PG]) {
+  const WinStage st = win_stage(g, w, tid, nt);
+  // every group is loaded (rows past the window read in-plane data or nothing and
+  // are not stored), so that no register keeps an older value beside the load
+#pragma unroll
+  for (int e = 0; e < PG; ++e) buf[e] = load_group<SAFE>(src, g, w, st, st.r0 + e * st.step);
+}
+
+template <int PG>
+__device__ __forceinline__ void fetch_win(const float* __restrict__ src, const Geo<float>& g, const WinRect& w,
+                                          bool edge, int tid, int nt, f32x4 (&buf)[PG]) {
+  if (edge) fetch_win_as<PG, true>(src, g, w, tid, nt, buf);
+  else fetch_win_as<PG, false>(src, g, w, tid, nt, buf);
+}
+
+template <int PG>
+__device__ __forceinline__ void put_win(const float* __restrict__ src, const Geo<float>& g, const WinRect& w,
+                                        bool edge, int pitch, int tid, int nt, const f32x4 (&buf)[PG],
+                                        float* tile) {
+  const WinStage st = win_stage(g, w, tid, nt);
+  float* t = tile + st.r0 * pitch + 4 * st.cg;
+#pragma unroll
+  for (int e = 0; e < PG; ++e) {
+    const int r = st.r0 + e * st.step;
+    if (r < w.nr) *reinterpret_cast<f32x4*>(t + e * st.step * pitch) = mask_group(g, w, st, r, buf[e]);
+  }
+  for (int r = st.r0 + PG * st.step; r < w.nr; r += st.step) {
+    const f32x4 v = edge ? load_group<true>(src, g, w, st, r) : load_group<false>(src, g, w, st, r);
+    *reinterpret_cast<f32x4*>(tile + r * pitch + 4 * st.cg) = mask_group(g, w, st, r, v);
+  }
+}
+
+// Column groups per thread prefetched by the windowed adjoint: the whole window of
+// a piece of 2 x 2 tiles with 61 taps (92 rows of 24 groups, 21 rows a pass over
+// 512 threads), so no group is loaded after the matrix loop that hides the latency.
+constexpr int PGW = 5;
+
+template <int NW, int TPW>
+__global__ void __launch_bounds__(64 * NW) k_conv_f32_adj_win(Geo<float> g, AdjWin aw, int n_items,
+                                                              const int4* __restrict__ box,
+                                                              const float* __restrict__ zca,
+                                                              const float* __restrict__ in,
+                                                              float* __restrict__ out) {
+  extern __shared__ __align__(16) float lds[];
+  constexpr int NT = 64 * NW;
+  const int h = g.h;
+  const int pitch = aw.pitch, E = aw.E, SS = aw.SS;
+  float* tile = lds;
+  float* kx = lds + aw.rows * pitch;
+  float* kq = kx + (h + 1) * E;
+  float* part = kq + (h + 1) * (h + 1);  // (NW - 1) x 256 partial sums, 16-byte aligned
+  part = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(part) + 15) & ~(uintptr_t)15);
+  const size_t plane = (size_t)g.Nu * g.Nv;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int m = lane & 15, kk = lane >> 4;
+  const float* bbase = kx + 4 * kk + 15 - m;
+  const int off = h + 15;
+
+  // the covered tiles of an item (nI = 0: nothing to compute) and a piece's window
+  struct Cov {
+    int Iw, Jw, nI, nJ, npi, npj;
+  };
+  auto cov_of = [&](int item) {
+    Cov c;
+    const int4 bx = box[item / g.Nk];
+    const int u0 = max(bx.x, 0), u1 = min(bx.y, g.Nu), v0 = max(bx.z, 0), v1 = min(bx.w, g.Nv);
+    c.Iw = u0;
+    c.Jw = v0;
+    c.nI = u1 > u0 && v1 > v0 ? (u1 - u0 + MT - 1) / MT : 0;
+    c.nJ = u1 > u0 && v1 > v0 ? (v1 - v0 + MT - 1) / MT : 0;
+    c.npi = (c.nI + aw.WI - 1) / aw.WI;
+    c.npj = (c.nJ + aw.WJ - 1) / aw.WJ;
+    return c;
+  };
+  auto win_of = [&](const Cov& c, int pp, int* nIp, int* nJp) {
+    const int pi = pp / c.npj, pj = pp - (pp / c.npj) * c.npj;
+    *nIp = min(aw.WI, c.nI - aw.WI * pi);
+    *nJp = min(aw.WJ, c.nJ - aw.WJ * pj);
+    WinRect w;
+    w.r0 = c.Iw + MT * aw.WI * pi - h;
+    w.c0 = c.Jw + MT * aw.WJ * pj - h;
+    w.nr = MT * *nIp + 2 * h;
+    w.nc = MT * (*nJp - 1) + 16 * SS;
+    return w;
+  };
+
+  // One trip per piece: item it, piece pp.  Items whose box misses the plane are
+  // skipped without staging; the next piece's input (of this item or of the next
+  // live one) is in flight during each piece's matrix work.
+  auto next_live = [&](int from, Cov* cv) {
+    for (; from < n_items; from += gridDim.x) {
+      *cv = cov_of(from);
+      if (cv->nI > 0) break;
+    }
+    return from;
+  };
+  f32x4 buf[PGW];
+  Cov c;
+  int it = next_live(blockIdx.x, &c), pp = 0;
+  if (it < n_items) {
+    int a, b;
+    fetch_win<PGW>(in + (size_t)it * plane, g, win_of(c, 0, &a, &b), it == 0 || it == n_items - 1, tid, NT, buf);
+  }
+  while (it < n_items) {
+    const float* src = in + (size_t)it * plane;
+    float* dst = out + (size_t)it * plane;
+    int nIp, nJp;
+    const WinRect w = win_of(c, pp, &nIp, &nJp);
+    put_win<PGW>(src, g, w, it == 0 || it == n_items - 1, pitch, tid, NT, buf, tile);
+    if (pp == 0) {
+      unique_taps(g, it % g.Nk, zca[it], kq, tid, NT);
+      __syncthreads();
+      build_kx(kq, kx, h, E, off, wave, lane, NW);
+    }
+    // the next piece: (it, pp + 1) or the first piece of the next live item
+    int nit = it, npp = pp + 1;
+    Cov cn = c;
+    if (npp == c.npi * c.npj) {
+      npp = 0;
+      nit = next_live(it + gridDim.x, &cn);
+    }
+    __syncthreads();
+    if (nit < n_items) {
+      int a, b;
+      fetch_win<PGW>(in + (size_t)nit * plane, g, win_of(cn, npp, &a, &b), nit == 0 || nit == n_items - 1, tid,
+                     NT, buf);
+    }
+    const int Ip = w.r0 + h, Jp = w.c0 + h;  // the piece's first output row and column
+    const int nT = nIp * nJp;
+    const int C = nT < NW ? NW / nT : 1;  // tap-row chunks per tile
+    const int chunk = wave % C, slot = wave / C, slots = NW / C;
+    const int h1 = h + 1, pa = (h1 * chunk) / C, pb = (h1 * (chunk + 1)) / C - 1;
+    int nact = 0;
+    const float* ab[TPW];
+    int oI[TPW], oJ[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = slot + slots * q;
+      const bool use = t < nT;
+      const int ti = use ? t / nJp : 0, tj = use ? t - (t / nJp) * nJp : 0;
+      oI[q] = Ip + MT * ti;
+      oJ[q] = Jp + MT * tj;
+      ab[q] = tile + (MT * ti + m + h) * pitch + MT * tj + 4 * kk;
+      nact += use ? 1 : 0;
+    }
+    f32x4 acc[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (nact == 1) f32_steps<1>(ab, bbase, pitch, E, pa, pb, 0, SS - 1, acc);
+    if (TPW >= 2 && nact == 2) f32_steps<TPW >= 2 ? 2 : 1>(ab, bbase, pitch, E, pa, pb, 0, SS - 1, acc);
+    if (C > 1) {
+      // (C > 1 only with one tile per wavefront) chunks 1 .. C-1 park their sums,
+      // chunk 0 adds them in order
+      __syncthreads();
+      if (chunk > 0 && nact > 0)
+        park_partial((lds_f32x4*)(part + ((slot * (C - 1) + chunk - 1) * 64 + lane) * 4), acc[0]);
+      __syncthreads();
+      if (chunk == 0 && nact > 0) {
+        for (int cc = 1; cc < C; ++cc)
+          acc[0] += *reinterpret_cast<const f32x4*>(part + ((slot * (C - 1) + cc - 1) * 64 + lane) * 4);
+        store_tile_from(g, oI[0], oJ[0], 0, 0, lane, acc[0], dst);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < TPW; ++q)
+        if (q < nact) store_tile_from(g, oI[q], oJ[q], 0, 0, lane, acc[q], dst);
+    }
+    __syncthreads();  // the image (and, before a new item, the taps) are rewritten next
+    it = nit;
+    pp = npp;
+    c = cn;
+  }
+}
+
 // ------------------------------------------------------------------ launch
 
 // Persistent grid: as many workgroups as fit on the device at once (a multiple of
@@ -835,6 +1154,69 @@ static hipError_t launch_f32_adj(const Geo<float>& g, const RegionShape& rs, con
   return launch_f32_adj_cfg<kAdjNW, 3>(g, rs, fs, nb, box, z, in, out, s);
 }
 
+
+// Wavefronts of the windowed adjoint: 8, two workgroups per CU at the field sizes
+// of the clinical planes (eight wavefronts, whose tiles' tap rows are split over
+// them, measured faster than four with whole tiles each).
+constexpr int kAdjWinNW = 8;
+
+static size_t f32_adj_win_lds(int h, const AdjWin& aw, int nw) {
+  return sizeof(float) * ((size_t)aw.rows * aw.pitch + (size_t)(h + 1) * aw.E + (size_t)(h + 1) * (h + 1)) + 16 +
+         sizeof(float) * 256 * (nw - 1);
+}
+
+template <int TPW>
+static hipError_t launch_f32_adj_win_cfg(const Geo<float>& g, const AdjWin& aw, int nb, const int4* box,
+                                         const float* z, const float* in, float* out, hipStream_t s) {
+  constexpr int NW = kAdjWinNW;
+  const void* kern = (const void*)k_conv_f32_adj_win<NW, TPW>;
+  const size_t lds = f32_adj_win_lds(g.h, aw, NW);
+  if (lds > LDS_MAX) return hipErrorInvalidConfiguration;
+  {
+    hipError_t e = ensure_lds_limit(kern, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const long n_items = (long)g.Nk * nb;
+  if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;
+  const int grid = persistent_grid(kern, 64 * NW, lds, 1, n_items);
+  hipLaunchKernelGGL((k_conv_f32_adj_win<NW, TPW>), dim3(grid), dim3(64 * NW), lds, s, g, aw, (int)n_items, box, z,
+                     in, out);
+  return hipGetLastError();
+}
+
+// Pieces sized for the largest rectangle that jaws inside the field limits give
+// (bigger rectangles take several pieces), at most 16 tiles (two per wavefront),
+// made smaller while the image does not fit the LDS.  False: not even one tile's
+// image fits.
+static bool f32_adj_win_shape(const Geo<float>& g, AdjWin* out) {
+  const int half_u = (g.Nu - 1) / 2 - g.h, half_v = (g.Nv - 1) / 2 - g.h;  // field limit in pixels
+  const int bu = 2 * (half_u > 0 ? half_u : 0) + 4, bv = 2 * (half_v > 0 ? half_v : 0) + 4;
+  AdjWin aw;
+  aw.WI = (bu + MT - 1) / MT;
+  aw.WJ = (bv + MT - 1) / MT;
+  aw.WI = aw.WI < 1 ? 1 : (aw.WI > 4 ? 4 : aw.WI);
+  aw.WJ = aw.WJ < 1 ? 1 : (aw.WJ > 4 ? 4 : aw.WJ);
+  aw.SS = (MT + 2 * g.h + 15) / 16;
+  aw.E = 16 * aw.SS + 16;
+  for (;;) {
+    aw.rows = MT * aw.WI + 2 * g.h;
+    aw.pitch = pitch_f32(MT * (aw.WJ - 1) + 16 * aw.SS);
+    if (f32_adj_win_lds(g.h, aw, kAdjWinNW) <= LDS_MAX) break;
+    if (aw.WI == 1 && aw.WJ == 1) return false;
+    if (aw.WJ >= aw.WI) --aw.WJ;
+    else --aw.WI;
+  }
+  *out = aw;
+  return true;
+}
+
+static hipError_t launch_f32_adj_win(const Geo<float>& g, const AdjWin& aw, int nb, const int4* box,
+                                     const float* z, const float* in, float* out, hipStream_t s) {
+  const int tiles = aw.WI * aw.WJ;
+  if (tiles <= kAdjWinNW) return launch_f32_adj_win_cfg<1>(g, aw, nb, box, z, in, out, s);
+  return launch_f32_adj_win_cfg<2>(g, aw, nb, box, z, in, out, s);
+}
+
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                 hipStream_t s, const int* box, int support) {
   const int4* bx = reinterpret_cast<const int4*>(box);
@@ -843,6 +1225,13 @@ hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, con
   // repeat the tap loop; the tiled kernel below is faster there)
   if (bx && support == CONV_IN_BOX && !g.fcorr && conv_fwd_reg_supported(g, false))
     return launch_conv_fwd_reg(g, nb, z, in, out, s, box, false);
+  // the adjoint with a window image, unless the fluence corrections widen the
+  // rectangles past the field limits its pieces are sized for (then each rectangle
+  // takes several pieces whose windows overlap; the region kernel below stages its
+  // data once)
+  AdjWin aw;
+  if (bx && support == CONV_OUT_BOX && !g.fcorr && f32_adj_win_shape(g, &aw))
+    return launch_f32_adj_win(g, aw, nb, bx, z, in, out, s);
   const bool adj = bx && support == CONV_OUT_BOX;
   RegionShape rs;
   F32Shape fs;
