@@ -27,6 +27,30 @@ __device__ __forceinline__ void unique_taps(const Geo<float>& g, int k, float zk
   }
 }
 
+// The same taps written straight into the extended, folded tap rows of the FP32
+// matrix kernels: kx[p][off + q] = kx[p][off - q] = K[p][q] for 0 <= p, q <= h,
+// row p = 0 halved (the fold counts it twice).  Pair (p, q), p <= q, fills the
+// four places of K[p][q] and of K[q][p]; every entry within h of `off` is written,
+// the rest of each row (zero) is not touched.
+__device__ __forceinline__ void taps_to_kx(const Geo<float>& g, int k, float zk, float* kx, int E, int off, int tid,
+                                           int nt) {
+  TapParams<float> tp = tap_params(g, k, zk);
+  const int h1 = g.h + 1;
+  for (int t = tid; t < h1 * (h1 + 1) / 2; t += nt) {
+    int q = (int)((sqrtf((float)(8 * t + 1)) - 1.f) * 0.5f);
+    if ((q + 1) * (q + 2) / 2 <= t) ++q;
+    if (q * (q + 1) / 2 > t) --q;
+    const int p = t - q * (q + 1) / 2;
+    const float v = tap_value(tp, p, q);
+    const float vp = p == 0 ? 0.5f * v : v;  // row p
+    const float vq = q == 0 ? 0.5f * v : v;  // row q
+    kx[p * E + off + q] = vp;
+    kx[p * E + off - q] = vp;
+    kx[q * E + off + p] = vq;
+    kx[q * E + off - p] = vq;
+  }
+}
+
 // The part of the plane that a region's LDS image holds: rows [r0, r0 + nr) and
 // columns [c0, c0 + nc) of the plane, stored at LDS row r - (I0 - h), column
 // c - (J0 - h).  Everything else in the image is zero and stays zero.

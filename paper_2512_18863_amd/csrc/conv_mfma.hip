@@ -941,8 +941,7 @@ __global__ void __launch_bounds__(64 * NW) k_conv_f32_adj_win(Geo<float> g, AdjW
   const int pitch = aw.pitch, E = aw.E, SS = aw.SS;
   float* tile = lds;
   float* kx = lds + aw.rows * pitch;
-  float* kq = kx + (h + 1) * E;
-  float* part = kq + (h + 1) * (h + 1);  // (NW - 1) x 256 partial sums, 16-byte aligned
+  float* part = kx + (h + 1) * E;  // (NW - 1) x 256 partial sums, 16-byte aligned
   part = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(part) + 15) & ~(uintptr_t)15);
   const size_t plane = (size_t)g.Nu * g.Nv;
   const int tid = threadIdx.x;
@@ -950,6 +949,10 @@ __global__ void __launch_bounds__(64 * NW) k_conv_f32_adj_win(Geo<float> g, AdjW
   const int m = lane & 15, kk = lane >> 4;
   const float* bbase = kx + 4 * kk + 15 - m;
   const int off = h + 15;
+  // the tap rows' entries farther than h from `off` stay zero; the taps of each item
+  // overwrite the others
+  zero_lds(kx, (h + 1) * E, tid, NT);
+  __syncthreads();
 
   // the covered tiles of an item (nI = 0: nothing to compute) and a piece's window
   struct Cov {
@@ -989,12 +992,18 @@ __global__ void __launch_bounds__(64 * NW) k_conv_f32_adj_win(Geo<float> g, AdjW
     }
     return from;
   };
+  // the central-axis depth of an item, read with a vector load so that it can be in
+  // flight during the matrix loop (an outstanding scalar load there would make
+  // each LDS wait a full one)
+  auto depth_of = [&](int item) { return zca[item + opaque(0)]; };
   f32x4 buf[PGW];
   Cov c;
   int it = next_live(blockIdx.x, &c), pp = 0;
+  float zk = 0.f;
   if (it < n_items) {
     int a, b;
     fetch_win<PGW>(in + (size_t)it * plane, g, win_of(c, 0, &a, &b), it == 0 || it == n_items - 1, tid, NT, buf);
+    zk = depth_of(it);
   }
   while (it < n_items) {
     const float* src = in + (size_t)it * plane;
@@ -1002,11 +1011,7 @@ __global__ void __launch_bounds__(64 * NW) k_conv_f32_adj_win(Geo<float> g, AdjW
     int nIp, nJp;
     const WinRect w = win_of(c, pp, &nIp, &nJp);
     put_win<PGW>(src, g, w, it == 0 || it == n_items - 1, pitch, tid, NT, buf, tile);
-    if (pp == 0) {
-      unique_taps(g, it % g.Nk, zca[it], kq, tid, NT);
-      __syncthreads();
-      build_kx(kq, kx, h, E, off, wave, lane, NW);
-    }
+    if (pp == 0) taps_to_kx(g, it % g.Nk, zk, kx, E, off, tid, NT);
     // the next piece: (it, pp + 1) or the first piece of the next live item
     int nit = it, npp = pp + 1;
     Cov cn = c;
@@ -1015,10 +1020,12 @@ __global__ void __launch_bounds__(64 * NW) k_conv_f32_adj_win(Geo<float> g, AdjW
       nit = next_live(it + gridDim.x, &cn);
     }
     __syncthreads();
+    float zn = zk;
     if (nit < n_items) {
       int a, b;
       fetch_win<PGW>(in + (size_t)nit * plane, g, win_of(cn, npp, &a, &b), nit == 0 || nit == n_items - 1, tid,
                      NT, buf);
+      if (npp == 0) zn = depth_of(nit);
     }
     const int Ip = w.r0 + h, Jp = w.c0 + h;  // the piece's first output row and column
     const int nT = nIp * nJp;
@@ -1064,6 +1071,7 @@ __global__ void __launch_bounds__(64 * NW) k_conv_f32_adj_win(Geo<float> g, AdjW
     it = nit;
     pp = npp;
     c = cn;
+    zk = zn;
   }
 }
 
@@ -1161,8 +1169,7 @@ static hipError_t launch_f32_adj(const Geo<float>& g, const RegionShape& rs, con
 constexpr int kAdjWinNW = 8;
 
 static size_t f32_adj_win_lds(int h, const AdjWin& aw, int nw) {
-  return sizeof(float) * ((size_t)aw.rows * aw.pitch + (size_t)(h + 1) * aw.E + (size_t)(h + 1) * (h + 1)) + 16 +
-         sizeof(float) * 256 * (nw - 1);
+  return sizeof(float) * ((size_t)aw.rows * aw.pitch + (size_t)(h + 1) * aw.E) + 16 + sizeof(float) * 256 * (nw - 1);
 }
 
 template <int TPW>

@@ -27,7 +27,7 @@ def shape(Nu, Nv, h, nw=8, lds_max=160 * 1024):
     while True:
         rows = MT * WI + 2 * h
         pitch = pitch_f32(MT * (WJ - 1) + 16 * SS)
-        lds = 4 * (rows * pitch + (h + 1) * E + (h + 1) ** 2) + 16 + 4 * 256 * (nw - 1)
+        lds = 4 * (rows * pitch + (h + 1) * E) + 16 + 4 * 256 * (nw - 1)
         if lds <= lds_max:
             return dict(WI=WI, WJ=WJ, SS=SS, E=E, rows=rows, pitch=pitch)
         if WI == 1 and WJ == 1:
@@ -137,7 +137,7 @@ def test_windowed_adjoint_matches_direct_convolution(Nu, Nv, h, box):
 def test_benchmark_shape_fits_two_workgroups_per_cu():
     aw = shape(89, 89, 30)
     assert (aw["WI"], aw["WJ"]) == (2, 2)
-    lds = 4 * (aw["rows"] * aw["pitch"] + 31 * aw["E"] + 31 * 31) + 16 + 4 * 256 * 7
+    lds = 4 * (aw["rows"] * aw["pitch"] + 31 * aw["E"]) + 16 + 4 * 256 * 7
     assert 2 * lds <= 160 * 1024
 
 
