@@ -199,6 +199,9 @@ __device__ __forceinline__ void f32_steps(const float* const* abase, const float
     f32x4v ac[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) ac[q] = MODE == 0 ? a0[q] + a1[q] : (MODE == 1 ? a0[q] : a1[q]);
+    // the step's adds before its matrix instructions: an add between two of them
+    // costs more issue time than the adds grouped
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -263,6 +266,7 @@ __device__ __forceinline__ void f32_steps_hpair(const float* abase, const float*
   };
   auto compute = [&](const f32x4v& a0, const f32x4v& a1, const float (&b0)[4], const float (&b1)[4]) {
     const f32x4v a = MODE == 0 ? a0 + a1 : (MODE == 1 ? a0 : a1);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b0[e], c0, 0, 0, 0);
