@@ -231,6 +231,89 @@ __device__ __forceinline__ void f32_steps(const float* const* abase, const float
   for (int q = 0; q < NA; ++q) acc[q] = ac_[q];
 }
 
+// The same sums (tap rows p in [pa, pb], all SS super-steps, both folded rows) for
+// a super-step count fixed at compile time: a tap row's steps are unrolled, so
+// their LDS addresses are immediate offsets of three pointers that move once per
+// row.  Two rows form one loop trip (with SS odd the second row's steps use the
+// operand sets in the other order); the operands of each step are loaded one
+// step ahead, across row ends as well; the order of every sum is that of
+// f32_steps.
+template <int NA, int SS>
+__device__ __forceinline__ void f32_rows(const float* const* abase, const float* bbase, int pitch, int E, int pa,
+                                         int pb, f32x4* acc) {
+  if (pb < pa) return;
+  const float* ap[NA];
+  const float* am[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    ap[q] = abase[q] + pa * pitch;
+    am[q] = abase[q] - pa * pitch;
+  }
+  const float* bp = bbase + pa * E;
+  f32x4 ac_[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) ac_[q] = acc[q];
+  f32x4v A0[2][NA], A1[2][NA];
+  float B[2][4];
+  auto load = [&](int set, int u) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) B[set][e] = bp[16 * u + e];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      A0[set][q] = *reinterpret_cast<const f32x4v*>(ap[q] + 16 * u);
+      A1[set][q] = *reinterpret_cast<const f32x4v*>(am[q] + 16 * u);
+    }
+  };
+  auto advance = [&](bool more) {  // to the next row, or (after the last) stay
+    const int da = more ? pitch : 0, db = more ? E : 0;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      ap[q] += da;
+      am[q] -= da;
+    }
+    bp += db;
+  };
+  auto compute = [&](int set) {
+    f32x4v ac[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) ac[q] = A0[set][q] + A1[set][q];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int q = 0; q < NA; ++q)
+        ac_[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[q][e], B[set][e], ac_[q], 0, 0, 0);
+    // the step's adds ahead of its matrix instructions, all together
+    __builtin_amdgcn_sched_group_barrier(0x002, 4 * NA, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 4 * NA, 0);
+  };
+  // one row whose step u uses set (S0 + u) & 1; returns false after the last row
+  auto row = [&](auto s0, int p) {
+    constexpr int S0 = decltype(s0)::value;
+#pragma unroll
+    for (int u = 0; u < SS; ++u) {
+      const int cur = (S0 + u) & 1, nxt = (S0 + u + 1) & 1;
+      if (u + 1 < SS) {
+        load(nxt, u + 1);
+      } else {
+        // the next row's first step (after the last row, the last row's again:
+        // unconditional, so that each step waits for its own operands only)
+        advance(p < pb);
+        load(nxt, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // the loads ahead of the matrix work they overlap
+      compute(cur);
+    }
+    return p < pb;
+  };
+  load(0, 0);
+  for (int p = pa;; p += 2) {
+    if (!row(std::integral_constant<int, 0>{}, p)) break;
+    if (!row(std::integral_constant<int, SS & 1>{}, p + 1)) break;
+  }
+#pragma unroll
+  for (int q = 0; q < NA; ++q) acc[q] = ac_[q];
+}
+
 // The same loop for two horizontally adjacent tiles whose column windows start at
 // the same input column: they share the A operand (the same input rows and
 // columns) and each multiplies it by its own Toeplitz operand, the right tile's
@@ -933,7 +1016,7 @@ __device__ __forceinline__ void put_win(const float* __restrict__ src, const Geo
 // 512 threads), so no group is loaded after the matrix loop that hides the latency.
 constexpr int PGW = 5;
 
-template <int NW, int TPW>
+template <int NW, int TPW, int SSC>
 __global__ void __launch_bounds__(64 * NW) k_conv_f32_adj_win(Geo<float> g, AdjWin aw, int n_items,
                                                               const int4* __restrict__ box,
                                                               const float* __restrict__ zca,
@@ -1052,8 +1135,14 @@ __global__ void __launch_bounds__(64 * NW) k_conv_f32_adj_win(Geo<float> g, AdjW
     f32x4 acc[TPW];
 #pragma unroll
     for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (nact == 1) f32_steps<1>(ab, bbase, pitch, E, pa, pb, 0, SS - 1, acc);
-    if (TPW >= 2 && nact == 2) f32_steps<TPW >= 2 ? 2 : 1>(ab, bbase, pitch, E, pa, pb, 0, SS - 1, acc);
+    // (SSC: the super-step count when fixed at compile time, 0 when not)
+    if (SSC > 0) {
+      if (nact == 1) f32_rows<1, SSC>(ab, bbase, pitch, E, pa, pb, acc);
+      if (TPW >= 2 && nact == 2) f32_rows<TPW >= 2 ? 2 : 1, SSC>(ab, bbase, pitch, E, pa, pb, acc);
+    } else {
+      if (nact == 1) f32_steps<1>(ab, bbase, pitch, E, pa, pb, 0, SS - 1, acc);
+      if (TPW >= 2 && nact == 2) f32_steps<TPW >= 2 ? 2 : 1>(ab, bbase, pitch, E, pa, pb, 0, SS - 1, acc);
+    }
     if (C > 1) {
       // (C > 1 only with one tile per wavefront) chunks 1 .. C-1 park their sums,
       // chunk 0 adds them in order
@@ -1176,11 +1265,11 @@ static size_t f32_adj_win_lds(int h, const AdjWin& aw, int nw) {
   return sizeof(float) * ((size_t)aw.rows * aw.pitch + (size_t)(h + 1) * aw.E) + 16 + sizeof(float) * 256 * (nw - 1);
 }
 
-template <int TPW>
+template <int TPW, int SSC>
 static hipError_t launch_f32_adj_win_cfg(const Geo<float>& g, const AdjWin& aw, int nb, const int4* box,
                                          const float* z, const float* in, float* out, hipStream_t s) {
   constexpr int NW = kAdjWinNW;
-  const void* kern = (const void*)k_conv_f32_adj_win<NW, TPW>;
+  const void* kern = (const void*)k_conv_f32_adj_win<NW, TPW, SSC>;
   const size_t lds = f32_adj_win_lds(g.h, aw, NW);
   if (lds > LDS_MAX) return hipErrorInvalidConfiguration;
   {
@@ -1190,7 +1279,7 @@ static hipError_t launch_f32_adj_win_cfg(const Geo<float>& g, const AdjWin& aw, 
   const long n_items = (long)g.Nk * nb;
   if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;
   const int grid = persistent_grid(kern, 64 * NW, lds, 1, n_items);
-  hipLaunchKernelGGL((k_conv_f32_adj_win<NW, TPW>), dim3(grid), dim3(64 * NW), lds, s, g, aw, (int)n_items, box, z,
+  hipLaunchKernelGGL((k_conv_f32_adj_win<NW, TPW, SSC>), dim3(grid), dim3(64 * NW), lds, s, g, aw, (int)n_items, box, z,
                      in, out);
   return hipGetLastError();
 }
@@ -1224,8 +1313,17 @@ static bool f32_adj_win_shape(const Geo<float>& g, AdjWin* out) {
 static hipError_t launch_f32_adj_win(const Geo<float>& g, const AdjWin& aw, int nb, const int4* box,
                                      const float* z, const float* in, float* out, hipStream_t s) {
   const int tiles = aw.WI * aw.WJ;
-  if (tiles <= kAdjWinNW) return launch_f32_adj_win_cfg<1>(g, aw, nb, box, z, in, out, s);
-  return launch_f32_adj_win_cfg<2>(g, aw, nb, box, z, in, out, s);
+  // super-step counts of 41 to 65 taps (h 17 to 32) unrolled, others looped
+  if (aw.SS == 5) {
+    if (tiles <= kAdjWinNW) return launch_f32_adj_win_cfg<1, 5>(g, aw, nb, box, z, in, out, s);
+    return launch_f32_adj_win_cfg<2, 5>(g, aw, nb, box, z, in, out, s);
+  }
+  if (aw.SS == 4) {
+    if (tiles <= kAdjWinNW) return launch_f32_adj_win_cfg<1, 4>(g, aw, nb, box, z, in, out, s);
+    return launch_f32_adj_win_cfg<2, 4>(g, aw, nb, box, z, in, out, s);
+  }
+  if (tiles <= kAdjWinNW) return launch_f32_adj_win_cfg<1, 0>(g, aw, nb, box, z, in, out, s);
+  return launch_f32_adj_win_cfg<2, 0>(g, aw, nb, box, z, in, out, s);
 }
 
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
