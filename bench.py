@@ -44,8 +44,9 @@ KERNELS = {
     # adjoint: the window kernel <NW, TPW> (the region kernel serves the fluence corrections)
     "conv_mfma_f32_adj": (("k_conv_f32_adj_win<", "k_conv_mfma_f32_adj<"), _CONV),
     "conv_mfma_bf16": (("k_conv_fwd_reg<true,",), _FWDREG),
-    # template arguments <NK, BR, BC, NWB, NWP, SUP>: adjoint 2 x 2 tiles in four wavefronts
-    "conv_mfma_bf16_adj": (("k_conv_bf16<*,2,2,1,4,*",), _CONV16),
+    # BF16 adjoint: the window kernel <NK> (the tiled kernel <NK, BR, BC, NWB, NWP, SUP> with
+    # 2 x 2 tiles in four wavefronts serves the fluence corrections)
+    "conv_mfma_bf16_adj": (("k_conv_bf16_adj_win<", "k_conv_bf16<*,2,2,1,4,*"), _CONV16),
     "march": (("k_march_serial<float,0,",), _FWD),
     "march_adj": (("k_march_serial<float,1,",), _FWD),
     "gather": (("k_gather<float",), _FWD),

@@ -308,6 +308,277 @@ k_conv_bf16(Geo<float> g, Bf16Plan q, const int4* __restrict__ box,
   }
 }
 
+// ---------------------------------------------------------------- windowed adjoint
+//
+// The adjoint with persistent workgroups of eight wavefronts that stage, per item,
+// only the window their output tiles read, as in the FP32 windowed adjoint: the
+// rectangle (clipped to the plane) is covered by 16 x 16 output tiles at its
+// corner, taken in pieces of at most 2 x 2 tiles; a piece's image holds plane
+// rows [I - h, I + 16 nI + h) and the 32 NK columns from J - h that its K-steps
+// read (zero outside the plane), staged in four-column groups (one four-word load,
+// two BF16 pairs, one 8-byte LDS store) and prefetched into registers during the
+// previous piece's matrix loop.  The tap rows are padded so that every B run of
+// every lane lies inside them (no masks): two copies of each row of taps |p|, the
+// second shifted by one element, so that a run is four aligned words at any
+// offset.  The 2h + 1 tap rows are split over the eight wavefronts; their sums are
+// added in LDS in wavefront order.  The arithmetic of every output is that of the
+// tiled kernel (BF16 operands, FP32 products and sums).
+struct Bf16AdjWin {
+  int rows, pitch;  // image rows (32 + 2h) and pitch in BF16 elements (32 NK + 8)
+  int L2;           // words per padded tap row (each copy): 16 NK + 16
+};
+
+// Element x of a padded tap row holds K[p][|x - X0|] (zero beyond h), X0 = h + 32:
+// the run of lane (m, kq) for column tile t and K-step s starts at
+// x = 32 s + 8 kq - 16 t - m + 32, in [1, 32 NK + 24].
+constexpr int kBwX0 = 32;
+
+template <int NK>
+__global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16AdjWin bw, int n_items,
+                                                           const int4* __restrict__ box,
+                                                           const float* __restrict__ zca,
+                                                           const float* __restrict__ in, float* __restrict__ out) {
+  constexpr int NW = 8, NT = 64 * NW, BR = 2, BC = 2, PG = 5;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int h = g.h, L2 = bw.L2, pitch = bw.pitch;
+  unsigned* T0 = reinterpret_cast<unsigned*>(smem_raw);  // [h + 1][L2]: elements (2i, 2i + 1)
+  unsigned* T1 = T0 + (h + 1) * L2;                      // elements (2i + 1, 2i + 2)
+  float* kq = reinterpret_cast<float*>(T1 + (h + 1) * L2);
+  const size_t img_off = ((reinterpret_cast<uintptr_t>(kq + (h + 1) * (h + 1)) + 15) & ~(uintptr_t)15);
+  __bf16* img = reinterpret_cast<__bf16*>(img_off);
+  f32x4c* red = reinterpret_cast<f32x4c*>(img_off + (((size_t)bw.rows * pitch * 2 + 15) & ~(size_t)15));
+  const size_t plane = (size_t)g.Nu * g.Nv;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m = lane & 15, kqd = lane >> 4;
+
+  struct Cov {
+    int Iw, Jw, nI, nJ, npi, npj;
+  };
+  auto cov_of = [&](int item) {
+    Cov c;
+    const int4 bx = box[item / g.Nk];
+    const int u0 = max(bx.x, 0), u1 = min(bx.y, g.Nu), v0 = max(bx.z, 0), v1 = min(bx.w, g.Nv);
+    c.Iw = u0;
+    c.Jw = v0;
+    c.nI = u1 > u0 && v1 > v0 ? (u1 - u0 + 15) / 16 : 0;
+    c.nJ = u1 > u0 && v1 > v0 ? (v1 - v0 + 15) / 16 : 0;
+    c.npi = (c.nI + BR - 1) / BR;
+    c.npj = (c.nJ + BC - 1) / BC;
+    return c;
+  };
+  auto win_of = [&](const Cov& c, int pp, int* nIp, int* nJp) {
+    const int pi = pp / c.npj, pj = pp - (pp / c.npj) * c.npj;
+    *nIp = min(BR, c.nI - BR * pi);
+    *nJp = min(BC, c.nJ - BC * pj);
+    WinRect w;
+    w.r0 = c.Iw + 16 * BR * pi - h;
+    w.c0 = c.Jw + 16 * BC * pj - h;
+    w.nr = 16 * *nIp + 2 * h;
+    w.nc = 32 * NK;
+    return w;
+  };
+  auto next_live = [&](int from, Cov* cv) {
+    for (; from < n_items; from += gridDim.x) {
+      *cv = cov_of(from);
+      if (cv->nI > 0) break;
+    }
+    return from;
+  };
+  auto depth_of = [&](int item) { return zca[item + opaque(0)]; };
+  // a piece's window groups into the BF16 image (masked, then rounded to BF16)
+  auto put_bf16 = [&](const float* src, const WinRect& w, bool edge, const f32x4 (&buf)[PG]) {
+    const WinStage st = win_stage(g, w, tid, NT);
+    auto store = [&](int r, f32x4 v) {
+      v = mask_group(g, w, st, r, v);
+      *reinterpret_cast<uint2*>(img + r * pitch + 4 * st.cg) = make_uint2(bf16_pair(v[0], v[1]), bf16_pair(v[2], v[3]));
+    };
+#pragma unroll
+    for (int e = 0; e < PG; ++e) {
+      const int r = st.r0 + e * st.step;
+      if (r < w.nr) store(r, buf[e]);
+    }
+    for (int r = st.r0 + PG * st.step; r < w.nr; r += st.step)
+      store(r, edge ? load_group<true>(src, g, w, st, r) : load_group<false>(src, g, w, st, r));
+  };
+
+  f32x4 buf[PG];
+  Cov c;
+  int it = next_live(blockIdx.x, &c), pp = 0;
+  float zk = 0.f;
+  if (it < n_items) {
+    int a, b;
+    fetch_win<PG>(in + (size_t)it * plane, g, win_of(c, 0, &a, &b), it == 0 || it == n_items - 1, tid, NT, buf);
+    zk = depth_of(it);
+  }
+  while (it < n_items) {
+    const float* src = in + (size_t)it * plane;
+    float* dst = out + (size_t)it * plane;
+    int nIp, nJp;
+    const WinRect w = win_of(c, pp, &nIp, &nJp);
+    put_bf16(src, w, it == 0 || it == n_items - 1, buf);
+    if (pp == 0) {
+      unique_taps(g, it % g.Nk, zk, kq, tid, NT);
+      __syncthreads();
+      // the padded rows, a wavefront per row, lanes along the words
+      for (int p = wave; p <= h; p += NW)
+        for (int i = lane; i < L2; i += 64) {
+          float v[3];
+#pragma unroll
+          for (int e = 0; e < 3; ++e) {
+            const int d = 2 * i + e - (h + kBwX0);
+            const int ad = d < 0 ? -d : d;
+            v[e] = ad <= h ? kq[p * (h + 1) + ad] : 0.f;
+          }
+          T0[p * L2 + i] = bf16_pair(v[0], v[1]);
+          T1[p * L2 + i] = bf16_pair(v[1], v[2]);
+        }
+    }
+    int nit = it, npp = pp + 1;
+    Cov cn = c;
+    if (npp == c.npi * c.npj) {
+      npp = 0;
+      nit = next_live(it + gridDim.x, &cn);
+    }
+    __syncthreads();
+    float zn = zk;
+    if (nit < n_items) {
+      int a, b;
+      fetch_win<PG>(in + (size_t)nit * plane, g, win_of(cn, npp, &a, &b), nit == 0 || nit == n_items - 1, tid, NT,
+                    buf);
+      if (npp == 0) zn = depth_of(nit);
+    }
+    // this wavefront's tap rows p in [pa, pz)
+    const int pa = -h + ((2 * h + 1) * wave) / NW, pz = -h + ((2 * h + 1) * (wave + 1)) / NW;
+    const unsigned* bb[BC][NK];
+#pragma unroll
+    for (int t = 0; t < BC; ++t)
+#pragma unroll
+      for (int s2 = 0; s2 < NK; ++s2) {
+        const int x = 32 * s2 + 8 * kqd - 16 * t - m + kBwX0;
+        bb[t][s2] = ((x & 1) ? T1 : T0) + (x >> 1);
+      }
+    const __bf16* ab = img + (m + h) * pitch + 8 * kqd;
+    const bool r1 = nIp > 1, t1 = nJp > 1;
+    f32x4c acc[BR][BC];
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+#pragma unroll
+      for (int t = 0; t < BC; ++t) acc[r][t] = f32x4c{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int p = pa; p < pz; ++p) {
+      const int ap = p < 0 ? -p : p;
+      u32x4c Bw[BC][NK], Aw[BR][NK];
+#pragma unroll
+      for (int t = 0; t < BC; ++t)
+#pragma unroll
+        for (int s2 = 0; s2 < NK; ++s2) {
+          const unsigned* row = bb[t][s2] + ap * L2;
+          Bw[t][s2] = u32x4c{row[0], row[1], row[2], row[3]};
+        }
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
+#pragma unroll
+        for (int s2 = 0; s2 < NK; ++s2)
+          Aw[r][s2] = *reinterpret_cast<const u32x4c*>(ab + (16 * r + p) * pitch + 32 * s2);
+#pragma unroll
+      for (int s2 = 0; s2 < NK; ++s2) {
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, Aw[0][s2]),
+                                                            __builtin_bit_cast(bf16x8c, Bw[0][s2]), acc[0][0], 0, 0, 0);
+        if (t1)
+          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, Aw[0][s2]),
+                                                              __builtin_bit_cast(bf16x8c, Bw[1][s2]), acc[0][1], 0, 0,
+                                                              0);
+        if (r1) {
+          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, Aw[1][s2]),
+                                                              __builtin_bit_cast(bf16x8c, Bw[0][s2]), acc[1][0], 0, 0,
+                                                              0);
+          if (t1)
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, Aw[1][s2]),
+                                                                __builtin_bit_cast(bf16x8c, Bw[1][s2]), acc[1][1], 0,
+                                                                0, 0);
+        }
+      }
+    }
+    // wavefronts 1 .. 7 park their sums, wavefront 0 adds them in that order
+    __syncthreads();
+    if (wave > 0) {
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
+#pragma unroll
+        for (int t = 0; t < BC; ++t) red[(((wave - 1) * BR + r) * BC + t) * 64 + lane] = acc[r][t];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll 1
+      for (int v = 1; v < NW; ++v)
+#pragma unroll
+        for (int r = 0; r < BR; ++r)
+#pragma unroll
+          for (int t = 0; t < BC; ++t) acc[r][t] += red[(((v - 1) * BR + r) * BC + t) * 64 + lane];
+      const int Ip = w.r0 + h, Jp = w.c0 + h;
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
+#pragma unroll
+        for (int t = 0; t < BC; ++t) {
+          const int j = Jp + 16 * t + m;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int i = Ip + 16 * r + 4 * kqd + e;
+            if (r < nIp && t < nJp && i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[r][t][e];
+          }
+        }
+    }
+    __syncthreads();  // the image, the sums' area and (before a new item) the taps are rewritten next
+    it = nit;
+    pp = npp;
+    c = cn;
+    zk = zn;
+  }
+}
+
+static size_t bf16_adj_win_lds(int h, const Bf16AdjWin& bw) {
+  size_t b = (size_t)2 * (h + 1) * bw.L2 * 4 + (size_t)(h + 1) * (h + 1) * 4;
+  b = (b + 15) & ~(size_t)15;
+  b += ((size_t)bw.rows * bw.pitch * 2 + 15) & ~(size_t)15;
+  b += (size_t)7 * 4 * 64 * 16;  // the parts' sums
+  return b + 16;
+}
+
+template <int NK>
+static hipError_t launch_bf16_adj_win_nk(const Geo<float>& g, int nb, const int4* box, const float* z,
+                                         const float* in, float* out, hipStream_t s) {
+  Bf16AdjWin bw;
+  bw.rows = 32 + 2 * g.h;
+  bw.pitch = 32 * NK + 8;
+  bw.L2 = 16 * NK + 16;
+  const size_t lds = bf16_adj_win_lds(g.h, bw);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  const void* kern = (const void*)k_conv_bf16_adj_win<NK>;
+  {
+    hipError_t e = ensure_lds_limit(kern, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const long n_items = (long)nb * g.Nk;
+  if (n_items > 0x7fffffffL) return hipErrorInvalidConfiguration;
+  const int grid = persistent_grid(kern, 512, lds, 1, n_items);
+  hipLaunchKernelGGL((k_conv_bf16_adj_win<NK>), dim3(grid), dim3(512), lds, s, g, bw, (int)n_items, box, z, in, out);
+  return hipGetLastError();
+}
+
+// The windowed adjoint for K-step counts up to 4 (h <= 48); false: not served.
+static bool launch_bf16_adj_win(const Geo<float>& g, int nb, const int4* box, const float* z, const float* in,
+                                float* out, hipStream_t s, hipError_t* err) {
+  const int nk = (32 + 2 * g.h + 31) / 32;
+  switch (nk) {
+    case 1: *err = launch_bf16_adj_win_nk<1>(g, nb, box, z, in, out, s); return true;
+    case 2: *err = launch_bf16_adj_win_nk<2>(g, nb, box, z, in, out, s); return true;
+    case 3: *err = launch_bf16_adj_win_nk<3>(g, nb, box, z, in, out, s); return true;
+    case 4: *err = launch_bf16_adj_win_nk<4>(g, nb, box, z, in, out, s); return true;
+    default: return false;
+  }
+}
+
 // Bounds of the aperture rectangle for jaws inside the field limits, as the
 // aperture-box kernel computes it (one pixel of margin each side): the image is
 // sized for it, and larger rectangles are processed in row and column chunks.
@@ -377,7 +648,13 @@ static hipError_t launch_bf16_sup(const Geo<float>& g, int nb, const int4* box, 
 hipError_t launch_conv_mfma_bf16(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
                                  hipStream_t s, const int* box, int support) {
   const int4* bx = reinterpret_cast<const int4*>(box);
-  if (support == CONV_OUT_BOX && bx) return launch_bf16_sup<CONV_OUT_BOX>(g, nb, bx, z, in, out, s);
+  if (support == CONV_OUT_BOX && bx) {
+    // the windowed adjoint, unless the fluence corrections widen the rectangles (as
+    // for FP32, the tiled kernel's chunks serve them)
+    hipError_t e;
+    if (!g.fcorr && launch_bf16_adj_win(g, nb, bx, z, in, out, s, &e)) return e;
+    return launch_bf16_sup<CONV_OUT_BOX>(g, nb, bx, z, in, out, s);
+  }
   // the forward with the rectangle in registers where its tap rows fit (not with
   // the fluence corrections' widened rectangles, as for FP32)
   if (support == CONV_IN_BOX && bx && !g.fcorr && conv_fwd_reg_supported(g, true))

@@ -905,112 +905,6 @@ struct AdjWin {
   int E, SS;         // extended tap row length and column super-steps of a tile
 };
 
-// A piece's window: plane rows [r0, r0 + nr) and columns [c0, c0 + nc) go to image
-// rows and columns [0, nr) x [0, nc); plane positions outside the plane read zero.
-struct WinRect {
-  int r0, c0, nr, nc;
-};
-
-// Staging of a window in groups of four columns.  A thread keeps one column group
-// and walks rows with a stride of NT / (groups per row): its column tests are made
-// once per piece, and each group is one four-word load (any word address) and one
-// 16-byte LDS store.  Positions outside the plane read as zero.  A group partly
-// outside the plane's columns reads the words before column 0 or after column
-// Nv - 1 from the neighbouring row and clears them; only in the batch's first and
-// last planes could that leave the batch's data (before its first row, after its
-// last), so those planes are loaded word by word, the columns inside only.
-typedef float f32x4u_w __attribute__((ext_vector_type(4), aligned(4)));
-
-struct WinStage {
-  int cg, r0, step;  // the thread's column group and first window row; rows per pass
-  int pc;            // plane column of the group's first element
-  int cmask;         // bit e: column pc + e lies in the plane
-};
-
-__device__ __forceinline__ WinStage win_stage(const Geo<float>& g, const WinRect& w, int tid, int nt) {
-  WinStage st;
-  const int gw = w.nc >> 2;
-  st.r0 = opaque(tid) / gw;
-  st.cg = tid - st.r0 * gw;
-  st.step = nt / gw;
-  if (st.r0 >= st.step) st.r0 = w.nr;  // threads past the last whole row of groups stay idle
-  st.pc = w.c0 + 4 * st.cg;
-  st.cmask = 0;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) st.cmask |= (st.pc + e >= 0 && st.pc + e < g.Nv) ? 1 << e : 0;
-  return st;
-}
-
-// Group r (window row) of the stage as loaded: positions outside the plane hold
-// whatever lies there (or zero) until mask_group clears them, so that a prefetch
-// does not wait for its loads.  SAFE (the batch's first and last planes) loads word
-// by word only the columns inside the plane; it is a uniform choice per plane, so
-// both forms keep every load of a thread in registers of its own.
-__device__ __forceinline__ bool group_row_ok(const Geo<float>& g, const WinRect& w, const WinStage& st, int r) {
-  const int pr = w.r0 + r;
-  return pr >= 0 && pr < g.Nu && st.cmask != 0;
-}
-
-template <bool SAFE>
-__device__ __forceinline__ f32x4 load_group(const float* __restrict__ src, const Geo<float>& g, const WinRect& w,
-                                            const WinStage& st, int r) {
-  const int pr = w.r0 + r;
-  const bool rok = group_row_ok(g, w, st, r);
-  const float* p = src + (rok ? pr * g.Nv + st.pc : 0);
-  f32x4 v;
-  if (SAFE) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = rok && ((st.cmask >> e) & 1) ? p[e] : 0.f;
-  } else {
-    const f32x4u_w x = *reinterpret_cast<const f32x4u_w*>(p);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = x[e];
-  }
-  return v;
-}
-
-__device__ __forceinline__ f32x4 mask_group(const Geo<float>& g, const WinRect& w, const WinStage& st, int r,
-                                            f32x4 v) {
-  const bool rok = group_row_ok(g, w, st, r);
-#pragma unroll
-  for (int e = 0; e < 4; ++e) v[e] = rok && ((st.cmask >> e) & 1) ? v[e] : 0.f;
-  return v;
-}
-
-template <int PG, bool SAFE>
-__device__ __forceinline__ void fetch_win_as(const float* __restrict__ src, const Geo<float>& g, const WinRect& w,
-                                             int tid, int nt, f32x4 (&buf)[PG]) {
-  const WinStage st = win_stage(g, w, tid, nt);
-  // every group is loaded (rows past the window read in-plane data or nothing and
-  // are not stored), so that no register keeps an older value beside the load
-#pragma unroll
-  for (int e = 0; e < PG; ++e) buf[e] = load_group<SAFE>(src, g, w, st, st.r0 + e * st.step);
-}
-
-template <int PG>
-__device__ __forceinline__ void fetch_win(const float* __restrict__ src, const Geo<float>& g, const WinRect& w,
-                                          bool edge, int tid, int nt, f32x4 (&buf)[PG]) {
-  if (edge) fetch_win_as<PG, true>(src, g, w, tid, nt, buf);
-  else fetch_win_as<PG, false>(src, g, w, tid, nt, buf);
-}
-
-template <int PG>
-__device__ __forceinline__ void put_win(const float* __restrict__ src, const Geo<float>& g, const WinRect& w,
-                                        bool edge, int pitch, int tid, int nt, const f32x4 (&buf)[PG],
-                                        float* tile) {
-  const WinStage st = win_stage(g, w, tid, nt);
-  float* t = tile + st.r0 * pitch + 4 * st.cg;
-#pragma unroll
-  for (int e = 0; e < PG; ++e) {
-    const int r = st.r0 + e * st.step;
-    if (r < w.nr) *reinterpret_cast<f32x4*>(t + e * st.step * pitch) = mask_group(g, w, st, r, buf[e]);
-  }
-  for (int r = st.r0 + PG * st.step; r < w.nr; r += st.step) {
-    const f32x4 v = edge ? load_group<true>(src, g, w, st, r) : load_group<false>(src, g, w, st, r);
-    *reinterpret_cast<f32x4*>(tile + r * pitch + 4 * st.cg) = mask_group(g, w, st, r, v);
-  }
-}
-
 // Column groups per thread prefetched by the windowed adjoint: the whole window of
 // a piece of 2 x 2 tiles with 61 taps (92 rows of 24 groups, 21 rows a pass over
 // 512 threads), so no group is loaded after the matrix loop that hides the latency.
