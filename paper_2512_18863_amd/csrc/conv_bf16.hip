@@ -450,14 +450,10 @@ __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16Adj
     }
     // this wavefront's tap rows p in [pa, pz)
     const int pa = -h + ((2 * h + 1) * wave) / NW, pz = -h + ((2 * h + 1) * (wave + 1)) / NW;
-    const unsigned* bb[BC][NK];
-#pragma unroll
-    for (int t = 0; t < BC; ++t)
-#pragma unroll
-      for (int s2 = 0; s2 < NK; ++s2) {
-        const int x = 32 * s2 + 8 * kqd - 16 * t - m + kBwX0;
-        bb[t][s2] = ((x & 1) ? T1 : T0) + (x >> 1);
-      }
+    // every B run of the lane has the parity of its first one (tile 0, K-step 0):
+    // tile t, step s start 16 s - 8 t words further in the same copy
+    const int x0 = 8 * kqd - m + kBwX0;
+    const unsigned* bb = ((x0 & 1) ? T1 : T0) + (x0 >> 1);
     const __bf16* ab = img + (m + h) * pitch + 8 * kqd;
     const bool r1 = nIp > 1, t1 = nJp > 1;
     f32x4c acc[BR][BC];
@@ -465,40 +461,47 @@ __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16Adj
     for (int r = 0; r < BR; ++r)
 #pragma unroll
       for (int t = 0; t < BC; ++t) acc[r][t] = f32x4c{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-    for (int p = pa; p < pz; ++p) {
-      const int ap = p < 0 ? -p : p;
-      u32x4c Bw[BC][NK], Aw[BR][NK];
+    // the operands of tap row p: B runs of both column tiles, A fragments of both
+    // row tiles (rows past the piece's tiles read the image's first rows, unused)
+    struct Ops {
+      u32x4c B[BC][NK], A[BR][NK];
+    };
+    auto load = [&](int p, Ops& o) {
+      const unsigned* row = bb + (p < 0 ? -p : p) * L2;
+      const __bf16* a0 = ab + p * pitch;
 #pragma unroll
       for (int t = 0; t < BC; ++t)
 #pragma unroll
         for (int s2 = 0; s2 < NK; ++s2) {
-          const unsigned* row = bb[t][s2] + ap * L2;
-          Bw[t][s2] = u32x4c{row[0], row[1], row[2], row[3]};
+          const unsigned* w = row + 16 * s2 - 8 * t;
+          o.B[t][s2] = u32x4c{w[0], w[1], w[2], w[3]};
         }
 #pragma unroll
       for (int r = 0; r < BR; ++r)
 #pragma unroll
         for (int s2 = 0; s2 < NK; ++s2)
-          Aw[r][s2] = *reinterpret_cast<const u32x4c*>(ab + (16 * r + p) * pitch + 32 * s2);
+          o.A[r][s2] = *reinterpret_cast<const u32x4c*>(a0 + 16 * r * pitch + 32 * s2);
+    };
+    auto mfma = [&](const u32x4c& A, const u32x4c& B, f32x4c& c) {
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, A), __builtin_bit_cast(bf16x8c, B), c,
+                                                  0, 0, 0);
+    };
+    auto compute = [&](const Ops& o) {
 #pragma unroll
       for (int s2 = 0; s2 < NK; ++s2) {
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, Aw[0][s2]),
-                                                            __builtin_bit_cast(bf16x8c, Bw[0][s2]), acc[0][0], 0, 0, 0);
-        if (t1)
-          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, Aw[0][s2]),
-                                                              __builtin_bit_cast(bf16x8c, Bw[1][s2]), acc[0][1], 0, 0,
-                                                              0);
+        mfma(o.A[0][s2], o.B[0][s2], acc[0][0]);
+        if (t1) mfma(o.A[0][s2], o.B[1][s2], acc[0][1]);
         if (r1) {
-          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, Aw[1][s2]),
-                                                              __builtin_bit_cast(bf16x8c, Bw[0][s2]), acc[1][0], 0, 0,
-                                                              0);
-          if (t1)
-            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, Aw[1][s2]),
-                                                                __builtin_bit_cast(bf16x8c, Bw[1][s2]), acc[1][1], 0,
-                                                                0, 0);
+          mfma(o.A[1][s2], o.B[0][s2], acc[1][0]);
+          if (t1) mfma(o.A[1][s2], o.B[1][s2], acc[1][1]);
         }
       }
+    };
+#pragma unroll 1
+    for (int p = pa; p < pz; ++p) {
+      Ops o;
+      load(p, o);
+      compute(o);
     }
     // wavefronts 1 .. 7 park their sums, wavefront 0 adds them in that order
     __syncthreads();
