@@ -321,8 +321,9 @@ k_conv_bf16(Geo<float> g, Bf16Plan q, const int4* __restrict__ box,
 // every lane lies inside them (no masks): two copies of each row of taps |p|, the
 // second shifted by one element, so that a run is four aligned words at any
 // offset.  The 2h + 1 tap rows are split over the eight wavefronts; their sums are
-// added in LDS in wavefront order.  The arithmetic of every output is that of the
-// tiled kernel (BF16 operands, FP32 products and sums).
+// added in LDS in wavefront order, one tile per wavefront.  The arithmetic of
+// every output is that of the tiled kernel (BF16 operands, FP32 products and
+// sums).
 struct Bf16AdjWin {
   int rows, pitch;  // image rows (32 + 2h) and pitch in BF16 elements (32 NK + 8)
   int L2;           // words per padded tap row (each copy): 16 NK + 16
@@ -503,34 +504,28 @@ __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16Adj
       load(p, o);
       compute(o);
     }
-    // wavefronts 1 .. 7 park their sums, wavefront 0 adds them in that order
+    // every wavefront parks its sums; wavefront t < 4 then adds tile t's eight
+    // parts in wavefront order and stores the tile
     __syncthreads();
-    if (wave > 0) {
 #pragma unroll
-      for (int r = 0; r < BR; ++r)
+    for (int r = 0; r < BR; ++r)
 #pragma unroll
-        for (int t = 0; t < BC; ++t) red[(((wave - 1) * BR + r) * BC + t) * 64 + lane] = acc[r][t];
-    }
+      for (int t = 0; t < BC; ++t) red[((wave * BR + r) * BC + t) * 64 + lane] = acc[r][t];
     __syncthreads();
-    if (wave == 0) {
+    if (wave < BR * BC) {
+      const int r = wave / BC, t = wave % BC;
+      if (r < nIp && t < nJp) {
+        f32x4c sum = red[(r * BC + t) * 64 + lane];
 #pragma unroll 1
-      for (int v = 1; v < NW; ++v)
+        for (int v = 1; v < NW; ++v) sum += red[((v * BR + r) * BC + t) * 64 + lane];
+        const int Ip = w.r0 + h, Jp = w.c0 + h;
+        const int j = Jp + 16 * t + m;
 #pragma unroll
-        for (int r = 0; r < BR; ++r)
-#pragma unroll
-          for (int t = 0; t < BC; ++t) acc[r][t] += red[(((v - 1) * BR + r) * BC + t) * 64 + lane];
-      const int Ip = w.r0 + h, Jp = w.c0 + h;
-#pragma unroll
-      for (int r = 0; r < BR; ++r)
-#pragma unroll
-        for (int t = 0; t < BC; ++t) {
-          const int j = Jp + 16 * t + m;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int i = Ip + 16 * r + 4 * kqd + e;
-            if (r < nIp && t < nJp && i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = acc[r][t][e];
-          }
+        for (int e = 0; e < 4; ++e) {
+          const int i = Ip + 16 * r + 4 * kqd + e;
+          if (i < g.Nu && j < g.Nv) dst[(size_t)i * g.Nv + j] = sum[e];
         }
+      }
     }
     __syncthreads();  // the image, the sums' area and (before a new item) the taps are rewritten next
     it = nit;
@@ -544,7 +539,7 @@ static size_t bf16_adj_win_lds(int h, const Bf16AdjWin& bw) {
   size_t b = (size_t)2 * (h + 1) * bw.L2 * 4 + (size_t)(h + 1) * (h + 1) * 4;
   b = (b + 15) & ~(size_t)15;
   b += ((size_t)bw.rows * bw.pitch * 2 + 15) & ~(size_t)15;
-  b += (size_t)7 * 4 * 64 * 16;  // the parts' sums
+  b += (size_t)8 * 4 * 64 * 16;  // the parts' sums
   return b + 16;
 }
 
