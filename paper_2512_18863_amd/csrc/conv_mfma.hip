@@ -1188,6 +1188,9 @@ static bool f32_adj_win_shape(const Geo<float>& g, AdjWin* out) {
   AdjWin aw;
   aw.WI = (bu + MT - 1) / MT;
   aw.WJ = (bv + MT - 1) / MT;
+  // (pieces of 2 x 2 tiles for 3 x 3 rectangles were measured slower: the overlap
+  // of their windows and the per-piece barriers cost more than the one wavefront
+  // with two tiles)
   aw.WI = aw.WI < 1 ? 1 : (aw.WI > 4 ? 4 : aw.WI);
   aw.WJ = aw.WJ < 1 ? 1 : (aw.WJ > 4 ? 4 : aw.WJ);
   aw.SS = (MT + 2 * g.h + 15) / 16;
@@ -1206,18 +1209,24 @@ static bool f32_adj_win_shape(const Geo<float>& g, AdjWin* out) {
 
 static hipError_t launch_f32_adj_win(const Geo<float>& g, const AdjWin& aw, int nb, const int4* box,
                                      const float* z, const float* in, float* out, hipStream_t s) {
-  const int tiles = aw.WI * aw.WJ;
-  // super-step counts of 41 to 65 taps (h 17 to 32) unrolled, others looped
-  if (aw.SS == 5) {
-    if (tiles <= kAdjWinNW) return launch_f32_adj_win_cfg<1, 5>(g, aw, nb, box, z, in, out, s);
-    return launch_f32_adj_win_cfg<2, 5>(g, aw, nb, box, z, in, out, s);
+  // one or two tiles per wavefront; super-step counts 2 to 5 (h 1 to 32) unrolled,
+  // others looped
+  if (aw.WI * aw.WJ <= kAdjWinNW) {
+    switch (aw.SS) {
+      case 2: return launch_f32_adj_win_cfg<1, 2>(g, aw, nb, box, z, in, out, s);
+      case 3: return launch_f32_adj_win_cfg<1, 3>(g, aw, nb, box, z, in, out, s);
+      case 4: return launch_f32_adj_win_cfg<1, 4>(g, aw, nb, box, z, in, out, s);
+      case 5: return launch_f32_adj_win_cfg<1, 5>(g, aw, nb, box, z, in, out, s);
+      default: return launch_f32_adj_win_cfg<1, 0>(g, aw, nb, box, z, in, out, s);
+    }
   }
-  if (aw.SS == 4) {
-    if (tiles <= kAdjWinNW) return launch_f32_adj_win_cfg<1, 4>(g, aw, nb, box, z, in, out, s);
-    return launch_f32_adj_win_cfg<2, 4>(g, aw, nb, box, z, in, out, s);
+  switch (aw.SS) {
+    case 2: return launch_f32_adj_win_cfg<2, 2>(g, aw, nb, box, z, in, out, s);
+    case 3: return launch_f32_adj_win_cfg<2, 3>(g, aw, nb, box, z, in, out, s);
+    case 4: return launch_f32_adj_win_cfg<2, 4>(g, aw, nb, box, z, in, out, s);
+    case 5: return launch_f32_adj_win_cfg<2, 5>(g, aw, nb, box, z, in, out, s);
+    default: return launch_f32_adj_win_cfg<2, 0>(g, aw, nb, box, z, in, out, s);
   }
-  if (tiles <= kAdjWinNW) return launch_f32_adj_win_cfg<1, 0>(g, aw, nb, box, z, in, out, s);
-  return launch_f32_adj_win_cfg<2, 0>(g, aw, nb, box, z, in, out, s);
 }
 
 hipError_t launch_conv_mfma_f32(const Geo<float>& g, int nb, const float* z, const float* in, float* out,
