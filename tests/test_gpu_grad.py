@@ -283,3 +283,28 @@ def test_backward_is_deterministic():
     b = [t.cpu().numpy() for t in eng.backward(_t(c.leaves), _t(c.jaws), _t(c.mu), w)]
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("n_taps", [41, 71])
+@pytest.mark.parametrize("conv", ["fp32", "bf16"])
+def test_wide_kernel_paths_against_oracle(n_taps, conv):
+    """Kernel widths whose convolutions take the remaining code paths: n = 41 (the
+    windowed FP32 adjoint's unrolled loop of four super-steps), n = 71 (h = 35: the
+    tiled FP32 forward, the windowed FP32 adjoint's generic step loop, the BF16
+    windowed adjoint with four K-steps).  Dose and gradients against the oracle:
+    FP32 at 1e-5 / 1e-4 of the maxima, BF16 at 2^-8 of the maxima (its rounding)."""
+    from tests.test_gpu_parity import gpu_dose, oracle_dose, _rel_err
+    _say("kernel width n=%d, %s" % (n_taps, conv))
+    c = inputs.tiny_case(seed=40 + n_taps, n_cp=2, n_taps=n_taps, shape=(8, 8, 8), spacing=5.0, field=40.0)
+    ref, _, _ = oracle_dose(c)
+    got, _ = gpu_dose(c, conv=conv)
+    err = _rel_err(got, ref)
+    _say("forward max|dD|/maxD = %.3e" % err)
+    assert err <= (1e-5 if conv == "fp32" else 2.0 ** -8)
+    w = np.random.default_rng(n_taps).uniform(size=c.shape)
+    gl, gj, gm, _ = _grads_gpu(c, w, conv=conv)
+    rl, rj, rm = _grads_oracle(c, w)
+    for name, g, r in (("leaves", gl, rl), ("jaws", gj, rj), ("mu", gm, rm)):
+        e = np.abs(g - r).max() / np.abs(r).max()
+        _say("%s: max|dg|/max|g| = %.3e" % (name, e))
+        assert e <= (TOL_GRAD if conv == "fp32" else 2.0 ** -8), name
