@@ -1,7 +1,8 @@
 // conv_common.hpp — staging helpers shared by the per-plane lateral convolutions
 // (arXiv:2512.18863 §2.2.6, Eq. 8): the unique taps of a plane, the rectangle of a
 // plane that one workgroup's LDS image holds, register prefetch of the next
-// plane, and the grid of a persistent launch.
+// plane, the windowed adjoints' staging in four-column groups, and the grid of a
+// persistent launch.
 #pragma once
 
 #include "taps.hpp"
