@@ -285,10 +285,16 @@ __global__ void __launch_bounds__(64 * kRegNW) k_conv_fwd_reg(Geo<float> g, cons
   const bool single = nrc == 1 && ncc == 1;
   const int wr0 = single ? r0 - 16 * kRegQB : 0, wr1 = single ? r0 + 16 * (T + kRegQB) : 0;
   {
-    RectWalk w(tid, NT, Nv);
-    for (; w.r < Nu; w.next(Nv)) {
-      const int j = w.c - cw0;
-      if (!(j >= 0 && j < 16 * njt && w.r >= wr0 && w.r < wr1)) dst[(size_t)w.r * Nv + w.c] = 0.f;
+    // whole rows above and below the window (two contiguous ranges), then the
+    // columns left and right of it in the rows between
+    const int zr0 = min(max(wr0, 0), Nu), zr1 = min(max(wr1, zr0), Nu);
+    const int cz1 = min(Nv, cw0 + 16 * njt);
+    const int top = zr0 * Nv, nfull = top + (Nu - zr1) * Nv;
+    for (int d = tid; d < nfull; d += NT) dst[d < top ? d : zr1 * Nv + (d - top)] = 0.f;
+    const int side = cw0 + (Nv - cz1), nside = (zr1 - zr0) * side;
+    for (int d = tid; d < nside; d += NT) {
+      const int rr = d / side, cc = d - rr * side;
+      dst[(size_t)(zr0 + rr) * Nv + (cc < cw0 ? cc : cz1 + (cc - cw0))] = 0.f;
     }
   }
   __syncthreads();
