@@ -28,13 +28,13 @@ __device__ __forceinline__ void unique_taps(const Geo<float>& g, int k, float zk
   }
 }
 
-// The same taps written straight into the extended, folded tap rows of the FP32
-// matrix kernels: kx[p][off + q] = kx[p][off - q] = K[p][q] for 0 <= p, q <= h,
-// row p = 0 halved (the fold counts it twice).  Pair (p, q), p <= q, fills the
-// four places of K[p][q] and of K[q][p]; every entry within h of `off` is written,
-// the rest of each row (zero) is not touched.
+// The same taps written straight into extended tap rows: kx[p][off + q] =
+// kx[p][off - q] = K[p][q] for 0 <= p, q <= h, row p = 0 scaled by s0 (0.5 for the
+// folded rows of the FP32 adjoint, which count that row twice; 1 otherwise).  Pair
+// (p, q), p <= q, fills the four places of K[p][q] and of K[q][p]; every entry
+// within h of `off` is written, the rest of each row (zero) is not touched.
 __device__ __forceinline__ void taps_to_kx(const Geo<float>& g, int k, float zk, float* kx, int E, int off, int tid,
-                                           int nt) {
+                                           int nt, float s0 = 0.5f) {
   TapParams<float> tp = tap_params(g, k, zk);
   const int h1 = g.h + 1;
   for (int t = tid; t < h1 * (h1 + 1) / 2; t += nt) {
@@ -43,8 +43,8 @@ __device__ __forceinline__ void taps_to_kx(const Geo<float>& g, int k, float zk,
     if (q * (q + 1) / 2 > t) --q;
     const int p = t - q * (q + 1) / 2;
     const float v = tap_value(tp, p, q);
-    const float vp = p == 0 ? 0.5f * v : v;  // row p
-    const float vq = q == 0 ? 0.5f * v : v;  // row q
+    const float vp = p == 0 ? s0 * v : v;  // row p
+    const float vq = q == 0 ? s0 * v : v;  // row q
     kx[p * E + off + q] = vp;
     kx[p * E + off - q] = vp;
     kx[q * E + off + p] = vq;

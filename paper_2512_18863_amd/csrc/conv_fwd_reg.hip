@@ -260,13 +260,13 @@ __global__ void __launch_bounds__(64 * kRegNW) k_conv_fwd_reg(Geo<float> g, cons
   const int jt0 = wave;  // this wavefront's first strip
   if (jt0 < njt) load_b(0, 0);  // in flight while the taps are built
 
-  unique_taps(g, k, zca[bk], kq, tid, NT);
-  __syncthreads();
-  auto tap = [&](int p, int x) {
-    const int q = x < off ? off - x : x - off;
-    return q <= h ? kq[p * (h + 1) + q] : 0.f;
-  };
   if constexpr (BF) {
+    unique_taps(g, k, zca[bk], kq, tid, NT);
+    __syncthreads();
+    auto tap = [&](int p, int x) {
+      const int q = x < off ? off - x : x - off;
+      return q <= h ? kq[p * (h + 1) + q] : 0.f;
+    };
     // word i of copy 0 holds taps (2i, 2i + 1), of copy 1 taps (2i + 1, 2i + 2)
     unsigned* t0 = reinterpret_cast<unsigned*>(lds);
     unsigned* t1 = t0 + (size_t)(h + 1) * (E / 2);
@@ -276,8 +276,13 @@ __global__ void __launch_bounds__(64 * kRegNW) k_conv_fwd_reg(Geo<float> g, cons
         t1[p * (E / 2) + i] = reg_bf16_pair(tap(p, 2 * i + 1), tap(p, 2 * i + 2));
       }
   } else {
+    // the taps straight into the rows, and the rows' entries farther than h from
+    // `off` (the ranges [0, off - h) and (off + h, E)) cleared: disjoint entries,
+    // so no barrier between the two
+    taps_to_kx(g, k, zca[bk], lds, E, off, tid, NT, 1.f);
+    const int zl = off - h, zr = E - (off + h + 1);
     for (int p = wave; p <= h; p += kRegNW)
-      for (int x = lane; x < E; x += 64) lds[p * E + x] = tap(p, x);
+      for (int i = lane; i < zl + zr; i += 64) lds[p * E + (i < zl ? i : off + h + 1 + (i - zl))] = 0.f;
   }
   // With one chunk the strips are stored once and the plane outside them [wr0, wr1)
   // x [cw0, cw0 + 16 njt) is zero; with several the whole plane is cleared first
