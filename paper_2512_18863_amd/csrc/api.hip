@@ -195,6 +195,9 @@ int size_problem(const pdrt_grid* grid, const pdrt_beam* beam, const pdrt_kernel
   off += align256((size_t)B * P->Nk * elem);
   L.vol0 = off;
   off += align256((size_t)B * P->Nk * plane * elem);
+  // (vol1 directly follows vol0: the register-resident forward convolution, whose
+  // input is vol0, may read a few words past a row's end, i.e. past vol0's end
+  // after the last row, which stays inside the workspace)
   L.vol1 = off;
   off += align256((size_t)B * P->Nk * plane * elem);
   L.adj = off;

@@ -102,7 +102,7 @@ __device__ __forceinline__ void reg_add_shifted(const f32x4r (&Y)[T], f32x4r (&O
 }
 
 // Operands of one precision.  FP32: A of group u and step s is one tap (aaddr[u] +
-// P E + 4 s), B[t][4 u + s] one input value.  BF16: A of group u is eight taps read
+// P E + s), B[t][4 u + s] one input value.  BF16: A of group u is eight taps read
 // as four words from the copy of the row whose pairs start at the lane's parity
 // (aaddr[u] + P E / 2 words), B[t][u] eight inputs as four words.
 template <bool BF, int T, int SU>
@@ -119,7 +119,7 @@ struct RegOps<false, T, SU> {
 #pragma unroll
     for (int u = 0; u < SU; ++u)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) A[4 * u + s] = aaddr[u][P * E + 4 * s];
+      for (int s = 0; s < 4; ++s) A[4 * u + s] = aaddr[u][P * E + s];
     // group 0 always runs and starts the chains from zero (out of reach its A is
     // zero); the others run when their bit of umask is set and accumulate in place
 #pragma unroll
@@ -230,29 +230,41 @@ __global__ void __launch_bounds__(64 * kRegNW) k_conv_fwd_reg(Geo<float> g, cons
   const int nrc = (r1 - r0 + 16 * T - 1) / (16 * T), ncc = (c1 - c0 + GW * SU - 1) / (GW * SU);
 
   // B fragments of box chunk (rc, cc).  FP32: lane (n, kk) holds in[R + 16 t + n][C +
-  // 4 ks + kk]; BF16: in[R + 16 t + n][C + 32 u + 8 kk .. + 7] as bf16 pairs.
+  // 16 u + 4 kk + s] for step s of group u (the K index of a matrix step may stand for
+  // any column as long as A and B agree: here a lane's four columns of a group are
+  // consecutive); BF16: in[R + 16 t + n][C + 32 u + 8 kk .. + 7] as bf16 pairs.  Each
+  // run of four columns is one four-word load from a row inside the box (rows past it
+  // and runs past its last column read the box's first row or column and are
+  // cleared); a run that starts inside the box may read up to three words past its
+  // last column, i.e. past the end of the row into the next one (or, after the
+  // batch's last row, into the workspace that follows the convolution's input).
   typename Ops::BOp B;
   auto load_b = [&](int rc, int cc) {
     const int R = r0 + 16 * T * rc, C = c0 + GW * SU * cc;
+    auto run4 = [&](int r, int c) {
+      const f32x4u x = *reinterpret_cast<const f32x4u*>(src + (size_t)(r < r1 ? r : r0) * Nv + (c < c1 ? c : c0));
+      f32x4r v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = (r < r1 && c + e < c1) ? x[e] : 0.f;
+      return v;
+    };
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       const int r = R + 16 * t + n;
-      const float* row = src + (size_t)r * Nv;
       if constexpr (BF) {
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
           const int c = C + 32 * u + 8 * kk;
-          float v[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = (r < r1 && c + e < c1) ? row[c + e] : 0.f;
-          B[t][u] = u32x4r{reg_bf16_pair(v[0], v[1]), reg_bf16_pair(v[2], v[3]), reg_bf16_pair(v[4], v[5]),
-                           reg_bf16_pair(v[6], v[7])};
+          const f32x4r a = run4(r, c), b = run4(r, c + 4);
+          B[t][u] = u32x4r{reg_bf16_pair(a[0], a[1]), reg_bf16_pair(a[2], a[3]), reg_bf16_pair(b[0], b[1]),
+                           reg_bf16_pair(b[2], b[3])};
         }
       } else {
 #pragma unroll
-        for (int ks = 0; ks < 4 * SU; ++ks) {
-          const int c = C + 4 * ks + kk;
-          B[t][ks] = (r < r1 && c < c1) ? row[c] : 0.f;
+        for (int u = 0; u < SU; ++u) {
+          const f32x4r v = run4(r, C + 16 * u + 4 * kk);
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2) B[t][4 * u + s2] = v[s2];
         }
       }
     }
@@ -321,11 +333,11 @@ __global__ void __launch_bounds__(64 * kRegNW) k_conv_fwd_reg(Geo<float> g, cons
         const int ub = min(nsu - 1, hi >= 0 ? hi / GW : -1);
         if (ua > ub) continue;
         // A of group u in tap row p starts at x = C + GW u + KL kk - J - m + off (m the
-        // lane's output column, KL its first box column's step: 1 for FP32, whose
-        // steps s add 4 s, 8 for BF16); groups outside [ua, ub] start at x = 15 +
+        // lane's output column, KL its first box column's step: 4 for FP32, whose
+        // steps s add s, 8 for BF16); groups outside [ua, ub] start at x = 15 +
         // KL kk - m, where the row is zero (group 0 runs with it, the others are
         // skipped)
-        constexpr int KL = BF ? 8 : 1;
+        constexpr int KL = BF ? 8 : 4;
         typename Ops::Addr aaddr[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u) {

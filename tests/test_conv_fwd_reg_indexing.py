@@ -84,14 +84,14 @@ def model(inp, box, h, kq, T, SU, bf):
             O = np.zeros((NB, 64, 4))
             for cc in range(ncc):
                 C = c0 + GW * SU * cc
-                # B of group u, product s: lane (n, kk) column C + GW u + 4 s + kk (FP32)
+                # B of group u, product s: lane (n, kk) column C + GW u + 4 kk + s (FP32)
                 # or C + 32 u + 8 kk + e (BF16)
                 B = np.zeros((T, SU, MPG, 64, KP))
                 for t in range(T):
                     for u in range(SU):
                         for sm in range(MPG):
                             r = R + 16 * t + n
-                            cols = (C + GW * u + 4 * sm + kk)[:, None] if not bf else \
+                            cols = (C + GW * u + 4 * kk + sm)[:, None] if not bf else \
                                 (C + GW * u + 8 * kk)[:, None] + ev[None, :]
                             ok = (r[:, None] < r1) & (cols < c1)
                             rr = np.broadcast_to(r[:, None], cols.shape)
@@ -106,10 +106,10 @@ def model(inp, box, h, kq, T, SU, bf):
                     S, Q = p & 15, p >> 4
                     A = np.zeros((SU, MPG, 64, KP))
                     for u in range(SU):
-                        KL = 8 if bf else 1
+                        KL = 8 if bf else 4
                         base = C + GW * u + KL * kk - J - n + off if ua <= u <= ub else 15 + KL * kk - n
                         for sm in range(MPG):
-                            x = (base + 4 * sm)[:, None] + ev[None, :]
+                            x = (base + sm)[:, None] + ev[None, :]
                             assert x.min() >= 0 and x.max() < (E + 1 if bf else E), (x.min(), x.max(), E)
                             if bf:   # words (x >> 1) .. (x >> 1) + 3 of a copy of E / 2 words
                                 assert ((base >> 1) + 3).max() < E // 2
