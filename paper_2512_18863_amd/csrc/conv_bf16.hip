@@ -33,6 +33,8 @@
 // items are independent, so several workgroups share a compute unit and hide
 // each other's set-up; the first global loads of the input are issued before the
 // taps are evaluated.
+#include <type_traits>
+
 #include "conv_common.hpp"
 
 namespace pdrt {
@@ -345,9 +347,11 @@ __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16Adj
   unsigned* T0 = reinterpret_cast<unsigned*>(smem_raw);  // [h + 1][L2]: elements (2i, 2i + 1)
   unsigned* T1 = T0 + (h + 1) * L2;                      // elements (2i + 1, 2i + 2)
   float* kq = reinterpret_cast<float*>(T1 + (h + 1) * L2);
-  const size_t img_off = ((reinterpret_cast<uintptr_t>(kq + (h + 1) * (h + 1)) + 15) & ~(uintptr_t)15);
-  __bf16* img = reinterpret_cast<__bf16*>(img_off);
-  f32x4c* red = reinterpret_cast<f32x4c*>(img_off + (((size_t)bw.rows * pitch * 2 + 15) & ~(size_t)15));
+  // byte offsets from the (16-byte aligned) base, so that every access stays an
+  // LDS access (an integer round trip of the address would make them generic)
+  const int img_off = (4 * (2 * (h + 1) * L2 + (h + 1) * (h + 1)) + 15) & ~15;
+  __bf16* img = reinterpret_cast<__bf16*>(smem_raw + img_off);
+  f32x4c* red = reinterpret_cast<f32x4c*>(smem_raw + img_off + ((bw.rows * pitch * 2 + 15) & ~15));
   const size_t plane = (size_t)g.Nu * g.Nv;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -487,23 +491,30 @@ __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16Adj
       c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8c, A), __builtin_bit_cast(bf16x8c, B), c,
                                                   0, 0, 0);
     };
-    auto compute = [&](const Ops& o) {
+    // full: a piece of 2 x 2 tiles, no tests inside the loop
+    auto rows_loop = [&](auto full) {
+      auto compute = [&](const Ops& o) {
 #pragma unroll
-      for (int s2 = 0; s2 < NK; ++s2) {
-        mfma(o.A[0][s2], o.B[0][s2], acc[0][0]);
-        if (t1) mfma(o.A[0][s2], o.B[1][s2], acc[0][1]);
-        if (r1) {
-          mfma(o.A[1][s2], o.B[0][s2], acc[1][0]);
-          if (t1) mfma(o.A[1][s2], o.B[1][s2], acc[1][1]);
+        for (int s2 = 0; s2 < NK; ++s2) {
+          mfma(o.A[0][s2], o.B[0][s2], acc[0][0]);
+          if (full || t1) mfma(o.A[0][s2], o.B[1][s2], acc[0][1]);
+          if (full || r1) {
+            mfma(o.A[1][s2], o.B[0][s2], acc[1][0]);
+            if (full || t1) mfma(o.A[1][s2], o.B[1][s2], acc[1][1]);
+          }
         }
+      };
+#pragma unroll 1
+      for (int p = pa; p < pz; ++p) {
+        Ops o;
+        load(p, o);
+        compute(o);
       }
     };
-#pragma unroll 1
-    for (int p = pa; p < pz; ++p) {
-      Ops o;
-      load(p, o);
-      compute(o);
-    }
+    if (r1 && t1)
+      rows_loop(std::true_type{});
+    else
+      rows_loop(std::false_type{});
     // every wavefront parks its sums; wavefront t < 4 then adds tile t's eight
     // parts in wavefront order and stores the tile
     __syncthreads();

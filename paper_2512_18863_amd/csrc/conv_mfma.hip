@@ -758,8 +758,9 @@ __global__ void __launch_bounds__(64 * NW) k_conv_mfma_f32_adj(Geo<float> g, Reg
   float* tile = lds;
   float* kx = lds + rows * pitch;
   float* kq = kx + (h + 1) * E;
-  float* part = kq + (h + 1) * (h + 1);  // (NW - 1) x 256 partial sums, 16-byte aligned (see f32_adj_lds)
-  part = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(part) + 15) & ~(uintptr_t)15);
+  // (NW - 1) x 256 partial sums, 16-byte aligned (see f32_adj_lds); an offset from
+  // the base, so that the accesses stay LDS accesses
+  float* part = lds + ((rows * pitch + (h + 1) * E + (h + 1) * (h + 1) + 3) & ~3);
   const int nreg = rs.regions_i * rs.regions_j;
   const size_t plane = (size_t)g.Nu * g.Nv;
   const int tid = threadIdx.x;
@@ -922,8 +923,9 @@ __global__ void __launch_bounds__(64 * NW) k_conv_f32_adj_win(Geo<float> g, AdjW
   const int pitch = aw.pitch, E = aw.E, SS = aw.SS;
   float* tile = lds;
   float* kx = lds + aw.rows * pitch;
-  float* part = kx + (h + 1) * E;  // (NW - 1) x 256 partial sums, 16-byte aligned
-  part = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(part) + 15) & ~(uintptr_t)15);
+  // (NW - 1) x 256 partial sums, 16-byte aligned; an offset from the base, so that
+  // the accesses stay LDS accesses
+  float* part = lds + ((aw.rows * pitch + (h + 1) * E + 3) & ~3);
   const size_t plane = (size_t)g.Nu * g.Nv;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
