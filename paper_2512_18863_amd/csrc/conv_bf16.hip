@@ -327,7 +327,8 @@ k_conv_bf16(Geo<float> g, Bf16Plan q, const int4* __restrict__ box,
 // every output is that of the tiled kernel (BF16 operands, FP32 products and
 // sums).
 struct Bf16AdjWin {
-  int rows, pitch;  // image rows (32 + 2h) and pitch in BF16 elements (32 NK + 8)
+  int rows, pitch;  // image rows (32 + 2h) and pitch in BF16 elements (32 NK + 16: 16 NK + 8 words, the
+                    // 16-byte operand reads of a half-wavefront in distinct slots of a 512-byte line)
   int L2;           // words per padded tap row (each copy): 16 NK + 16
 };
 
@@ -335,6 +336,13 @@ struct Bf16AdjWin {
 // the run of lane (m, kq) for column tile t and K-step s starts at
 // x = 32 s + 8 kq - 16 t - m + 32, in [1, 32 NK + 24].
 constexpr int kBwX0 = 32;
+
+// Words from the first copy of the tap rows to the second: congruent to 16 mod 32,
+// so that a half-wavefront's run read, whose lanes take words 8 to 20 of one copy
+// and 8 to 19 of the other (plus a common offset), never asks one of the 32 banks
+// that 4-byte reads see for two different words (measured: offsets congruent to
+// 0 mod 32 cost twice the cycles per read).
+__host__ __device__ inline int bw_t1_words(int h, int L2) { return (((h + 1) * L2 + 31) & ~31) + 16; }
 
 template <int NK>
 __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16AdjWin bw, int n_items,
@@ -345,11 +353,12 @@ __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16Adj
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int h = g.h, L2 = bw.L2, pitch = bw.pitch;
   unsigned* T0 = reinterpret_cast<unsigned*>(smem_raw);  // [h + 1][L2]: elements (2i, 2i + 1)
-  unsigned* T1 = T0 + (h + 1) * L2;                      // elements (2i + 1, 2i + 2)
+  const int t1w = bw_t1_words(h, L2);
+  unsigned* T1 = T0 + t1w;                               // elements (2i + 1, 2i + 2)
   float* kq = reinterpret_cast<float*>(T1 + (h + 1) * L2);
   // byte offsets from the (16-byte aligned) base, so that every access stays an
   // LDS access (an integer round trip of the address would make them generic)
-  const int img_off = (4 * (2 * (h + 1) * L2 + (h + 1) * (h + 1)) + 15) & ~15;
+  const int img_off = (4 * (t1w + (h + 1) * L2 + (h + 1) * (h + 1)) + 15) & ~15;
   __bf16* img = reinterpret_cast<__bf16*>(smem_raw + img_off);
   f32x4c* red = reinterpret_cast<f32x4c*>(smem_raw + img_off + ((bw.rows * pitch * 2 + 15) & ~15));
   const size_t plane = (size_t)g.Nu * g.Nv;
@@ -547,7 +556,7 @@ __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16Adj
 }
 
 static size_t bf16_adj_win_lds(int h, const Bf16AdjWin& bw) {
-  size_t b = (size_t)2 * (h + 1) * bw.L2 * 4 + (size_t)(h + 1) * (h + 1) * 4;
+  size_t b = (size_t)4 * (bw_t1_words(h, bw.L2) + (h + 1) * bw.L2) + (size_t)(h + 1) * (h + 1) * 4;
   b = (b + 15) & ~(size_t)15;
   b += ((size_t)bw.rows * bw.pitch * 2 + 15) & ~(size_t)15;
   b += (size_t)8 * 4 * 64 * 16;  // the parts' sums
@@ -559,7 +568,7 @@ static hipError_t launch_bf16_adj_win_nk(const Geo<float>& g, int nb, const int4
                                          const float* in, float* out, hipStream_t s) {
   Bf16AdjWin bw;
   bw.rows = 32 + 2 * g.h;
-  bw.pitch = 32 * NK + 8;
+  bw.pitch = 32 * NK + 16;
   bw.L2 = 16 * NK + 16;
   const size_t lds = bf16_adj_win_lds(g.h, bw);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;

@@ -84,8 +84,12 @@ struct F32Shape {
   int rows, pitch;
 };
 
-// Row pitch (elements) congruent to 4 mod 32.
-static int pitch_f32(int cols) { return ((cols + 27) / 32) * 32 + 4; }
+// Row pitch (elements): the smallest one not below `cols` that is congruent to 8
+// mod 16.  A half-wavefront's 16-byte operand reads (16 rows, two four-column
+// groups) then fall in 32 distinct 16-byte slots of a 512-byte LDS line, which
+// gfx950 serves without bank conflicts; pitches congruent to 4 mod 16 (or 0 mod
+// 16) were measured at twice the cycles per read.
+static int pitch_f32(int cols) { return ((cols + 7) / 16) * 16 + 8; }
 
 static F32Shape f32_shape(int h, const RegionShape& r) {
   F32Shape s;

@@ -13,7 +13,7 @@ MT = 16
 
 
 def pitch_f32(cols):
-    return ((cols + 27) // 32) * 32 + 4
+    return ((cols + 7) // 16) * 16 + 8
 
 
 def shape(Nu, Nv, h, nw=8, lds_max=160 * 1024):

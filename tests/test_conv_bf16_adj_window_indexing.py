@@ -45,8 +45,8 @@ def model(inp, box, h, kq):
         nIp, nJp = min(2, nI - 2 * pi), min(2, nJ - 2 * pj)
         r0, c0 = u0 + 32 * pi - h, v0 + 32 * pj - h
         nr, nc = 16 * nIp + 2 * h, 32 * NK
-        rows, pitch = 32 + 2 * h, 32 * NK + 8
-        assert nr <= rows and nc <= pitch - 8
+        rows, pitch = 32 + 2 * h, 32 * NK + 16
+        assert nr <= rows and nc <= pitch - 16
         img = np.full((rows, pitch), np.nan)
         for r in range(nr):
             for c in range(nc):

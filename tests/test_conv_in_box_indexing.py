@@ -38,7 +38,7 @@ def region_shape(N):
 
 
 def pitch_f32(cols):
-    return ((cols + 27) // 32) * 32 + 4
+    return ((cols + 7) // 16) * 16 + 8
 
 
 def row_reach(X, lo, hi, h):
@@ -276,7 +276,7 @@ def test_image_capacity_fits_two_workgroups_at_the_benchmark_size():
     TI, _ = region_shape(N)
     SS = (16 + 2 * h + 15) // 16
     rows, cols = image_capacity(N, N, h, TI, TI, SS)
-    assert (rows, pitch_f32(cols)) == (119, 132)
+    assert (rows, pitch_f32(cols)) == (119, 136)
     E = 16 * SS + 16
     lds = 4 * (rows * pitch_f32(cols) + (h + 1) * E + (h + 1) ** 2) + 16 + 4 * 9 * RMAX * RMAX
     assert 2 * lds <= 160 * 1024
