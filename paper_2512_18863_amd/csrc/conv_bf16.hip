@@ -329,7 +329,8 @@ k_conv_bf16(Geo<float> g, Bf16Plan q, const int4* __restrict__ box,
 struct Bf16AdjWin {
   int rows, pitch;  // image rows (32 + 2h) and pitch in BF16 elements (32 NK + 16: 16 NK + 8 words, the
                     // 16-byte operand reads of a half-wavefront in distinct slots of a 512-byte line)
-  int L2;           // words per padded tap row (each copy): 16 NK + 16
+  int L2;           // words per padded tap row (each copy): 16 NK + 17 (odd, so that the
+                    // taps' writes down a column of rows fall in distinct banks)
 };
 
 // Element x of a padded tap row holds K[p][|x - X0|] (zero beyond h), X0 = h + 32:
@@ -344,6 +345,35 @@ constexpr int kBwX0 = 32;
 // 0 mod 32 cost twice the cycles per read).
 __host__ __device__ inline int bw_t1_words(int h, int L2) { return (((h + 1) * L2 + 31) & ~31) + 16; }
 
+// The taps of plane k written straight into both padded copies: tap K[p][q] sits
+// at elements X0 + h +- q of row p and X0 + h +- p of row q; copy 0 holds element
+// x at half-word x of its row, copy 1 at half-word x - 1.  Every other element of
+// the rows is zero and is never written here (the rows are cleared once).
+__device__ __forceinline__ void taps_to_bf16_rows(const Geo<float>& g, int k, float zk, unsigned* T0, unsigned* T1,
+                                                  int L2, int tid, int nt) {
+  TapParams<float> tp = tap_params(g, k, zk);
+  const int h1 = g.h + 1, x0 = g.h + kBwX0;
+  unsigned short* H0 = reinterpret_cast<unsigned short*>(T0);
+  unsigned short* H1 = reinterpret_cast<unsigned short*>(T1);
+  for (int t = tid; t < h1 * (h1 + 1) / 2; t += nt) {
+    int q = (int)((sqrtf((float)(8 * t + 1)) - 1.f) * 0.5f);
+    if ((q + 1) * (q + 2) / 2 <= t) ++q;
+    if (q * (q + 1) / 2 > t) --q;
+    const int p = t - q * (q + 1) / 2;
+    const __bf16 b = (__bf16)tap_value(tp, p, q);
+    const unsigned short v = *reinterpret_cast<const unsigned short*>(&b);
+    const int rp = 2 * L2 * p + x0, rq = 2 * L2 * q + x0;
+    H0[rp + q] = v;
+    H0[rp - q] = v;
+    H0[rq + p] = v;
+    H0[rq - p] = v;
+    H1[rp + q - 1] = v;
+    H1[rp - q - 1] = v;
+    H1[rq + p - 1] = v;
+    H1[rq - p - 1] = v;
+  }
+}
+
 template <int NK>
 __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16AdjWin bw, int n_items,
                                                            const int4* __restrict__ box,
@@ -355,10 +385,9 @@ __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16Adj
   unsigned* T0 = reinterpret_cast<unsigned*>(smem_raw);  // [h + 1][L2]: elements (2i, 2i + 1)
   const int t1w = bw_t1_words(h, L2);
   unsigned* T1 = T0 + t1w;                               // elements (2i + 1, 2i + 2)
-  float* kq = reinterpret_cast<float*>(T1 + (h + 1) * L2);
   // byte offsets from the (16-byte aligned) base, so that every access stays an
   // LDS access (an integer round trip of the address would make them generic)
-  const int img_off = (4 * (t1w + (h + 1) * L2 + (h + 1) * (h + 1)) + 15) & ~15;
+  const int img_off = (4 * (t1w + (h + 1) * L2) + 15) & ~15;
   __bf16* img = reinterpret_cast<__bf16*>(smem_raw + img_off);
   f32x4c* red = reinterpret_cast<f32x4c*>(smem_raw + img_off + ((bw.rows * pitch * 2 + 15) & ~15));
   const size_t plane = (size_t)g.Nu * g.Nv;
@@ -425,29 +454,15 @@ __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16Adj
     fetch_win<PG>(in + (size_t)it * plane, g, win_of(c, 0, &a, &b), it == 0 || it == n_items - 1, tid, NT, buf);
     zk = depth_of(it);
   }
+  zero_lds(T0, t1w + (h + 1) * L2, tid, NT);  // both copies (and the gap between them)
+  __syncthreads();
   while (it < n_items) {
     const float* src = in + (size_t)it * plane;
     float* dst = out + (size_t)it * plane;
     int nIp, nJp;
     const WinRect w = win_of(c, pp, &nIp, &nJp);
     put_bf16(src, w, it == 0 || it == n_items - 1, buf);
-    if (pp == 0) {
-      unique_taps(g, it % g.Nk, zk, kq, tid, NT);
-      __syncthreads();
-      // the padded rows, a wavefront per row, lanes along the words
-      for (int p = wave; p <= h; p += NW)
-        for (int i = lane; i < L2; i += 64) {
-          float v[3];
-#pragma unroll
-          for (int e = 0; e < 3; ++e) {
-            const int d = 2 * i + e - (h + kBwX0);
-            const int ad = d < 0 ? -d : d;
-            v[e] = ad <= h ? kq[p * (h + 1) + ad] : 0.f;
-          }
-          T0[p * L2 + i] = bf16_pair(v[0], v[1]);
-          T1[p * L2 + i] = bf16_pair(v[1], v[2]);
-        }
-    }
+    if (pp == 0) taps_to_bf16_rows(g, it % g.Nk, zk, T0, T1, L2, tid, NT);
     int nit = it, npp = pp + 1;
     Cov cn = c;
     if (npp == c.npi * c.npj) {
@@ -556,7 +571,7 @@ __global__ void __launch_bounds__(512) k_conv_bf16_adj_win(Geo<float> g, Bf16Adj
 }
 
 static size_t bf16_adj_win_lds(int h, const Bf16AdjWin& bw) {
-  size_t b = (size_t)4 * (bw_t1_words(h, bw.L2) + (h + 1) * bw.L2) + (size_t)(h + 1) * (h + 1) * 4;
+  size_t b = (size_t)4 * (bw_t1_words(h, bw.L2) + (h + 1) * bw.L2);
   b = (b + 15) & ~(size_t)15;
   b += ((size_t)bw.rows * bw.pitch * 2 + 15) & ~(size_t)15;
   b += (size_t)8 * 4 * 64 * 16;  // the parts' sums
@@ -569,7 +584,7 @@ static hipError_t launch_bf16_adj_win_nk(const Geo<float>& g, int nb, const int4
   Bf16AdjWin bw;
   bw.rows = 32 + 2 * g.h;
   bw.pitch = 32 * NK + 16;
-  bw.L2 = 16 * NK + 16;
+  bw.L2 = 16 * NK + 17;
   const size_t lds = bf16_adj_win_lds(g.h, bw);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
   const void* kern = (const void*)k_conv_bf16_adj_win<NK>;
