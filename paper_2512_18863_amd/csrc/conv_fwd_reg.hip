@@ -197,7 +197,7 @@ __host__ __device__ inline size_t reg_tap_words(int h, bool bf) {
 
 // One workgroup per (control point, plane) item.  T: row blocks of 16 box rows per
 // chunk; SU: column groups per chunk (boxes larger than a chunk are taken chunk by
-// chunk).  LDS: the tap rows, then the (h + 1)^2 unique taps.
+// chunk).  LDS: the tap rows.
 template <bool BF, int T, int SU>
 __global__ void __launch_bounds__(64 * kRegNW) k_conv_fwd_reg(Geo<float> g, const int4* __restrict__ box,
                                                               const float* __restrict__ zca,
@@ -209,7 +209,6 @@ __global__ void __launch_bounds__(64 * kRegNW) k_conv_fwd_reg(Geo<float> g, cons
   constexpr int GW = RegPrec<BF>::GW;
   constexpr int NB = T + 2 * kRegQB;
   const int h = g.h, E = reg_tap_len(h, BF), off = reg_tap_off(h, BF);
-  float* kq = lds + reg_tap_words(h, BF);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int bk = blockIdx.x;
@@ -273,20 +272,55 @@ __global__ void __launch_bounds__(64 * kRegNW) k_conv_fwd_reg(Geo<float> g, cons
   if (jt0 < njt) load_b(0, 0);  // in flight while the taps are built
 
   if constexpr (BF) {
-    unique_taps(g, k, zca[bk], kq, tid, NT);
-    __syncthreads();
-    auto tap = [&](int p, int x) {
-      const int q = x < off ? off - x : x - off;
-      return q <= h ? kq[p * (h + 1) + q] : 0.f;
-    };
-    // word i of copy 0 holds taps (2i, 2i + 1), of copy 1 taps (2i + 1, 2i + 2)
+    // word i of copy c holds taps (2i + c, 2i + c + 1): element x of row p is half-word
+    // x - c of the copy's row.  The taps go straight into both copies; the elements
+    // farther than h from `off` are zero: the words made only of them are cleared
+    // whole, and the two elements just outside the taps (off - h - 1, off + h + 1)
+    // one by one.  Those entries are disjoint from the taps, so no barrier between.
+    const int W2 = E / 2;
     unsigned* t0 = reinterpret_cast<unsigned*>(lds);
-    unsigned* t1 = t0 + (size_t)(h + 1) * (E / 2);
-    for (int p = wave; p <= h; p += kRegNW)
-      for (int i = lane; i < E / 2; i += 64) {
-        t0[p * (E / 2) + i] = reg_bf16_pair(tap(p, 2 * i), tap(p, 2 * i + 1));
-        t1[p * (E / 2) + i] = reg_bf16_pair(tap(p, 2 * i + 1), tap(p, 2 * i + 2));
+    unsigned* t1 = t0 + (size_t)(h + 1) * W2;
+    unsigned short* H0 = reinterpret_cast<unsigned short*>(t0);
+    unsigned short* H1 = reinterpret_cast<unsigned short*>(t1);
+    {
+      const TapParams<float> tp = tap_params(g, k, zca[bk]);
+      const int h1 = h + 1;
+      for (int t = tid; t < h1 * (h1 + 1) / 2; t += NT) {
+        int q = (int)((sqrtf((float)(8 * t + 1)) - 1.f) * 0.5f);
+        if ((q + 1) * (q + 2) / 2 <= t) ++q;
+        if (q * (q + 1) / 2 > t) --q;
+        const int p = t - q * (q + 1) / 2;
+        const __bf16 bv = (__bf16)tap_value(tp, p, q);
+        const unsigned short v = *reinterpret_cast<const unsigned short*>(&bv);
+        const int rp = 2 * W2 * p + off, rq = 2 * W2 * q + off;
+        H0[rp + q] = v;
+        H0[rp - q] = v;
+        H0[rq + p] = v;
+        H0[rq - p] = v;
+        H1[rp + q - 1] = v;
+        H1[rp - q - 1] = v;
+        H1[rq + p - 1] = v;
+        H1[rq - p - 1] = v;
       }
+    }
+    const int xa = off - h, xb = off + h;             // the taps' elements
+    const int nl0 = xa / 2, nl1 = (xa - 1) / 2;        // whole zero words left of them
+    const int ir0 = xb / 2 + 1, ir1 = (xb - 1) / 2 + 1; // first whole zero word right of them
+    const int n0 = nl0 + (W2 - ir0), n1 = nl1 + (W2 - ir1);
+    for (int p = wave; p <= h; p += kRegNW) {
+      for (int i = lane; i < n0 + n1; i += 64) {
+        if (i < n0) {
+          t0[p * W2 + (i < nl0 ? i : ir0 + (i - nl0))] = 0u;
+        } else {
+          const int j = i - n0;
+          t1[p * W2 + (j < nl1 ? j : ir1 + (j - nl1))] = 0u;
+        }
+      }
+      if (lane < 4) {
+        const int c = lane & 1, x = lane < 2 ? xa - 1 : xb + 1;
+        if (x - c >= 0 && x - c < 2 * W2) (c ? H1 : H0)[2 * W2 * p + x - c] = 0;
+      }
+    }
   } else {
     // the taps straight into the rows, and the rows' entries farther than h from
     // `off` (the ranges [0, off - h) and (off + h, E)) cleared: disjoint entries,
@@ -378,8 +412,8 @@ __global__ void __launch_bounds__(64 * kRegNW) k_conv_fwd_reg(Geo<float> g, cons
   }
 }
 
-// LDS of the kernel: tap rows and the unique taps.
-static size_t reg_lds(int h, bool bf) { return sizeof(float) * (reg_tap_words(h, bf) + (size_t)(h + 1) * (h + 1)); }
+// LDS of the kernel: the tap rows.
+static size_t reg_lds(int h, bool bf) { return sizeof(float) * reg_tap_words(h, bf); }
 
 bool conv_fwd_reg_supported(const Geo<float>& g, bool bf16) {
   return g.h >= 1 && g.h <= kRegMaxH && reg_lds(g.h, bf16) <= 160 * 1024;

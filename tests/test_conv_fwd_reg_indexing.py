@@ -176,3 +176,49 @@ def test_register_forward_matches_direct_convolution(Nu, Nv, h, box, T, SU, bf):
     got = model(inp, box, h, kq, T, SU if not bf else (SU + 1) // 2, bf)
     ref = direct(inp, box, h, kq)
     assert np.abs(got - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("h", [1, 2, 5, 16, 30, 31])
+def test_bf16_tap_rows_written_once_inside_the_rows(h):
+    """The BF16 forward's tap rows (two copies; copy c holds element x of row p at
+    half-word x - c): each tap K[p][q] (pair p <= q) is written at elements off +- q
+    of row p and off +- p of row q, whole words made only of elements farther than
+    h from off are cleared, and the two elements beside the taps one by one.  Every
+    half-word of every row must end up written, with the tap or zero, and no write
+    may leave its row."""
+    E, off = 2 * h + 96, h + 47
+    W2 = E // 2
+    rows = [[[None] * (2 * W2) for _ in range(h + 1)] for _ in range(2)]
+    kq = {(p, q): 1.0 + p * 100 + q for p in range(h + 1) for q in range(h + 1)}
+
+    def put(c, p, hw, v):
+        assert 0 <= hw < 2 * W2
+        old = rows[c][p][hw]
+        assert old is None or old == v          # only equal values may meet
+        rows[c][p][hw] = v
+
+    for q in range(h + 1):
+        for p in range(q + 1):
+            v = kq[(p, q)]
+            for c in range(2):
+                put(c, p, off + q - c, v)
+                put(c, p, off - q - c, v)
+                put(c, q, off + p - c, v)
+                put(c, q, off - p - c, v)
+    xa, xb = off - h, off + h
+    nl = [xa // 2, (xa - 1) // 2]
+    ir = [xb // 2 + 1, (xb - 1) // 2 + 1]
+    for p in range(h + 1):
+        for c in range(2):
+            for i in list(range(nl[c])) + list(range(ir[c], W2)):
+                put(c, p, 2 * i, 0.0)
+                put(c, p, 2 * i + 1, 0.0)
+            for x in (xa - 1, xb + 1):
+                if 0 <= x - c < 2 * W2:
+                    put(c, p, x - c, 0.0)
+    for c in range(2):
+        for p in range(h + 1):
+            for hw in range(2 * W2):
+                x = hw + c
+                want = kq[(min(p, abs(x - off)), max(p, abs(x - off)))] if abs(x - off) <= h else 0.0
+                assert rows[c][p][hw] == want, (c, p, hw)
