@@ -126,3 +126,44 @@ def test_windowed_bf16_adjoint_matches_direct_convolution(Nu, Nv, h, box):
     else:
         assert not written.any()
     assert np.abs(got[written] - ref[written]).max(initial=0.0) <= 1e-9 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("h", [1, 7, 15, 30, 47])
+def test_tap_rows_rewritten_whole_for_every_plane(h):
+    """The windowed BF16 adjoint's tap rows (taps_to_bf16_rows): both copies are
+    cleared once per workgroup, then every plane writes tap K[p][q] (pair p <= q)
+    at elements X0 + h +- q of row p and X0 + h +- p of row q, copy c at half-word
+    x - c of a row of 2 L2 half-words (L2 = 16 NK + 17).  After any sequence of
+    planes, every element within h of X0 + h holds the current plane's tap and
+    every other element zero; each write stays inside its row; and every B run a
+    lane reads (eight elements from x in [1, 32 NK + 24]) lies inside the row."""
+    NK = (32 + 2 * h + 31) // 32
+    L2 = 16 * NK + 17
+    x0 = h + 32
+    rows = [[[0] * (2 * L2) for _ in range(h + 1)] for _ in range(2)]    # cleared once
+
+    for plane in range(3):
+        def K(p, q):
+            return 1 + plane * 10000 + p * 100 + q
+        for q in range(h + 1):
+            for p in range(q + 1):
+                for c in range(2):
+                    for r, d in ((p, q), (p, -q), (q, p), (q, -p)):
+                        hw = x0 + d - c
+                        assert 0 <= hw < 2 * L2
+                        rows[c][r][hw] = K(p, q)
+        for c in range(2):
+            for r in range(h + 1):
+                for hw in range(2 * L2):
+                    d = abs(hw + c - x0)
+                    want = K(min(r, d), max(r, d)) if d <= h else 0
+                    assert rows[c][r][hw] == want, (plane, c, r, hw)
+    # B runs: start x = 32 s + 8 kq - 16 t - m + 32 (s < NK, kq < 4, t < 2, m < 16),
+    # read from the copy of x's parity as four words from word x >> 1
+    for s in range(NK):
+        for kq in range(4):
+            for t in range(2):
+                for m in range(16):
+                    x = 32 * s + 8 * kq - 16 * t - m + 32
+                    assert 1 <= x <= 32 * NK + 24
+                    assert (x >> 1) + 3 < L2
